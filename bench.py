@@ -1,0 +1,178 @@
+"""Benchmark of the WCSPH / k-epsilon open-boundary step on one MI355X.
+
+One "step" is one advection step of the whole per-step pipeline: cell-list
+build, correction matrix, dual-criteria advection step (ARD / RANS pass and
+the acoustic pressure / density sub-steps) and the bidirectional buffer
+update.  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0) with particle-steps/s, neighbour pairs/s,
+the FP64-path figures, the roofline of the dominant kernel (HIP events on
+the library's stream over the timed region) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+
+WORKLOADS = {
+    # name: (generator, kwargs, label)
+    "uchannel": ("make_uchannel", {}, "2D U-channel, dp=H/40, ~50k fluid particles, Re=50"),
+    "channel": ("make_channel", {}, "2D straight channel 10Hx1H, dp=H/20, 4k fluid, Re=100"),
+    "jet": ("make_jet", {}, "2D turbulent plane jet 20Dx20D, dp=D/20, 160k, k-eps"),
+    "mixer": ("make_mixer", {}, "3D micro-mixer, dp=0.005, ~3.3M fluid particles"),
+    "adjoint_channel": ("make_adjoint_channel", {}, "2D channel 20Hx1H, dp=H/80, 128k"),
+    "jet_640k": ("make_jet", {"dp": 0.025}, "2D jet geometry at dp=D/40, 640k"),
+    "jet_2560k": ("make_jet", {"dp": 0.0125}, "2D jet geometry at dp=D/80, 2.56M"),
+    "jet_10m": ("make_jet", {"dp": 0.00625}, "2D jet geometry at dp=D/160, 10.2M"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="uchannel", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: --steps)")
+    return ap.parse_args()
+
+
+def make_case(name):
+    import cases
+    gen, kw, _ = WORKLOADS[name]
+    return getattr(cases, gen)(**kw)
+
+
+def run_gpu(case, precision, steps, warmup, torch):
+    from paper_2510_25702_amd import sph
+    g = sph.Simulation(case, precision=precision)
+    g.build_cells()
+    g.buffer_update()                  # label the particles that start in buffers
+    for _ in range(warmup):
+        g.advance()
+    torch.cuda.synchronize()
+    g.pair_count()                     # reset the pair counter
+    g.profile(True)
+    n_real0 = sph.sph_get_count(g.ctx)[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_ac = 0
+    real_steps = 0
+    for _ in range(steps):
+        info, cnt = g.advance()
+        n_ac += info.n_ac
+        real_steps += cnt.n_real
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pairs = g.pair_count()
+    stats = g.kernel_stats()
+    g.profile(False)
+    dt = t1 - t0
+    return dict(seconds=dt, particle_steps=real_steps, n_real=n_real0, pairs=pairs,
+                n_ac=n_ac, stats=stats, sim=g)
+
+
+def roofline(stats):
+    dom = max(("pressure", "density", "advection", "correction", "cells"),
+              key=lambda k: stats[k].total_ms)
+    s = stats[dom]
+    avg_ms = s.total_ms / max(1, s.launches)
+    bytes_per_launch = s.bytes / max(1, s.launches)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return dom, dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                     kernel=dom, avg_launch_us=round(avg_ms * 1e3, 3),
+                     algorithmic_bytes_per_launch=int(bytes_per_launch),
+                     launches=int(s.launches))
+
+
+def cpu_baseline(case, seconds):
+    import oracle
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    nthreads = max(1, min(nthreads, 16))
+    s = oracle.OracleSim(case, threads=nthreads)
+    s.buffer_update()
+    t0 = time.perf_counter()
+    psteps = 0
+    k = 0
+    while True:
+        s.step()
+        c = s.buffer_update()
+        psteps += c.n_real
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=round(psteps / dt, 1), unit="particle-steps/s", cores=nthreads,
+                kind="oracle", sample=f"first {k} advection steps (+ buffer updates) of the "
+                                      f"same workload from its initial state, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"decomposition is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2510_25702_amd import sph
+    case = make_case(args.workload)
+    r32 = run_gpu(case, sph.SPH_FP32_MIXED, args.steps, args.warmup, torch)
+    value = r32["particle_steps"] / r32["seconds"]
+    dom, roof = roofline(r32["stats"])
+    out = {
+        "metric": "particle-steps/s + neighbor pairs/s, FP32-mixed vs FP64 at stated error",
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload][2],
+                   "particles_real": int(r32["n_real"]), "particles_total": int(case.n),
+                   "precision": "fp32-mixed (f32 pair arithmetic; f64 density, position, "
+                                "correction inverse)",
+                   "acoustic_substeps": r32["n_ac"]},
+        "pairs_per_s": round(r32["pairs"] / r32["seconds"], 1),
+        "pairs_per_step": round(r32["pairs"] / args.steps, 1),
+        "roofline": roof,
+        "kernels": {k: {"ms": round(v.total_ms, 3), "launches": int(v.launches),
+                        "avg_us": round(1e3 * v.total_ms / max(1, v.launches), 3),
+                        "GBps_algorithmic": round(v.bytes / max(1e-12, v.total_ms * 1e-3) / 1e9, 1)}
+                    for k, v in r32["stats"].items() if v.launches},
+    }
+    if not args.no_fp64:
+        steps64 = args.fp64_steps or args.steps
+        r64 = run_gpu(case, sph.SPH_FP64, steps64, args.warmup, torch)
+        v64 = r64["particle_steps"] / r64["seconds"]
+        _, roof64 = roofline(r64["stats"])
+        out["fp64"] = {"value": round(v64, 1), "unit": "particle-steps/s", "steps": steps64,
+                       "ms_per_step": round(1e3 * r64["seconds"] / steps64, 4),
+                       "pairs_per_s": round(r64["pairs"] / r64["seconds"], 1),
+                       "roofline": roof64}
+        out["fp32_over_fp64"] = round(value / v64, 3)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -76,6 +76,10 @@ class Case:
     pid: np.ndarray
     steps: int
     note: str = ""
+    drho: np.ndarray = None       # last continuity rate (None: zero)
+    npid: int = None              # id of the next injected particle
+    step: int = 0                 # step counter of the state
+    t: float = 0.0                # physical time of the state
 
     @property
     def n(self) -> int:
@@ -91,6 +95,8 @@ class Case:
 
     @property
     def next_pid(self) -> int:
+        if self.npid is not None:
+            return int(self.npid)
         return int(self.pid.max()) + 1 if self.n else 0
 
     def capacity(self, factor: float = 1.25, extra: int = 4096) -> int:
@@ -209,7 +215,14 @@ def make_adjoint_channel(dp=None, seed=4, steps=100, n_coef=16, amp=0.1):
 # leg, both open faces at x = 0.
 # ----------------------------------------------------------------------------
 def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
-                  noise=1e-3, seed=1, steps=2000):
+                  noise=1e-3, seed=1, steps=2000, ramp_time=5.0, inlet="velocity"):
+    """U-channel with legs of length Lleg joined by a 180-degree bend.
+
+    The driving pressure drop p_in sets the Poiseuille estimate of the mean
+    velocity U (and so nu from Re).  inlet="velocity" prescribes that flow as a
+    parabolic velocity inlet (mean U, ramped); inlet="pressure" prescribes
+    p = p_in at the inlet buffer instead.  The outlet buffer has p = 0.
+    """
     dp = H / 40 if dp is None else dp
     R_in = H
     cy = R_in + H                      # bend centre (Lleg, cy)
@@ -242,15 +255,20 @@ def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
     v = np.zeros((fluid.shape[0], 3))
     v[:, :2] = noise * Umax * rng.uniform(-1.0, 1.0, (fluid.shape[0], 2))
     Lb = 4 * dp
-    inlet = Buffer(1, (0.0, H / 2, 0.0), _frame2(1.0, 0.0), Lb, (H / 2, 0.0),
-                   0.5 * dp, vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED,
-                   p_ob=p_in)
+    if inlet == "pressure":
+        inb = Buffer(1, (0.0, H / 2, 0.0), _frame2(1.0, 0.0), Lb, (H / 2, 0.0),
+                     0.5 * dp, vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED,
+                     p_ob=p_in, ramp_time=ramp_time)
+    else:
+        inb = Buffer(1, (0.0, H / 2, 0.0), _frame2(1.0, 0.0), Lb, (H / 2, 0.0),
+                     0.5 * dp, vel_mode=VEL_PRESCRIBED, p_mode=P_EXTRAPOLATE,
+                     profile=PROFILE_PARABOLIC, u0=Umax, ramp_time=ramp_time)
     outlet = Buffer(2, (0.0, 2 * cy - H / 2, 0.0), _frame2(1.0, 0.0), Lb,
                     (H / 2, 0.0), 0.5 * dp, vel_mode=VEL_EXTRAPOLATE,
                     p_mode=P_PRESCRIBED, p_ob=0.0)
-    return _assemble("uchannel", P, [inlet, outlet], fluid, wall, steps, v=v,
+    return _assemble("uchannel", P, [inb, outlet], fluid, wall, steps, v=v,
                      note=f"U-channel H={H} dp={dp} legs={Lleg} Re={Re} "
-                          f"nu={nu:.4g} U_ref={U:.4g}")
+                          f"nu={nu:.4g} U_ref={U:.4g} {inlet} inlet")
 
 
 # ----------------------------------------------------------------------------

@@ -191,6 +191,8 @@ class OracleSim:
         self.eps[:n] = case.eps
         self.tag[:n] = case.tag
         self.pid[:n] = case.pid
+        if getattr(case, "drho", None) is not None:
+            self.drho[:n] = case.drho
         self.S = StateC()
         self.S.n, self.S.cap = n, cap
         self.S.x, self.S.v = _ptr(self.x), _ptr(self.v)
@@ -198,7 +200,8 @@ class OracleSim:
         self.S.k, self.S.eps = _ptr(self.k), _ptr(self.eps)
         self.S.tag, self.S.pid = _ptr(self.tag, C.c_uint32), _ptr(self.pid, C.c_uint32)
         self.S.next_pid = case.next_pid
-        self.S.step, self.S.t = 0, 0.0
+        self.S.step = int(getattr(case, "step", 0))
+        self.S.t = float(getattr(case, "t", 0.0))
         lib().ora_set_threads(int(threads))
 
     # -- views -------------------------------------------------------------

@@ -244,6 +244,12 @@ static int in_region(int dim, const ora_buffer* b, const double* y) {
   return y[0] >= 0.0 && y[0] <= b->length && contained(dim, b, y);
 }
 
+/* start-up ramp of a buffer's prescribed values: 0.5 (1 - cos(pi t / T)) */
+static double ramp(const ora_buffer* b, double t) {
+  if (b->ramp_time > 0.0 && t < b->ramp_time) return 0.5 * (1.0 - cos(PI * t / b->ramp_time));
+  return 1.0;
+}
+
 static const ora_buffer* find_buffer(const ora_buffer* B, int nbuf, int id) {
   for (int q = 0; q < nbuf; ++q)
     if (B[q].id == id) return &B[q];
@@ -259,40 +265,55 @@ static double pow_dim(double a, int dim) { return dim == 2 ? a * a : a * a * a; 
 /* of Sec. 3.3: near each buffer's open face the mirror images of the real   */
 /* particles (self included) across the face plane complete the support.     */
 /* ------------------------------------------------------------------------ */
+/* B = A^-1 with a guard for ill-conditioned moments (paper silent; reading):
+ * with d = det A / (tr A / dim)^dim (1 for an isotropic support, >= 0.5 for
+ * every healthy, truncated or jittered support), B = A^-1 for d >= 0.25 and
+ * B = w A^-1 + (1 - w) I, w = (d / 0.25)^2, below; B = I if tr A <= 0 or
+ * d <= 0 (fewer than dim independent neighbours). */
 static void invert_guarded(int dim, const double* A, double* Bm) {
+  const double theta = 0.25;
+  double inv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double tr, det, d;
   for (int a = 0; a < 9; ++a) Bm[a] = 0.0;
   if (dim == 2) {
-    double tr = A[0] + A[4];
-    double det = A[0] * A[4] - A[1] * A[3];
-    if (!(tr > 0.0) || !(det > 1e-8 * (0.5 * tr) * (0.5 * tr))) {
+    tr = A[0] + A[4];
+    det = A[0] * A[4] - A[1] * A[3];
+    d = (tr > 0.0) ? det / ((0.5 * tr) * (0.5 * tr)) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
       Bm[0] = Bm[4] = 1.0;
       return;
     }
-    Bm[0] = A[4] / det;
-    Bm[1] = -A[1] / det;
-    Bm[3] = -A[3] / det;
-    Bm[4] = A[0] / det;
-    return;
+    inv[0] = A[4] / det;
+    inv[1] = -A[1] / det;
+    inv[3] = -A[3] / det;
+    inv[4] = A[0] / det;
+  } else {
+    double c00 = A[4] * A[8] - A[5] * A[7];
+    double c01 = A[5] * A[6] - A[3] * A[8];
+    double c02 = A[3] * A[7] - A[4] * A[6];
+    det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    tr = A[0] + A[4] + A[8];
+    double t3 = tr / 3.0;
+    d = (tr > 0.0) ? det / (t3 * t3 * t3) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
+      Bm[0] = Bm[4] = Bm[8] = 1.0;
+      return;
+    }
+    inv[0] = c00 / det;
+    inv[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    inv[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    inv[3] = c01 / det;
+    inv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    inv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    inv[6] = c02 / det;
+    inv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    inv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
   }
-  double c00 = A[4] * A[8] - A[5] * A[7];
-  double c01 = A[5] * A[6] - A[3] * A[8];
-  double c02 = A[3] * A[7] - A[4] * A[6];
-  double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
-  double tr = A[0] + A[4] + A[8];
-  double t3 = tr / 3.0;
-  if (!(tr > 0.0) || !(det > 1e-8 * t3 * t3 * t3)) {
-    Bm[0] = Bm[4] = Bm[8] = 1.0;
-    return;
+  double w = d >= theta ? 1.0 : (d / theta) * (d / theta);
+  for (int a = 0; a < 9; ++a) {
+    double id = (a % 4 == 0 && (a < 8 || dim == 3)) ? 1.0 : 0.0;
+    Bm[a] = w * inv[a] + (1.0 - w) * id;
   }
-  Bm[0] = c00 / det;
-  Bm[1] = (A[2] * A[7] - A[1] * A[8]) / det;
-  Bm[2] = (A[1] * A[5] - A[2] * A[4]) / det;
-  Bm[3] = c01 / det;
-  Bm[4] = (A[0] * A[8] - A[2] * A[6]) / det;
-  Bm[5] = (A[2] * A[3] - A[0] * A[5]) / det;
-  Bm[6] = c02 / det;
-  Bm[7] = (A[1] * A[6] - A[0] * A[7]) / det;
-  Bm[8] = (A[0] * A[4] - A[1] * A[3]) / det;
 }
 
 /* A_i -= V_j r_ij (x) grad W_ij */
@@ -455,6 +476,7 @@ typedef struct {
   const double* Bmat;
   const double* x;
   const double* v;
+  double t;            /* time of the prescribed boundary values */
 } pass_t;
 
 /* Equation of state, Eq. (eos), and Table 1: p_eff = p + 2/3 rho k (RANS). */
@@ -518,7 +540,7 @@ static int pass_pressure(const pass_t* T, double* ap, int64_t* npairs) {
     if (KIND(t) == ORA_BUFFER) {
       const ora_buffer* b = find_buffer(T->B, T->nbuf, BID(t));
       if (b && b->p_mode != ORA_P_NONE) {
-        double pob = b->p_mode == ORA_P_PRESCRIBED ? b->p_ob : pi;
+        double pob = b->p_mode == ORA_P_PRESCRIBED ? b->p_ob * ramp(b, T->t) : pi;
         double c[3];
         if (compB) matvec(Bi, s, c);
         else { c[0] = s[0]; c[1] = s[1]; c[2] = s[2]; }
@@ -701,7 +723,7 @@ int ora_rates_eval(const ora_params* P, const ora_buffer* B, int nbuf,
   volumes(P, S, R->vol);
   for (int64_t i = 0; i < S->n; ++i)
     R->p[i] = is_real(S->tag[i]) ? eos(P, S->rho[i], P->turbulence ? S->k[i] : 0.0) : 0.0;
-  pass_t T = {P, B, nbuf, S, &g, S->rho, R->p, R->vol, Bmat, S->x, S->v};
+  pass_t T = {P, B, nbuf, S, &g, S->rho, R->p, R->vol, Bmat, S->x, S->v, S->t};
   if (R->ap) err |= pass_pressure(&T, R->ap, NULL);
   if (R->drho) err |= pass_density(&T, R->drho, NULL);
   if (R->anu) err |= pass_viscous(&T, R->anu, NULL);
@@ -763,8 +785,7 @@ static double profile_u(const ora_params* P, const ora_buffer* b, const double* 
       u = b->u0;
   }
   if (b->noise_amp != 0.0) u *= 1.0 + b->noise_amp * ora_uniform(P->seed, pid, step, 0);
-  if (b->ramp_time > 0.0 && t < b->ramp_time) u *= 0.5 * (1.0 - cos(PI * t / b->ramp_time));
-  return u;
+  return u * ramp(b, t);
 }
 
 static void apply_velocity_bc(const ora_params* P, const ora_buffer* b,
@@ -785,6 +806,12 @@ int ora_velocity_bc(const ora_params* P, const ora_buffer* B, int nbuf, ora_stat
       apply_velocity_bc(P, b, S->x + 3 * i, S->v + 3 * i, S->pid[i], S->step, S->t);
   }
   return ORA_OK;
+}
+
+/* Density of a buffer particle with a prescribed pressure: Eq. (eos) solved
+ * for p = p_ob (laminar reading of the pressure boundary value). */
+static double rho_of_p(const ora_params* P, double p) {
+  return P->rho0 * (p / (P->rho0 * P->c0 * P->c0) + 1.0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -841,7 +868,7 @@ int ora_advection_step(const ora_params* P, const ora_buffer* B, int nbuf,
         if (m > 0) pairs += m;
       }
   }
-  pass_t T = {P, B, nbuf, S, &g, S->rho, p, vol, Bmat, S->x, S->v};
+  pass_t T = {P, B, nbuf, S, &g, S->rho, p, vol, Bmat, S->x, S->v, S->t};
   err |= pass_viscous(&T, anu, &pairs);
   if (P->turbulence) {
     err |= pass_turbulence(&T, gradv, dk, de);
@@ -1097,8 +1124,7 @@ int ora_buffer_update(const ora_params* P, const ora_buffer* B, int nbuf,
     }
     if (b->vel_mode == ORA_VEL_PRESCRIBED)
       apply_velocity_bc(P, b, S->x + 3 * i, S->v + 3 * i, S->pid[i], S->step, S->t);
-    if (b->p_mode == ORA_P_PRESCRIBED)
-      S->rho[i] = P->rho0 * (b->p_ob / (P->rho0 * P->c0 * P->c0) + 1.0);
+    if (b->p_mode == ORA_P_PRESCRIBED) S->rho[i] = rho_of_p(P, b->p_ob * ramp(b, S->t));
     if (P->turbulence && b->turb_mode == ORA_TURB_FREESTREAM) {
       S->k[i] = b->k_bc;
       S->eps[i] = b->eps_bc;

@@ -1,0 +1,379 @@
+// Cell-linked-list build (Sec. 2.4.1/2.4.3 of the paper: global cell list,
+// rebuilt after deletion every advection step) as a counting sort on gfx950:
+//   keys + per-cell histogram (integer atomics)  ->  exclusive scan  ->
+//   scatter  ->  per-cell ordering by particle id  ->  gather of every field
+// into cell order, emitting cell-relative positions in the pair precision.
+// Also: particle upload / download and small fill kernels.
+#include "sph_ctx.h"
+
+namespace sphx {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_set_particles(int n, const double* __restrict__ x, const double* __restrict__ v,
+                                const double* __restrict__ rho, const double* __restrict__ drho,
+                                const double* __restrict__ kk, const double* __restrict__ ee,
+                                const uint32_t* __restrict__ tag, const uint32_t* __restrict__ pid,
+                                double* X0, double* X1, double* X2, T* V0, T* V1, T* V2,
+                                double* R, T* DR, T* K, T* E, T* NT, uint32_t* TG, uint32_t* PD,
+                                double Cmu, int turb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  X0[i] = x[i];
+  X1[i] = x[n + i];
+  X2[i] = x[2 * n + i];
+  V0[i] = (T)v[i];
+  V1[i] = (T)v[n + i];
+  V2[i] = (T)v[2 * n + i];
+  R[i] = rho[i];
+  DR[i] = drho ? (T)drho[i] : T(0);
+  double k = (turb && kk) ? kk[i] : 0.0, e = (turb && ee) ? ee[i] : 0.0;
+  K[i] = (T)k;
+  E[i] = (T)e;
+  NT[i] = (T)((turb && e > 0.0) ? Cmu * k * k / e : 0.0);
+  TG[i] = tag[i];
+  PD[i] = pid[i];
+}
+
+template <typename T>
+__global__ void k_get_particles(int n, double* x, double* v, double* rho, double* drho,
+                                double* kk, double* ee, uint32_t* tag, uint32_t* pid,
+                                const double* X0, const double* X1, const double* X2,
+                                const T* V0, const T* V1, const T* V2, const double* R,
+                                const T* DR, const T* K, const T* E, const uint32_t* TG,
+                                const uint32_t* PD, int turb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (x) { x[i] = X0[i]; x[n + i] = X1[i]; x[2 * n + i] = X2[i]; }
+  if (v) { v[i] = (double)V0[i]; v[n + i] = (double)V1[i]; v[2 * n + i] = (double)V2[i]; }
+  if (rho) rho[i] = R[i];
+  if (drho) drho[i] = (double)DR[i];
+  if (kk) kk[i] = turb ? (double)K[i] : 0.0;
+  if (ee) ee[i] = turb ? (double)E[i] : 0.0;
+  if (tag) tag[i] = TG[i];
+  if (pid) pid[i] = PD[i];
+}
+
+// K1: cell id of every particle (FP64, floor((x - lo) / cs), IEEE division)
+// and its rank inside the cell; particles tagged dead get key -1.
+template <int DIM>
+__global__ void k_cell_keys(int n, const double* __restrict__ x0, const double* __restrict__ x1,
+                            const double* __restrict__ x2, const uint32_t* __restrict__ tag,
+                            GridDev g, int32_t* __restrict__ key, int32_t* __restrict__ slot,
+                            int32_t* __restrict__ count, uint32_t* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (tag_kind(tag[i]) == kDead) {
+    key[i] = -1;
+    return;
+  }
+  const double* xs[3] = {x0, x1, x2};
+  int c[3] = {0, 0, 0};
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    double q = floor(__ddiv_rn(__dsub_rn(xs[k][i], g.lo[k]), g.cs));
+    if (!(q >= 1.0 && q <= (double)(g.n[k] - 2))) {
+      bad = true;
+      q = (q >= 1.0) ? (double)(g.n[k] - 2) : 1.0;   // also catches NaN
+    }
+    c[k] = (int)q;
+  }
+  if (bad) atomicOr(flags, kFlagOutOfGrid);
+  int id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
+  key[i] = id;
+  slot[i] = atomicAdd(&count[id], 1);
+}
+
+// K2: exclusive scan of the per-cell counts (reduce, scan of partials, apply).
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                              int n, int32_t* __restrict__ part) {
+  __shared__ int sm[kScanThreads / kWave + 1];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) s += (base + q < n) ? in[base + q] : 0;
+  int total;
+  block_excl_scan(s, sm, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* __restrict__ part, int nb,
+                                                             int32_t* __restrict__ out, int n) {
+  __shared__ int sm[kScanThreads / kWave + 1];
+  int base = threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = (base + q < nb) ? part[base + q] : 0;
+    s += v[q];
+  }
+  int total;
+  int off = block_excl_scan(s, sm, &total);
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < nb) part[base + q] = off;
+    off += v[q];
+  }
+  if (threadIdx.x == 0) out[n] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __restrict__ in, int n,
+                                                             const int32_t* __restrict__ part,
+                                                             int32_t* __restrict__ out) {
+  __shared__ int sm[kScanThreads / kWave + 1];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : 0;
+    s += v[q];
+  }
+  int total;
+  int off = block_excl_scan(s, sm, &total) + part[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < n) out[base + q] = off;
+    off += v[q];
+  }
+}
+
+// K3a: scatter to cell-sorted positions (arbitrary order inside a cell).
+__global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t* __restrict__ slot,
+                          const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int k = key[i];
+  if (k < 0) return;
+  perm[cell_start[k] + slot[i]] = i;
+}
+
+// K3b: deterministic order inside every cell (ascending particle id).
+__global__ void k_sort_cells(int ncell, const int32_t* __restrict__ cell_start,
+                             int32_t* __restrict__ perm, const uint32_t* __restrict__ pid) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int b = cell_start[c], e = cell_start[c + 1];
+  for (int a = b + 1; a < e; ++a) {
+    int ia = perm[a];
+    uint32_t pa = pid[ia];
+    int q = a - 1;
+    while (q >= b && pid[perm[q]] > pa) {
+      perm[q + 1] = perm[q];
+      --q;
+    }
+    perm[q + 1] = ia;
+  }
+}
+
+// K3c: gather every field into cell order; cell-relative positions in T.
+template <typename T, int DIM>
+struct GatherArgs {
+  const int32_t* perm;
+  const int32_t* key;
+  const int32_t* cell_start;
+  int ncell;
+  GridDev g;
+  double mass, Vw;
+  int turb;
+  const double* x[3];
+  double* xo[3];
+  T* xro[3];
+  const T* v[3];
+  T* vo[3];
+  const double* rho;
+  double* rhoo;
+  const T* drho;
+  T* drhoo;
+  const T *k, *eps, *nut;
+  T *ko, *epso, *nuto;
+  const uint32_t *tag, *pid;
+  uint32_t *tago, *pido;
+  T* volo;
+  int32_t* cello;
+  uint32_t* flags;
+};
+
+template <typename T, int DIM>
+__global__ void k_gather(int n_out, GatherArgs<T, DIM> a) {
+  int d = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = a.cell_start[a.ncell];
+  if (d == 0 && total != n_out) atomicOr(a.flags, kFlagCountMismatch);
+  if (d >= n_out || d >= total) return;
+  int s = a.perm[d];
+  int c = a.key[s];
+  int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double xv = a.x[k][s];
+    a.xo[k][d] = xv;
+    double org = (k < DIM) ? a.g.lo[k] + (double)cc[k] * a.g.cs : 0.0;
+    a.xro[k][d] = (T)(xv - org);
+    a.vo[k][d] = a.v[k][s];
+  }
+  double r = a.rho[s];
+  a.rhoo[d] = r;
+  a.drhoo[d] = a.drho[s];
+  uint32_t t = a.tag[s];
+  a.tago[d] = t;
+  a.pido[d] = a.pid[s];
+  a.volo[d] = (T)(tag_kind(t) == kWall ? a.Vw : a.mass / r);
+  a.cello[d] = c;
+  if (a.turb) {
+    a.ko[d] = a.k[s];
+    a.epso[d] = a.eps[s];
+    a.nuto[d] = a.nut[s];
+  }
+}
+
+template <typename T>
+T* tp(void* p) { return static_cast<T*>(p); }
+
+template <typename T, int DIM>
+hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
+  hipStream_t st = c->stream;
+  Fields& F = c->F;
+  Scratch& S = c->S;
+  const GridDev& g = c->grid;
+  const int nc = g.ncell;
+  if (n_in > 0) {
+    k_fill_i32<<<(nc + 255) / 256, 256, 0, st>>>(S.count, nc, 0);
+    k_cell_keys<DIM><<<(int)((n_in + 255) / 256), 256, 0, st>>>(
+        (int)n_in, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.tag.live(), g, S.key, S.slot,
+        S.count, S.flags);
+  } else {
+    k_fill_i32<<<(nc + 255) / 256, 256, 0, st>>>(S.count, nc, 0);
+  }
+  int nb = (nc + kScanTile - 1) / kScanTile;
+  k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums);
+  k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc);
+  k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start);
+  if (n_in > 0) {
+    k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>((int)n_in, S.key, S.slot,
+                                                          S.cell_start, S.perm);
+    k_sort_cells<<<(nc + 255) / 256, 256, 0, st>>>(nc, S.cell_start, S.perm, F.pid.live());
+  }
+  GatherArgs<T, DIM> a;
+  a.perm = S.perm;
+  a.key = S.key;
+  a.cell_start = S.cell_start;
+  a.ncell = nc;
+  a.g = g;
+  double Vw = c->P.dim == 2 ? c->P.dp * c->P.dp : c->P.dp * c->P.dp * c->P.dp;
+  a.mass = c->P.rho0 * Vw;
+  a.Vw = Vw;
+  a.turb = c->P.turbulence;
+  for (int k = 0; k < 3; ++k) {
+    a.x[k] = F.x[k].live();
+    a.xo[k] = F.x[k].other();
+    a.xro[k] = tp<T>(F.xr[k].other());
+    a.v[k] = tp<T>(F.v[k].live());
+    a.vo[k] = tp<T>(F.v[k].other());
+  }
+  a.rho = F.rho.live();
+  a.rhoo = F.rho.other();
+  a.drho = tp<T>(F.drho.live());
+  a.drhoo = tp<T>(F.drho.other());
+  a.k = tp<T>(F.k.live());
+  a.eps = tp<T>(F.eps.live());
+  a.nut = tp<T>(F.nut.live());
+  a.ko = tp<T>(F.k.other());
+  a.epso = tp<T>(F.eps.other());
+  a.nuto = tp<T>(F.nut.other());
+  a.tag = F.tag.live();
+  a.pid = F.pid.live();
+  a.tago = F.tag.other();
+  a.pido = F.pid.other();
+  a.volo = tp<T>(F.vol.a[0]);
+  a.cello = F.cell;
+  a.flags = S.flags;
+  k_gather<T, DIM><<<(int)((n_out + 255) / 256) + (n_out == 0), 256, 0, st>>>((int)n_out, a);
+  for (int k = 0; k < 3; ++k) {
+    F.x[k].flip();
+    F.xr[k].cur = F.x[k].cur;
+    F.v[k].flip();
+  }
+  F.rho.flip();
+  F.drho.flip();
+  F.tag.flip();
+  F.pid.flip();
+  if (c->P.turbulence) {
+    F.k.flip();
+    F.eps.flip();
+    F.nut.flip();
+  }
+  F.p.cur = 0;
+  F.vol.cur = 0;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t set_impl(sph_ctx* c, int64_t n, const sph_particles* s) {
+  Fields& F = c->F;
+  int turb = c->P.turbulence;
+  k_set_particles<T><<<(int)((n + 255) / 256) + (n == 0), 256, 0, c->stream>>>(
+      (int)n, s->x, s->v, s->rho, s->drho, s->k, s->eps, s->tag, s->pid, F.x[0].live(),
+      F.x[1].live(), F.x[2].live(), tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
+      tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.drho.live()), tp<T>(F.k.live()),
+      tp<T>(F.eps.live()), tp<T>(F.nut.live()), F.tag.live(), F.pid.live(), c->P.Cmu, turb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t get_impl(sph_ctx* c, const sph_particles* d) {
+  Fields& F = c->F;
+  int64_t n = c->n_total;
+  k_get_particles<T><<<(int)((n + 255) / 256) + (n == 0), 256, 0, c->stream>>>(
+      (int)n, d->x, d->v, d->rho, d->drho, d->k, d->eps, d->tag, d->pid, F.x[0].live(),
+      F.x[1].live(), F.x[2].live(), tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
+      tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.drho.live()), tp<T>(F.k.live()),
+      tp<T>(F.eps.live()), F.tag.live(), F.pid.live(), c->P.turbulence);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) {
+  const int nb = (n + kScanTile - 1) / kScanTile + (n == 0);
+  if (nb > kScanTile) return hipErrorInvalidValue;
+  k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums);
+  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n);
+  k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  k_fill_i32<<<(int)((n + 255) / 256), 256, 0, c->stream>>>(p, n, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src) {
+  return c->P.precision == SPH_FP64 ? set_impl<double>(c, n, src) : set_impl<float>(c, n, src);
+}
+
+hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst) {
+  return c->P.precision == SPH_FP64 ? get_impl<double>(c, dst) : get_impl<float>(c, dst);
+}
+
+hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out) {
+  if (c->P.precision == SPH_FP64)
+    return c->P.dim == 2 ? build_cells_impl<double, 2>(c, n_in, n_out)
+                         : build_cells_impl<double, 3>(c, n_in, n_out);
+  return c->P.dim == 2 ? build_cells_impl<float, 2>(c, n_in, n_out)
+                       : build_cells_impl<float, 3>(c, n_in, n_out);
+}
+
+}  // namespace sphx

@@ -1,0 +1,1075 @@
+// Neighbour passes of the SPH step on gfx950 (Sec. 2.2 of the paper).
+//
+// Layout: every field is a structure-of-arrays in cell order (built by
+// k_cells.hip).  One thread owns one particle i and gathers over the
+// 3^dim cells around the cell it was sorted into; in each cell row the
+// three cells are one contiguous index range, so the j-side reads of a
+// wavefront are contiguous and shared through the vector L1 / L2.  Pair
+// arithmetic runs in T (float in FP32-mixed mode, double in FP64 mode) on
+// cell-relative positions; densities, positions and the inversion of the
+// correction matrix stay in FP64.  Every particle sums its own neighbours
+// (gather form): no floating-point atomics, results are deterministic.
+#include "sph_ctx.h"
+
+namespace sphx {
+
+namespace {
+
+template <typename T>
+T* tp(void* p) { return static_cast<T*>(p); }
+
+template <typename T>
+struct PairCtx {
+  const T* xr[3];
+  const T* vol;
+  const uint32_t* tag;
+  const int32_t* cell;
+  const int32_t* cs;    // cell_start
+  int nx, ny;
+  T csz, rc2, inv_h, kf;
+  long long* pairs;   // directed pairs counter (NULL: not counted)
+};
+
+__device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
+  if (!ctr) return;
+  m = wave_sum_ll(m);
+  if ((threadIdx.x & (kWave - 1)) == 0 && m)
+    atomicAdd(reinterpret_cast<unsigned long long*>(ctr), (unsigned long long)m);
+}
+
+// Visit every j != i with |r_ij|^2 < (2h)^2 among the particles of the
+// 3^DIM build cells around i's cell; r = x_i - x_j from cell-relative
+// positions: r = (xr_i - xr_j) - (cell_j - cell_i) * cs.
+template <typename T, int DIM, typename Fn>
+__device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, const T xi[3],
+                                              Fn&& fn) {
+  const int c = pc.cell[i];
+  const int cx = c % pc.nx;
+  const int cyz = c / pc.nx;
+  const int cy = cyz % pc.ny;
+  const int cz = cyz / pc.ny;
+  constexpr int zr = DIM == 3 ? 1 : 0;
+#pragma unroll
+  for (int dz = -zr; dz <= zr; ++dz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx;
+      const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
+                j3 = pc.cs[base + 2];
+      const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      for (int j = j0; j < j3; ++j) {
+        const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
+        T r[3];
+        r[0] = (xi[0] - pc.xr[0][j]) + ox;
+        r[1] = (xi[1] - pc.xr[1][j]) + oy;
+        r[2] = DIM == 3 ? (xi[2] - pc.xr[2][j]) + oz : T(0);
+        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                              : r[0] * r[0] + r[1] * r[1];
+        if (r2 < pc.rc2 && j != i) fn(j, r, r2);
+      }
+    }
+  }
+}
+
+// B (symmetric, packed xx xy xz yy yz zz) times a vector.
+template <typename T, int DIM>
+__device__ __forceinline__ void symv(const T B[6], const T a[3], T o[3]) {
+  if (DIM == 2) {
+    o[0] = B[0] * a[0] + B[1] * a[1];
+    o[1] = B[1] * a[0] + B[3] * a[1];
+    o[2] = T(0);
+  } else {
+    o[0] = B[0] * a[0] + B[1] * a[1] + B[2] * a[2];
+    o[1] = B[1] * a[0] + B[3] * a[1] + B[4] * a[2];
+    o[2] = B[2] * a[0] + B[4] * a[1] + B[5] * a[2];
+  }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void load_B(const T* const* Bp, int i, T B[6]) {
+  B[0] = Bp[0][i];
+  B[1] = Bp[1][i];
+  B[3] = Bp[3][i];
+  if (DIM == 3) {
+    B[2] = Bp[2][i];
+    B[4] = Bp[4][i];
+    B[5] = Bp[5][i];
+  } else {
+    B[2] = B[4] = B[5] = T(0);
+  }
+}
+
+__device__ __forceinline__ double eos(double rho, double k, double rho0, double c0, int turb) {
+  double p = rho0 * c0 * c0 * (rho / rho0 - 1.0);
+  if (turb) p += (2.0 / 3.0) * rho * k;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// K5: correction matrix, Eq. (equ-B-matrix): A_i = -sum_j V_j r_ij (x) gradW_ij,
+// plus mirror images across every buffer's open face (Sec. 3.3) for
+// obc_mode >= 3, B_i = A_i^-1 in FP64 with a singularity guard.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CorrArgs {
+  const double* x[3];
+  const BufDev* bufs;
+  T* B[6];
+  uint32_t* flags;
+  int mirror;
+};
+
+// B = A^-1 for a well-conditioned moment; with d = det A / (tr A / dim)^dim
+// below 0.25 the inverse is blended towards the identity with weight
+// (d / 0.25)^2, and B = I when tr A <= 0 or d <= 0.
+template <int DIM>
+__device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
+  constexpr double theta = 0.25;
+  double inv[6], det, tr, d;
+  if (DIM == 2) {
+    tr = A[0] + A[3];
+    det = A[0] * A[3] - A[1] * A[1];
+    d = tr > 0.0 ? det / ((0.5 * tr) * (0.5 * tr)) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
+      B[0] = 1.0; B[1] = 0.0; B[3] = 1.0; B[2] = B[4] = B[5] = 0.0;
+      return;
+    }
+    inv[0] = A[3] / det; inv[1] = -A[1] / det; inv[3] = A[0] / det;
+    inv[2] = inv[4] = inv[5] = 0.0;
+  } else {
+    const double c00 = A[3] * A[5] - A[4] * A[4];
+    const double c01 = A[4] * A[2] - A[1] * A[5];
+    const double c02 = A[1] * A[4] - A[3] * A[2];
+    det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    tr = A[0] + A[3] + A[5];
+    const double t3 = tr / 3.0;
+    d = tr > 0.0 ? det / (t3 * t3 * t3) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
+      B[0] = 1.0; B[1] = 0.0; B[2] = 0.0; B[3] = 1.0; B[4] = 0.0; B[5] = 1.0;
+      return;
+    }
+    inv[0] = c00 / det;
+    inv[1] = c01 / det;
+    inv[2] = c02 / det;
+    inv[3] = (A[0] * A[5] - A[2] * A[2]) / det;
+    inv[4] = (A[2] * A[1] - A[0] * A[4]) / det;
+    inv[5] = (A[0] * A[3] - A[1] * A[1]) / det;
+  }
+  const double w = d >= theta ? 1.0 : (d / theta) * (d / theta);
+  const double id[6] = {1.0, 0.0, 0.0, 1.0, 0.0, DIM == 3 ? 1.0 : 0.0};
+  for (int k = 0; k < 6; ++k) B[k] = w * inv[k] + (1.0 - w) * id[k];
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const CorrArgs<T>& a) {
+  if (i >= n) return 0;
+  int m_pairs = 0;
+  const uint32_t ti = pc.tag[i];
+  if (!is_real(ti)) {
+    a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
+    if (DIM == 3) { a.B[2][i] = T(0); a.B[4][i] = T(0); a.B[5][i] = T(1); }
+    return m_pairs;
+  }
+  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+  T A[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  auto acc = [&](const T r[3], T r2, T Vj) {
+    const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+    const T Vf = Vj * f;
+    A[0] -= Vf * r[0] * r[0];
+    A[1] -= Vf * r[0] * r[1];
+    A[3] -= Vf * r[1] * r[1];
+    if (DIM == 3) {
+      A[2] -= Vf * r[0] * r[2];
+      A[4] -= Vf * r[1] * r[2];
+      A[5] -= Vf * r[2] * r[2];
+    }
+  };
+  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+    acc(r, r2, pc.vol[j]);
+    ++m_pairs;
+  });
+  if (a.mirror) {
+    const double xi0 = a.x[0][i], xi1 = a.x[1][i], xi2 = a.x[2][i];
+    const double twoh = 2.0 * C.h;
+    for (int q = 0; q < C.nbuf; ++q) {
+      const BufDev& b = a.bufs[q];
+      double yi[3];
+      to_local(b, xi0, xi1, xi2, yi);
+      if (!(yi[0] >= 0.0 && yi[0] < twoh)) continue;
+      const double tt = 2.0 * yi[0];
+      const double m[3] = {xi0 - tt * b.frame[0], xi1 - tt * b.frame[1], xi2 - tt * b.frame[2]};
+      int cm[3] = {0, 0, 0};
+      bool ok = true;
+      for (int k = 0; k < DIM; ++k) {
+        cm[k] = cell_coord(m[k], C.grid.lo[k], C.grid.cs);
+        if (cm[k] < 1 || cm[k] > C.grid.n[k] - 2) ok = false;
+      }
+      if (!ok) {
+        atomicOr(a.flags, kFlagOutOfGrid);
+        continue;
+      }
+      constexpr int zr = DIM == 3 ? 1 : 0;
+      for (int dz = -zr; dz <= zr; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int base = ((cm[2] + dz) * pc.ny + (cm[1] + dy)) * pc.nx + cm[0];
+          const int j0 = pc.cs[base - 1], j3 = pc.cs[base + 2];
+          for (int j = j0; j < j3; ++j) {
+            if (!is_real(pc.tag[j])) continue;
+            double yj[3];
+            const double xj0 = a.x[0][j], xj1 = a.x[1][j], xj2 = a.x[2][j];
+            to_local(b, xj0, xj1, xj2, yj);
+            if (!(yj[0] >= 0.0) || !contained(DIM, b, yj)) continue;
+            const double tj = 2.0 * yj[0];
+            const T r[3] = {(T)(xi0 - (xj0 - tj * b.frame[0])),
+                            (T)(xi1 - (xj1 - tj * b.frame[1])),
+                            (T)(DIM == 3 ? xi2 - (xj2 - tj * b.frame[2]) : 0.0)};
+            const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                  : r[0] * r[0] + r[1] * r[1];
+            if (r2 < pc.rc2) acc(r, r2, pc.vol[j]);
+          }
+        }
+    }
+  }
+  double Ad[6] = {(double)A[0], (double)A[1], (double)A[2],
+                  (double)A[3], (double)A[4], (double)A[5]};
+  double Bd[6];
+  invert_sym<DIM>(Ad, Bd);
+  a.B[0][i] = (T)Bd[0];
+  a.B[1][i] = (T)Bd[1];
+  a.B[3][i] = (T)Bd[3];
+  if (DIM == 3) {
+    a.B[2][i] = (T)Bd[2];
+    a.B[4][i] = (T)Bd[4];
+    a.B[5][i] = (T)Bd[5];
+  }
+  return m_pairs;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = correction_body<T, DIM>(i, n, pc, C, a);
+  count_pairs(pc.pairs, m);
+}
+
+// ---------------------------------------------------------------------------
+// K6: advection-level pass.  ARD viscous acceleration, Eqs.
+// (eq-discretize-momentum-ARD2/-ARD-viscosity); RANS: velocity gradient,
+// Eq. (velo-grad-equ), k / epsilon diffusion and sources, Eqs.
+// (k-/epsilon-discretized-equ), explicit update over dt_adv, floors and
+// free-stream values; then the first half density update of the first
+// acoustic sub-step and its pressure / volume.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdvArgs {
+  const T* v[3];
+  double* rho;
+  const T* drho;
+  const T* B[6];
+  const T *k, *eps, *nut;
+  T *ko, *epso, *nuto;
+  T* anu[3];
+  T *p_out, *vol_out;
+  const BufDev* bufs;
+  const int32_t* bidx;
+  double dt_adv, half_dt;
+  int rates_only;
+  double *o_anu, *o_gradv, *o_dk, *o_deps;
+  int64_t n_out;
+};
+
+template <typename T, int DIM, int TURB>
+__device__ __forceinline__ int advection_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const AdvArgs<T>& a) {
+  if (i >= n) return 0;
+  int m_pairs = 0;
+  const uint32_t ti = pc.tag[i];
+  if (!is_real(ti)) {
+    if (!a.rates_only) {
+      for (int k = 0; k < 3; ++k) a.anu[k][i] = T(0);
+      a.p_out[i] = T(0);
+      a.vol_out[i] = (T)C.Vw;
+      if (TURB) { a.ko[i] = T(0); a.epso[i] = T(0); a.nuto[i] = T(0); }
+    }
+    return m_pairs;
+  }
+  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+  const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
+  const double rho_i = a.rho[i];
+  const T nut_i = TURB ? a.nut[i] : T(0);
+  const T mu_i = C.rho0_t * ((T)C.nu_l + nut_i);
+  T av[3] = {T(0), T(0), T(0)};
+  T G[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  T Bi[6];
+  T ki = T(0), ei = T(0), Dk_i = T(0), De_i = T(0), dfk = T(0), dfe = T(0);
+  if (TURB) {
+    load_B<T, DIM>(a.B, i, Bi);
+    ki = a.k[i];
+    ei = a.eps[i];
+    Dk_i = (T)C.nu_l + nut_i / (T)C.sigma_k;
+    De_i = (T)C.nu_l + nut_i / (T)C.sigma_eps;
+  }
+  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+    ++m_pairs;
+    const T rr = sqrt(r2);
+    const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
+    const T Vj = pc.vol[j];
+    const bool wall = tag_kind(pc.tag[j]) == kWall;
+    // no-slip dummy wall: antisymmetric velocity, same viscosity as i
+    T vij[3];
+    if (wall) {
+      vij[0] = T(2) * vi[0]; vij[1] = T(2) * vi[1]; vij[2] = T(2) * vi[2];
+    } else {
+      vij[0] = vi[0] - a.v[0][j];
+      vij[1] = vi[1] - a.v[1][j];
+      vij[2] = DIM == 3 ? vi[2] - a.v[2][j] : T(0);
+    }
+    T mu_ad;
+    if (TURB) {
+      const T nut_j = wall ? nut_i : a.nut[j];
+      const T mu_j = C.rho0_t * ((T)C.nu_l + nut_j);
+      const T mu_h = T(2) * mu_i * mu_j / (mu_i + mu_j);
+      // ARD limiter: beta = min(eta max(v_ij . e_ij, 0), c0), e_ij from i to j
+      T beta = T(0);
+      if (rr > T(0)) {
+        const T ve = -(vij[0] * r[0] + vij[1] * r[1] + vij[2] * r[2]) / rr;
+        beta = fmin(C.eta_t * fmax(ve, T(0)), C.c0_t);
+      }
+      mu_ad = fmax(mu_h, C.mu_R_t * beta);
+    } else {
+      mu_ad = mu_i;
+    }
+    const T s = mu_ad * f * Vj;
+    av[0] += s * vij[0];
+    av[1] += s * vij[1];
+    av[2] += s * vij[2];
+    if (TURB) {
+      const T gW[3] = {f * r[0], f * r[1], f * r[2]};
+      T BgW[3];
+      symv<T, DIM>(Bi, gW, BgW);
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) G[3 * p + q] -= Vj * vij[p] * BgW[q];
+      if (!wall) {
+        const T nut_j = a.nut[j];
+        const T Dk_j = (T)C.nu_l + nut_j / (T)C.sigma_k;
+        const T De_j = (T)C.nu_l + nut_j / (T)C.sigma_eps;
+        dfk += T(2) * Dk_i * Dk_j / (Dk_i + Dk_j) * (ki - a.k[j]) * f * Vj;
+        dfe += T(2) * De_i * De_j / (De_i + De_j) * (ei - a.eps[j]) * f * Vj;
+      }
+    }
+  });
+  const double two_over_rho = 2.0 / rho_i;
+  double anu_d[3] = {two_over_rho * (double)av[0], two_over_rho * (double)av[1],
+                     two_over_rho * (double)av[2]};
+  double k_new = 0.0, e_new = 0.0, nut_new = 0.0;
+  if (TURB) {
+    double diff_k = two_over_rho * (double)dfk, diff_e = two_over_rho * (double)dfe;
+    double dd = 0.0, tr = 0.0;
+    for (int p = 0; p < DIM; ++p) {
+      tr += (double)G[3 * p + p];
+      for (int q = 0; q < DIM; ++q)
+        dd += ((double)G[3 * p + q] + (double)G[3 * q + p]) * (double)G[3 * p + q];
+    }
+    const double kd = (double)ki, ed = (double)ei;
+    const double Gk = (double)nut_i * dd - (2.0 / 3.0) * kd * tr;
+    const double dk = Gk - ed + diff_k;
+    const double de = C.C1 * (ed / kd) * Gk - C.C2 * ed * ed / kd + diff_e;
+    if (a.rates_only) {
+      if (a.o_dk) a.o_dk[i] = dk;
+      if (a.o_deps) a.o_deps[i] = de;
+      if (a.o_gradv)
+        for (int p = 0; p < 9; ++p) a.o_gradv[(int64_t)p * a.n_out + i] = (double)G[p];
+    } else {
+      k_new = fmax(kd + a.dt_adv * dk, C.k_floor);
+      e_new = fmax(ed + a.dt_adv * de, C.eps_floor);
+      if (tag_kind(ti) == kBuffer) {
+        const int q = a.bidx[tag_bid(ti)];
+        if (q >= 0 && a.bufs[q].turb_mode == kTurbFreestream) {
+          k_new = a.bufs[q].k_bc;
+          e_new = a.bufs[q].eps_bc;
+        }
+      }
+      nut_new = C.Cmu * k_new * k_new / e_new;
+    }
+  }
+  if (a.rates_only) {
+    if (a.o_anu)
+      for (int k = 0; k < 3; ++k) a.o_anu[(int64_t)k * a.n_out + i] = anu_d[k];
+    return m_pairs;
+  }
+  for (int k = 0; k < 3; ++k) a.anu[k][i] = (T)anu_d[k];
+  if (TURB) {
+    a.ko[i] = (T)k_new;
+    a.epso[i] = (T)e_new;
+    a.nuto[i] = (T)nut_new;
+  }
+  // first half density update of the first acoustic sub-step
+  const double rho_h = rho_i + a.half_dt * (double)a.drho[i];
+  a.rho[i] = rho_h;
+  a.p_out[i] = (T)eos(rho_h, k_new, C.rho0, C.c0, TURB);
+  a.vol_out[i] = (T)(C.mass / rho_h);
+  return m_pairs;
+}
+
+template <typename T, int DIM, int TURB>
+__global__ __launch_bounds__(256) void k_advection(int n, PairCtx<T> pc, Consts<T> C, AdvArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = advection_body<T, DIM, TURB>(i, n, pc, C, a);
+  count_pairs(pc.pairs, m);
+}
+
+// ---------------------------------------------------------------------------
+// K8: pressure relaxation.  RKGC pair sum, Eq. (eq-discretize-momentum-p-RKGC),
+// with the open-boundary compensation of Eq. (eq-pressure-gradient-obc-B-
+// final) (Table 2 variant), velocity kick with the viscous and body force,
+// velocity boundary condition of prescribed-velocity buffers, FP64 drift.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PressArgs {
+  const T *p;
+  const double* rho;
+  const T* B[6];
+  T* v[3];
+  const T* anu[3];
+  const double* x[3];
+  double* xo[3];
+  T* xro[3];
+  const uint32_t* pid;
+  const BufDev* bufs;
+  const int32_t* bidx;
+  uint32_t* flags;
+  double dt;
+  int64_t step;
+  double t;
+  int rates_only;
+  double* o_ap;
+  int64_t n_out;
+};
+
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ int pressure_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const PressArgs<T>& a) {
+  if (i >= n) return 0;
+  int m_pairs = 0;
+  const uint32_t ti = pc.tag[i];
+  if (!is_real(ti)) {
+    if (!a.rates_only) {
+      for (int k = 0; k < 3; ++k) {
+        a.xo[k][i] = a.x[k][i];
+        a.xro[k][i] = pc.xr[k][i];
+      }
+    }
+    return m_pairs;
+  }
+  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+  const T pi = a.p[i];
+  T Bi[6];
+  if (MODE >= 2) load_B<T, DIM>(a.B, i, Bi);
+  T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
+  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+    ++m_pairs;
+    const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+    const T Vj = pc.vol[j];
+    const bool wall = tag_kind(pc.tag[j]) == kWall;
+    const T gW[3] = {f * r[0], f * r[1], DIM == 3 ? f * r[2] : T(0)};
+    if (MODE >= 2) {
+      // (p_i B_j + p_j B_i) gradW; wall: p_w = p_i, B_w = B_i
+      T Bj[6];
+      T pj;
+      if (wall) {
+        pj = pi;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Bj[q] = Bi[q];
+      } else {
+        pj = a.p[j];
+        load_B<T, DIM>(a.B, j, Bj);
+      }
+      T bj[3], bi[3];
+      symv<T, DIM>(Bj, gW, bj);
+      symv<T, DIM>(Bi, gW, bi);
+      const T vpi = Vj * pi, vpj = Vj * pj;
+      acc[0] += vpi * bj[0] + vpj * bi[0];
+      acc[1] += vpi * bj[1] + vpj * bi[1];
+      acc[2] += vpi * bj[2] + vpj * bi[2];
+    } else {
+      const T pj = wall ? pi : a.p[j];
+      const T w = Vj * (pi + pj);
+      acc[0] += w * gW[0];
+      acc[1] += w * gW[1];
+      acc[2] += w * gW[2];
+    }
+    s[0] += Vj * gW[0];
+    s[1] += Vj * gW[1];
+    s[2] += Vj * gW[2];
+  });
+  int q = -1;
+  if (tag_kind(ti) == kBuffer) q = a.bidx[tag_bid(ti)];
+  if (q >= 0 && a.bufs[q].p_mode != kPNone) {
+    const T pob = a.bufs[q].p_mode == kPPrescribed
+                      ? (T)(a.bufs[q].p_ob * buffer_ramp(a.bufs[q], a.t)) : pi;
+    T cc[3];
+    if (MODE == 4) symv<T, DIM>(Bi, s, cc);
+    else { cc[0] = s[0]; cc[1] = s[1]; cc[2] = s[2]; }
+    acc[0] -= T(2) * pob * cc[0];
+    acc[1] -= T(2) * pob * cc[1];
+    acc[2] -= T(2) * pob * cc[2];
+  }
+  const double inv_rho = 1.0 / a.rho[i];
+  const double ap[3] = {-(double)acc[0] * inv_rho, -(double)acc[1] * inv_rho,
+                        -(double)acc[2] * inv_rho};
+  if (a.rates_only) {
+    for (int k = 0; k < 3; ++k) a.o_ap[(int64_t)k * a.n_out + i] = ap[k];
+    return m_pairs;
+  }
+  const double xd[3] = {a.x[0][i], a.x[1][i], a.x[2][i]};
+  double vn[3];
+  for (int k = 0; k < 3; ++k)
+    vn[k] = (k < DIM) ? (double)a.v[k][i] + a.dt * (ap[k] + (double)a.anu[k][i] + C.g[k]) : 0.0;
+  if (q >= 0 && a.bufs[q].vel_mode == kVelPrescribed) {
+    const BufDev& b = a.bufs[q];
+    double y[3];
+    to_local(b, xd[0], xd[1], xd[2], y);
+    const double u = profile_speed(DIM, b, y, C.seed, a.pid[i], a.step, a.t);
+    for (int k = 0; k < DIM; ++k) vn[k] = u * b.frame[k];
+  }
+  const int c = pc.cell[i];
+  const int cc3[3] = {c % pc.nx, (c / pc.nx) % pc.ny, c / (pc.nx * pc.ny)};
+  bool bad = false;
+  for (int k = 0; k < 3; ++k) {
+    if (k < DIM) {
+      const T vt = (T)vn[k];
+      a.v[k][i] = vt;
+      const double xn = xd[k] + a.dt * (double)vt;
+      a.xo[k][i] = xn;
+      const double rel = xn - (C.grid.lo[k] + (double)cc3[k] * C.grid.cs);
+      if (!(rel >= -C.skin && rel <= C.grid.cs + C.skin)) bad = true;
+      a.xro[k][i] = (T)rel;
+    } else {
+      a.xo[k][i] = xd[k];
+      a.xro[k][i] = pc.xr[k][i];
+    }
+  }
+  if (bad) atomicOr(a.flags, kFlagSkin);
+  return m_pairs;
+}
+
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(256) void k_pressure(int n, PairCtx<T> pc, Consts<T> C, PressArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = pressure_body<T, DIM, MODE>(i, n, pc, C, a);
+  count_pairs(pc.pairs, m);
+}
+
+// ---------------------------------------------------------------------------
+// K9: density relaxation.  Continuity with the Riemann intermediate velocity,
+// Eqs. (discretize-continuity-equ-riemann) and (eq-intermediate-vel):
+// (v_i - v*) . gradW_ij = v_ij . gradW_ij / 2 + (p_i - p_j) / (2 rho0 c0) W'
+// with the Riemann axis from i to j; walls: v_w = 0, p_w = p_i.  Second half
+// density update (FP64) and, if another sub-step follows, its first half
+// update, pressure and volume.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DensArgs {
+  const T* v[3];
+  const T* p;
+  double* rho;
+  T* drho;
+  const T* k;
+  T *p_out, *vol_out;
+  double half_dt;
+  int last;
+  int rates_only;
+  double* o_drho;
+};
+
+template <typename T, int DIM, int TURB>
+__global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T> C,
+                                                 DensArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  long long cnt = 0;
+  if (i < n) {
+    const uint32_t ti = pc.tag[i];
+    if (is_real(ti)) {
+      const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
+      const T pi = a.p[i];
+      T sum = T(0);
+      int m = 0;
+      for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+        const T rr = sqrt(r2);
+        const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
+        const bool wall = tag_kind(pc.tag[j]) == kWall;
+        T vr, dp;
+        if (wall) {
+          vr = vi[0] * r[0] + vi[1] * r[1] + vi[2] * r[2];
+          dp = T(0);
+        } else {
+          vr = (vi[0] - a.v[0][j]) * r[0] + (vi[1] - a.v[1][j]) * r[1] +
+               (DIM == 3 ? (vi[2] - a.v[2][j]) * r[2] : T(0));
+          dp = pi - a.p[j];
+        }
+        sum += pc.vol[j] * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr);
+        ++m;
+      });
+      cnt = m;
+      const double rho_i = a.rho[i];
+      const double drho = 2.0 * rho_i * (double)sum;
+      if (a.rates_only) {
+        a.o_drho[i] = drho;
+      } else {
+        a.drho[i] = (T)drho;
+        double rho_n = rho_i + a.half_dt * drho;
+        if (!a.last) {
+          rho_n = rho_n + a.half_dt * drho;
+          a.p_out[i] = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
+          a.vol_out[i] = (T)(C.mass / rho_n);
+        }
+        a.rho[i] = rho_n;
+      }
+    } else if (!a.rates_only && !a.last) {
+      a.p_out[i] = T(0);
+      a.vol_out[i] = (T)C.Vw;
+    }
+  }
+  count_pairs(pc.pairs, cnt);
+}
+
+// p and V from the current density (rates at a state).
+template <typename T>
+__global__ void k_prepare_pv(int n, Consts<T> C, const double* rho, const T* kk,
+                             const uint32_t* tag, T* p, T* vol, double* o_p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!is_real(tag[i])) {
+    p[i] = T(0);
+    vol[i] = (T)C.Vw;
+    if (o_p) o_p[i] = 0.0;
+    return;
+  }
+  const double r = rho[i];
+  const double pp = eos(r, C.turbulence ? (double)kk[i] : 0.0, C.rho0, C.c0, C.turbulence);
+  p[i] = (T)pp;
+  vol[i] = (T)(C.mass / r);
+  if (o_p) o_p[i] = pp;
+}
+
+// ---------------------------------------------------------------------------
+// K11: max |v|^2, max nu_t over real particles and a non-finite flag.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_part(int n, const T* v0, const T* v1,
+                                                     const T* v2, const double* rho,
+                                                     const T* nut, const uint32_t* tag,
+                                                     int turb, double* part) {
+  __shared__ double sm[2][256 / kWave];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (i < n && is_real(tag[i])) {
+    const double x = v0[i], y = v1[i], z = v2[i];
+    a = (x * x + y * y) + z * z;
+    const double r = rho[i];
+    if (!(a == a) || !(r == r) || isinf(a) || isinf(r)) a = INFINITY;
+    if (turb) b = nut[i];
+  }
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) { sm[0][wid] = a; sm[1][wid] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+      a = fmax(a, sm[0][w]);
+      b = fmax(b, sm[1][w]);
+    }
+    part[2 * blockIdx.x] = sm[0][0] > a ? sm[0][0] : a;
+    part[2 * blockIdx.x + 1] = sm[1][0] > b ? sm[1][0] : b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(int nb, const double* part, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    a = fmax(a, part[2 * q]);
+    b = fmax(b, part[2 * q + 1]);
+  }
+  __shared__ double sm[2][256 / kWave];
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) { sm[0][wid] = a; sm[1][wid] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      a = fmax(a, sm[0][w]);
+      b = fmax(b, sm[1][w]);
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: neighbour lists with the FP64 predicate (parity / diagnostics).
+// ---------------------------------------------------------------------------
+template <int DIM, int FILL>
+__global__ void k_neighbors(int n, const double* x0, const double* x1, const double* x2,
+                            const int32_t* cell, const int32_t* cstart, int nx, int ny,
+                            double rc2, int32_t* row, int32_t* col, int64_t cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell[i];
+  const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+  const double xi0 = x0[i], xi1 = x1[i], xi2 = x2[i];
+  int m = 0;
+  int64_t o = FILL ? row[i] : 0;
+  constexpr int zr = DIM == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * ny + (cy + dy)) * nx + cx;
+      for (int j = cstart[base - 1]; j < cstart[base + 2]; ++j) {
+        if (j == i) continue;
+        const double d0 = __dsub_rn(xi0, x0[j]), d1 = __dsub_rn(xi1, x1[j]),
+                     d2 = __dsub_rn(xi2, x2[j]);
+        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)),
+                                    __dmul_rn(d2, d2));
+        if (r2 < rc2) {
+          if (FILL && o + m < cap) col[o + m] = j;
+          ++m;
+        }
+      }
+    }
+  if (!FILL) row[i] = m;
+}
+
+template <typename T, int DIM>
+__global__ void k_export_B(int n, const T* B0, const T* B1, const T* B2, const T* B3,
+                           const T* B4, const T* B5, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double b[6] = {(double)B0[i], (double)B1[i], DIM == 3 ? (double)B2[i] : 0.0,
+                 (double)B3[i], DIM == 3 ? (double)B4[i] : 0.0,
+                 DIM == 3 ? (double)B5[i] : 0.0};
+  const int64_t N = n;
+  out[0 * N + i] = b[0];
+  out[1 * N + i] = b[1];
+  out[2 * N + i] = b[2];
+  out[3 * N + i] = b[1];
+  out[4 * N + i] = b[3];
+  out[5 * N + i] = b[4];
+  out[6 * N + i] = b[2];
+  out[7 * N + i] = b[4];
+  out[8 * N + i] = b[5];
+}
+
+// ---------------------------------------------------------------------------
+// host-side argument assembly
+// ---------------------------------------------------------------------------
+template <typename T>
+Consts<T> make_consts(const sph_ctx* c) {
+  Consts<T> C;
+  const sph_params& P = c->P;
+  C.dim = P.dim;
+  C.turbulence = P.turbulence;
+  C.obc_mode = P.obc_mode;
+  C.nbuf = c->nbuf;
+  C.grid = c->grid;
+  C.h = P.h;
+  const double rc = 2.0 * P.h;
+  C.rc2 = rc * rc;
+  C.dp = P.dp;
+  C.Vw = P.dim == 2 ? P.dp * P.dp : P.dp * P.dp * P.dp;
+  C.mass = P.rho0 * C.Vw;
+  C.rho0 = P.rho0;
+  C.c0 = P.c0;
+  C.nu_l = P.nu_l;
+  C.eta = P.eta;
+  for (int k = 0; k < 3; ++k) C.g[k] = P.g[k];
+  C.C1 = P.C1;
+  C.C2 = P.C2;
+  C.Cmu = P.Cmu;
+  C.sigma_k = P.sigma_k;
+  C.sigma_eps = P.sigma_eps;
+  C.k_floor = P.k_floor;
+  C.eps_floor = P.eps_floor;
+  C.skin = 0.5 * (P.cell_size - 2.0 * P.h);
+  C.seed = P.seed;
+  const double alpha = P.dim == 2 ? 7.0 / (4.0 * M_PI * P.h * P.h)
+                                  : 21.0 / (16.0 * M_PI * P.h * P.h * P.h);
+  C.h_t = (T)P.h;
+  C.rc2_t = (T)C.rc2;
+  C.cs_t = (T)P.cell_size;
+  C.inv_h_t = (T)(1.0 / P.h);
+  C.kf_t = (T)(-5.0 * alpha / (P.h * P.h));
+  C.rho0_t = (T)P.rho0;
+  C.c0_t = (T)P.c0;
+  C.eta_t = (T)P.eta;
+  C.inv_2rc0_t = (T)(1.0 / (2.0 * P.rho0 * P.c0));
+  C.mu_R_t = (T)(0.5 * P.rho0 * P.h);
+  return C;
+}
+
+template <typename T>
+PairCtx<T> make_pc(const sph_ctx* c, const sphx::Slot2<void>* xr, int xslot) {
+  PairCtx<T> pc;
+  for (int k = 0; k < 3; ++k) pc.xr[k] = tp<T>(xr[k].a[xslot]);
+  pc.vol = tp<T>(c->F.vol.live());
+  pc.tag = c->F.tag.live();
+  pc.cell = c->F.cell;
+  pc.cs = c->S.cell_start;
+  pc.nx = c->grid.n[0];
+  pc.ny = c->grid.n[1];
+  pc.csz = (T)c->P.cell_size;
+  const double rc = 2.0 * c->P.h;
+  pc.rc2 = (T)(rc * rc);
+  pc.inv_h = (T)(1.0 / c->P.h);
+  pc.kf = T(0);
+  pc.pairs = c->S.pairs;
+  return pc;
+}
+
+inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
+
+template <typename T, int DIM>
+hipError_t correction_impl(sph_ctx* c) {
+  Consts<T> C = make_consts<T>(c);
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  CorrArgs<T> a;
+  for (int k = 0; k < 3; ++k) a.x[k] = c->F.x[k].live();
+  a.bufs = c->S.bufs;
+  for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(c->F.B[k]);
+  a.flags = c->S.flags;
+  a.mirror = c->P.obc_mode >= 3 ? 1 : 0;
+  const int64_t n = c->n_total;
+  k_correction<T, DIM><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
+                          const sph_rates* out) {
+  Consts<T> C = make_consts<T>(c);
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  AdvArgs<T> a;
+  Fields& F = c->F;
+  for (int k = 0; k < 3; ++k) {
+    a.v[k] = tp<T>(F.v[k].live());
+    a.anu[k] = tp<T>(F.anu[k]);
+  }
+  a.rho = F.rho.live();
+  a.drho = tp<T>(F.drho.live());
+  for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(F.B[k]);
+  a.k = tp<T>(F.k.live());
+  a.eps = tp<T>(F.eps.live());
+  a.nut = tp<T>(F.nut.live());
+  a.ko = tp<T>(F.k.other());
+  a.epso = tp<T>(F.eps.other());
+  a.nuto = tp<T>(F.nut.other());
+  a.p_out = tp<T>(F.p.other());
+  a.vol_out = tp<T>(F.vol.other());
+  a.bufs = c->S.bufs;
+  a.bidx = c->S.bidx;
+  a.dt_adv = dt_adv;
+  a.half_dt = 0.5 * dt_sub;
+  a.rates_only = rates_only ? 1 : 0;
+  a.o_anu = out ? out->anu : nullptr;
+  if (rates_only) pc.pairs = nullptr;
+  a.o_gradv = out ? out->gradv : nullptr;
+  a.o_dk = out ? out->dk : nullptr;
+  a.o_deps = out ? out->deps : nullptr;
+  a.n_out = c->n_total;
+  const int64_t n = c->n_total;
+  if (c->P.turbulence)
+    k_advection<T, DIM, 1><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  else
+    k_advection<T, DIM, 0><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates* out) {
+  Consts<T> C = make_consts<T>(c);
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  Fields& F = c->F;
+  PressArgs<T> a;
+  a.p = tp<T>(F.p.live());
+  a.rho = F.rho.live();
+  for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(F.B[k]);
+  for (int k = 0; k < 3; ++k) {
+    a.v[k] = tp<T>(F.v[k].live());
+    a.anu[k] = tp<T>(F.anu[k]);
+    a.x[k] = F.x[k].live();
+    a.xo[k] = F.x[k].other();
+    a.xro[k] = tp<T>(F.xr[k].other());
+  }
+  a.pid = F.pid.live();
+  a.bufs = c->S.bufs;
+  a.bidx = c->S.bidx;
+  a.flags = c->S.flags;
+  a.dt = dt;
+  a.step = c->step;
+  a.t = c->t;
+  a.rates_only = rates_only ? 1 : 0;
+  a.o_ap = out ? out->ap : nullptr;
+  if (rates_only) pc.pairs = nullptr;
+  a.n_out = c->n_total;
+  const int64_t n = c->n_total;
+  const int nb = nblk(n);
+  switch (c->P.obc_mode) {
+    case 1: k_pressure<T, DIM, 1><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
+    case 2: k_pressure<T, DIM, 2><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
+    case 3: k_pressure<T, DIM, 3><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
+    default: k_pressure<T, DIM, 4><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
+  }
+  if (!rates_only)
+    for (int k = 0; k < 3; ++k) {
+      F.x[k].flip();
+      F.xr[k].cur = F.x[k].cur;
+    }
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
+                        const sph_rates* out) {
+  Consts<T> C = make_consts<T>(c);
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  Fields& F = c->F;
+  DensArgs<T> a;
+  for (int k = 0; k < 3; ++k) a.v[k] = tp<T>(F.v[k].live());
+  a.p = tp<T>(F.p.live());
+  a.rho = F.rho.live();
+  a.drho = tp<T>(F.drho.live());
+  a.k = tp<T>(F.k.live());
+  a.p_out = tp<T>(F.p.other());
+  a.vol_out = tp<T>(F.vol.other());
+  a.half_dt = 0.5 * dt;
+  a.last = last ? 1 : 0;
+  a.rates_only = rates_only ? 1 : 0;
+  a.o_drho = out ? out->drho : nullptr;
+  if (rates_only) pc.pairs = nullptr;
+  const int64_t n = c->n_total;
+  if (c->P.turbulence)
+    k_density<T, DIM, 1><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  else
+    k_density<T, DIM, 0><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  if (!rates_only && !last) {
+    F.p.flip();
+    F.vol.flip();
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t prepare_pv_impl(sph_ctx* c, const sph_rates* out) {
+  Consts<T> C = make_consts<T>(c);
+  Fields& F = c->F;
+  F.p.cur = 0;
+  F.vol.cur = 0;
+  const int64_t n = c->n_total;
+  k_prepare_pv<T><<<nblk(n), 256, 0, c->stream>>>((int)n, C, F.rho.live(), tp<T>(F.k.live()),
+                                                   F.tag.live(), tp<T>(F.p.live()),
+                                                   tp<T>(F.vol.live()), out ? out->p : nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t reduce_impl(sph_ctx* c, double* host2) {
+  Fields& F = c->F;
+  const int64_t n = c->n_total;
+  const int nb = nblk(n);
+  k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, tp<T>(F.v[0].live()),
+                                               tp<T>(F.v[1].live()), tp<T>(F.v[2].live()),
+                                               F.rho.live(), tp<T>(F.nut.live()), F.tag.live(),
+                                               c->P.turbulence, c->S.red + 4);
+  k_reduce_final<<<1, 256, 0, c->stream>>>(nb, c->S.red + 4, c->S.red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(host2, c->S.red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+}
+
+template <typename T, int DIM>
+hipError_t export_B_impl(sph_ctx* c, double* B) {
+  Fields& F = c->F;
+  const int64_t n = c->n_total;
+  k_export_B<T, DIM><<<nblk(n), 256, 0, c->stream>>>(
+      (int)n, tp<T>(F.B[0]), tp<T>(F.B[1]), tp<T>(F.B[2]), tp<T>(F.B[3]), tp<T>(F.B[4]),
+      tp<T>(F.B[5]), B);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define SPHX_DISPATCH(fn, ...)                                                   \
+  (c->P.precision == SPH_FP64                                                    \
+       ? (c->P.dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)) \
+       : (c->P.dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)))
+
+hipError_t launch_correction(sph_ctx* c) { return SPHX_DISPATCH(correction_impl, c); }
+
+hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
+                            const sph_rates* out) {
+  return SPHX_DISPATCH(advection_impl, c, dt_adv, dt_sub, rates_only, out);
+}
+
+hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rates* out) {
+  return SPHX_DISPATCH(pressure_impl, c, dt, rates_only, out);
+}
+
+hipError_t launch_density(sph_ctx* c, double dt, bool last, bool rates_only,
+                          const sph_rates* out) {
+  return SPHX_DISPATCH(density_impl, c, dt, last, rates_only, out);
+}
+
+hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out) {
+  return c->P.precision == SPH_FP64 ? prepare_pv_impl<double>(c, out)
+                                    : prepare_pv_impl<float>(c, out);
+}
+
+hipError_t launch_reduce(sph_ctx* c, double* host2) {
+  return c->P.precision == SPH_FP64 ? reduce_impl<double>(c, host2) : reduce_impl<float>(c, host2);
+}
+
+hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }
+
+hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
+
+hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                            int64_t* n_pairs) {
+  const int64_t n = c->n_total;
+  const double rc = 2.0 * c->P.h;
+  const double rc2 = rc * rc;
+  Fields& F = c->F;
+  const int nb = nblk(n);
+  auto go = [&](auto dimtag, auto filltag) {
+    constexpr int D = decltype(dimtag)::value;
+    constexpr int FL = decltype(filltag)::value;
+    k_neighbors<D, FL><<<nb, 256, 0, c->stream>>>(
+        (int)n, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.cell, c->S.cell_start,
+        c->grid.n[0], c->grid.n[1], rc2, row_ptr, col, cap);
+  };
+  using D2 = std::integral_constant<int, 2>;
+  using D3 = std::integral_constant<int, 3>;
+  using F1 = std::integral_constant<int, 1>;
+  int32_t* counts = c->S.slot;   // scratch (rewritten by every cell build)
+  auto go_count = [&](auto dimtag) {
+    constexpr int D = decltype(dimtag)::value;
+    k_neighbors<D, 0><<<nb, 256, 0, c->stream>>>(
+        (int)n, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.cell, c->S.cell_start,
+        c->grid.n[0], c->grid.n[1], rc2, counts, col, cap);
+  };
+  if (c->P.dim == 2) go_count(D2{}); else go_count(D3{});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan_excl(c, counts, (int)n, row_ptr);
+  if (e != hipSuccess) return e;
+  int32_t total = 0;
+  e = hipMemcpyAsync(&total, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  *n_pairs = total;
+  if (c->P.dim == 2) go(D2{}, F1{}); else go(D3{}, F1{});
+  return hipGetLastError();
+}
+
+}  // namespace sphx

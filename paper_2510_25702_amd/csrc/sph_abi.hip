@@ -1,0 +1,725 @@
+// C ABI of the gfx950 SPH pipeline (declared in include/sph.h): parameter
+// validation, workspace layout, call sequencing, time-step selection and
+// kernel timing.  All device memory comes from the caller's workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "sph_ctx.h"
+
+using namespace sphx;
+
+namespace sphx {
+hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
+}
+
+namespace {
+
+const char* kNoCtx = "sph: null context";
+
+sph_status fail(sph_ctx* c, sph_status s, const char* msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+sph_status hip_fail(sph_ctx* c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return SPH_E_HIP;
+}
+
+#define HIPCHK(c, expr, where)                     \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    size_t off = total;
+    total += align256(bytes ? bytes : 1);
+    return off;
+  }
+};
+
+const char* validate(const sph_params* P, const sph_buffer_desc* B, int32_t nbuf) {
+  if (!P) return "params is NULL";
+  if (P->dim != 2 && P->dim != 3) return "dim must be 2 or 3";
+  if (P->precision != SPH_FP64 && P->precision != SPH_FP32_MIXED) return "bad precision";
+  if (P->turbulence != 0 && P->turbulence != 1) return "turbulence must be 0 or 1";
+  if (P->obc_mode < 1 || P->obc_mode > 4) return "obc_mode must be 1..4";
+  if (!(P->dp > 0) || !(P->h > 0) || !(P->rho0 > 0) || !(P->c0 > 0)) return "dp, h, rho0, c0 must be > 0";
+  if (!(P->nu_l >= 0)) return "nu_l must be >= 0";
+  if (!(P->cell_size >= 2.0 * P->h)) return "cell_size must be >= 2h";
+  if (!(P->cfl_adv > 0) || !(P->cfl_ac > 0) || !(P->u_ref > 0)) return "cfl_adv, cfl_ac, u_ref must be > 0";
+  if (P->turbulence && (!(P->k_floor > 0) || !(P->eps_floor > 0))) return "k/eps floors must be > 0";
+  if (P->capacity <= 0 || P->capacity > (int64_t)INT32_MAX / 2) return "capacity out of range";
+  for (int k = 0; k < P->dim; ++k)
+    if (!(P->hi[k] - P->lo[k] >= 3.0 * P->cell_size)) return "grid must span >= 3 cells per axis";
+  int64_t ncell = 1;
+  for (int k = 0; k < P->dim; ++k) {
+    double nk = std::ceil((P->hi[k] - P->lo[k]) / P->cell_size);
+    if (!(nk < 1e8)) return "grid too large";
+    ncell *= (int64_t)nk;
+  }
+  if (ncell > 16 * 1024 * 1024) return "more than 16M cells";
+  if (nbuf < 0 || nbuf > SPH_MAX_BUFFERS) return "nbuf out of range";
+  if (nbuf > 0 && !B) return "buffers is NULL";
+  for (int q = 0; q < nbuf; ++q) {
+    const sph_buffer_desc& b = B[q];
+    if (b.id < 1 || b.id > 255) return "buffer id must be 1..255";
+    if (q > 0 && b.id <= B[q - 1].id) return "buffer ids must be unique and ascending";
+    if (!(b.length > 0) || !(b.half_width[0] > 0) || !(b.fringe >= 0)) return "bad buffer box";
+    if (P->dim == 3 && !(b.half_width[1] > 0)) return "bad 3D buffer box";
+    if (b.n_coef < 0 || b.n_coef > 16) return "n_coef must be 0..16";
+    if (b.vel_mode < 0 || b.vel_mode > 1 || b.p_mode < 0 || b.p_mode > 2 ||
+        b.turb_mode < 0 || b.turb_mode > 1 || b.profile < 0 || b.profile > 2)
+      return "bad buffer mode";
+    if (P->turbulence && b.turb_mode == SPH_TURB_FREESTREAM && !(b.eps_bc > 0))
+      return "free-stream eps must be > 0";
+  }
+  return nullptr;
+}
+
+void grid_of(const sph_params* P, GridDev* g) {
+  for (int k = 0; k < 3; ++k) {
+    g->lo[k] = P->lo[k];
+    g->n[k] = k < P->dim ? (int32_t)std::ceil((P->hi[k] - P->lo[k]) / P->cell_size) : 1;
+  }
+  g->cs = P->cell_size;
+  g->ncell = g->n[0] * g->n[1] * g->n[2];
+}
+
+// Local cell-linked-list box of a buffer (Sec. 2.4.1): the cells of the
+// global grid covering the box widened by one cell, FP64, no contraction.
+#pragma clang fp contract(off)
+void lcll_box(const sph_params* P, const GridDev& g, const sph_buffer_desc& b, int32_t lo_c[3],
+              int32_t hi_c[3]) {
+  double cs = P->cell_size, m = cs;
+  double y0s[2] = {-m, b.length + b.fringe + m};
+  double y1s[2] = {-b.half_width[0] - m, b.half_width[0] + m};
+  double y2s[2] = {0.0, 0.0};
+  if (P->dim == 3) {
+    y2s[0] = -b.half_width[1] - m;
+    y2s[1] = b.half_width[1] + m;
+  }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c)
+      for (int d = 0; d < 2; ++d)
+        for (int k = 0; k < 3; ++k) {
+          double gk = b.origin[k] + ((y0s[a] * b.frame[k] + y1s[c] * b.frame[3 + k]) +
+                                     y2s[d] * b.frame[6 + k]);
+          if (gk < lo[k]) lo[k] = gk;
+          if (gk > hi[k]) hi[k] = gk;
+        }
+  for (int k = 0; k < 3; ++k) {
+    if (k >= P->dim) {
+      lo_c[k] = hi_c[k] = 0;
+      continue;
+    }
+    int64_t a = (int64_t)std::floor((lo[k] - P->lo[k]) / cs);
+    int64_t c = (int64_t)std::floor((hi[k] - P->lo[k]) / cs);
+    if (a < 0) a = 0;
+    if (c > g.n[k] - 1) c = g.n[k] - 1;
+    lo_c[k] = (int32_t)a;
+    hi_c[k] = (int32_t)c;
+  }
+}
+#pragma clang fp contract(on)
+
+std::vector<int32_t> candidate_cells(const sph_params* P, const GridDev& g,
+                                     const sph_buffer_desc* B, int nbuf) {
+  std::vector<char> mark((size_t)g.ncell, 0);
+  for (int q = 0; q < nbuf; ++q) {
+    int32_t lo[3], hi[3];
+    lcll_box(P, g, B[q], lo, hi);
+    for (int k = 0; k < P->dim; ++k) {   // one more cell for the drift since the build
+      lo[k] = std::max(lo[k] - 1, 1);
+      hi[k] = std::min(hi[k] + 1, g.n[k] - 2);
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) mark[((size_t)z * g.n[1] + y) * g.n[0] + x] = 1;
+  }
+  std::vector<int32_t> out;
+  for (int32_t c = 0; c < g.ncell; ++c)
+    if (mark[c]) out.push_back(c);
+  return out;
+}
+
+struct Plan {
+  Layout L;
+  size_t off_x[3][2], off_xr[3][2], off_v[3][2], off_rho[2], off_drho[2], off_k[2], off_eps[2],
+      off_nut[2], off_tag[2], off_pid[2], off_p[2], off_vol[2], off_B[6], off_anu[3], off_cell,
+      off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
+      off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
+      off_bidx;
+  int n_cand;
+};
+
+void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl) {
+  Layout& L = pl->L;
+  const size_t C = (size_t)P->capacity;
+  const size_t sT = P->precision == SPH_FP64 ? 8 : 4;
+  GridDev g;
+  grid_of(P, &g);
+  for (int k = 0; k < 3; ++k)
+    for (int s = 0; s < 2; ++s) {
+      pl->off_x[k][s] = L.take(C * 8);
+      pl->off_xr[k][s] = L.take(C * sT);
+      pl->off_v[k][s] = L.take(C * sT);
+    }
+  for (int s = 0; s < 2; ++s) {
+    pl->off_rho[s] = L.take(C * 8);
+    pl->off_drho[s] = L.take(C * sT);
+    pl->off_k[s] = L.take(C * sT);
+    pl->off_eps[s] = L.take(C * sT);
+    pl->off_nut[s] = L.take(C * sT);
+    pl->off_tag[s] = L.take(C * 4);
+    pl->off_pid[s] = L.take(C * 4);
+    pl->off_p[s] = L.take(C * sT);
+    pl->off_vol[s] = L.take(C * sT);
+  }
+  for (int k = 0; k < 6; ++k) pl->off_B[k] = L.take(C * sT);
+  for (int k = 0; k < 3; ++k) pl->off_anu[k] = L.take(C * sT);
+  pl->off_cell = L.take(C * 4);
+  pl->off_key = L.take(C * 4);
+  pl->off_slot = L.take(C * 4);
+  pl->off_perm = L.take(C * 4);
+  pl->off_dec = L.take(C * 4);
+  pl->off_count = L.take((size_t)g.ncell * 4);
+  pl->off_cstart = L.take(((size_t)g.ncell + 1) * 4);
+  pl->off_bsums = L.take(4096 * 4);
+  std::vector<int32_t> cand = candidate_cells(P, g, B, nbuf);
+  pl->n_cand = (int)cand.size();
+  pl->off_cand = L.take(cand.size() * 4);
+  pl->off_injk = L.take((size_t)kMaxInject * 8);
+  pl->off_inji = L.take((size_t)kMaxInject * 4);
+  pl->off_counters = L.take(1040 * 4);
+  pl->off_flags = L.take(4);
+  pl->off_red = L.take((C / 256 + 8) * 2 * 8 + 64);
+  pl->off_pairs = L.take(8);
+  pl->off_npid = L.take(8);
+  pl->off_bufs = L.take(sizeof(BufDev) * kMaxBuf);
+  pl->off_bidx = L.take(256 * 4);
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+hipEvent_t take_event(sph_ctx* c) {
+  if (!c->prof.pool.empty()) {
+    hipEvent_t e = c->prof.pool.back();
+    c->prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void resolve_events(sph_ctx* c) {
+  std::vector<Profile::Rec> keep;
+  for (auto& r : c->prof.pending) {
+    if (hipEventQuery(r.b) != hipSuccess) {
+      keep.push_back(r);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof.total_ms[r.kernel] += ms;
+      c->prof.launches[r.kernel] += 1;
+      c->prof.bytes[r.kernel] += r.bytes;
+      c->prof.particles[r.kernel] += r.particles;
+    }
+    c->prof.pool.push_back(r.a);
+    c->prof.pool.push_back(r.b);
+  }
+  c->prof.pending.swap(keep);
+}
+
+int g_prof_kernel = -1;
+
+}  // namespace
+
+namespace sphx {
+
+// Algorithmic bytes per particle of one launch of each neighbour kernel:
+// every input field of the particle read once plus every output written once.
+double kernel_bytes_per_particle(const sph_ctx* c, int kernel) {
+  const double sT = c->P.precision == SPH_FP64 ? 8.0 : 4.0;
+  const double d = c->P.dim;
+  const double nB = d == 2 ? 3 : 6;
+  const bool turb = c->P.turbulence != 0;
+  switch (kernel) {
+    case SPH_K_CORRECTION:  // xr, vol, tag, cell -> B
+      return d * sT + sT + 4 + 4 + nB * sT;
+    case SPH_K_ADVECTION:   // xr, v, vol, rho, drho, tag, cell -> anu(3), rho, p, vol
+      return d * sT + d * sT + sT + 8 + sT + 4 + 4 + 3 * sT + 8 + 2 * sT +
+             (turb ? nB * sT + 3 * sT + 3 * sT : 0.0);
+    case SPH_K_PRESSURE:    // xr, p, vol, B, rho, v, anu, tag, cell, x(3), pid -> v, x(3), xr(3)
+      return d * sT + 2 * sT + nB * sT + 8 + d * sT + 3 * sT + 4 + 4 + 3 * 8 + 4 + d * sT +
+             3 * 8 + 3 * sT;
+    case SPH_K_DENSITY:     // xr, v, p, vol, tag, cell, rho -> drho, rho, p, vol
+      return d * sT + d * sT + 2 * sT + 4 + 4 + 8 + sT + 8 + 2 * sT + (turb ? sT : 0.0);
+    case SPH_K_CELLS:       // keys, scatter, gather of every field (read + write)
+      return 3 * 8 + 4 + 8 + 8 + 4 + 2 * (4 + 4) +
+             2 * (3 * 8 + 3 * sT + 8 + sT + 4 + 4 + (turb ? 3 * sT : 0.0)) + 3 * sT + sT + 4;
+    default:
+      return 0.0;
+  }
+}
+
+void prof_begin(sph_ctx* c, int kernel, double bytes, double particles) {
+  g_prof_kernel = -1;
+  if (!c->prof.on) return;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return;
+  if (hipEventRecord(a, c->stream) != hipSuccess) return;
+  c->prof.pending.push_back({kernel, a, b, bytes, particles});
+  g_prof_kernel = kernel;
+}
+
+void prof_end(sph_ctx* c) {
+  if (!c->prof.on || g_prof_kernel < 0 || c->prof.pending.empty()) return;
+  (void)hipEventRecord(c->prof.pending.back().b, c->stream);
+  g_prof_kernel = -1;
+}
+
+}  // namespace sphx
+
+namespace {
+
+sph_status check_flags(sph_ctx* c, uint32_t f) {
+  if (f & kFlagCapacity) return fail(c, SPH_E_CAPACITY, "particle capacity / injection limit exceeded");
+  if (f & kFlagOutOfGrid) return fail(c, SPH_E_NUMERIC, "particle outside the cell grid");
+  if (f & kFlagSkin) return fail(c, SPH_E_NUMERIC, "particle moved beyond the cell skin in one step");
+  if (f & kFlagCountMismatch) return fail(c, SPH_E_NUMERIC, "cell count mismatch");
+  if (f & kFlagNonFinite) return fail(c, SPH_E_NUMERIC, "non-finite value");
+  return SPH_OK;
+}
+
+void profile_launch(sph_ctx* c, int kernel) {
+  if (!c->prof.on) return;
+  double n = (double)c->n_total;
+  prof_begin(c, kernel, n * kernel_bytes_per_particle(c, kernel), n);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sph_workspace_size(const sph_params* params, const sph_buffer_desc* bufs, int32_t nbuf) {
+  if (validate(params, bufs, nbuf)) return 0;
+  Plan pl;
+  make_plan(params, bufs, nbuf, &pl);
+  return pl.L.total;
+}
+
+sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int32_t nbuf,
+                      void* workspace, size_t ws_bytes, void* hip_stream, sph_ctx** out) {
+  if (!out) return SPH_E_ARG;
+  *out = nullptr;
+  const char* msg = validate(params, bufs, nbuf);
+  if (msg) return SPH_E_ARG;
+  Plan pl;
+  make_plan(params, bufs, nbuf, &pl);
+  if (!workspace || ws_bytes < pl.L.total || ((uintptr_t)workspace & 255)) return SPH_E_ARG;
+  sph_ctx* c = new (std::nothrow) sph_ctx();
+  if (!c) return SPH_E_ARG;
+  c->P = *params;
+  c->nbuf = nbuf;
+  c->bufs_h.assign(bufs, bufs + nbuf);
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  c->cap = params->capacity;
+  (void)hipGetDevice(&c->device);
+  grid_of(params, &c->grid);
+  char* w = c->ws;
+  Fields& F = c->F;
+  for (int k = 0; k < 3; ++k)
+    for (int s = 0; s < 2; ++s) {
+      F.x[k].a[s] = (double*)(w + pl.off_x[k][s]);
+      F.xr[k].a[s] = w + pl.off_xr[k][s];
+      F.v[k].a[s] = w + pl.off_v[k][s];
+    }
+  for (int s = 0; s < 2; ++s) {
+    F.rho.a[s] = (double*)(w + pl.off_rho[s]);
+    F.drho.a[s] = w + pl.off_drho[s];
+    F.k.a[s] = w + pl.off_k[s];
+    F.eps.a[s] = w + pl.off_eps[s];
+    F.nut.a[s] = w + pl.off_nut[s];
+    F.tag.a[s] = (uint32_t*)(w + pl.off_tag[s]);
+    F.pid.a[s] = (uint32_t*)(w + pl.off_pid[s]);
+    F.p.a[s] = w + pl.off_p[s];
+    F.vol.a[s] = w + pl.off_vol[s];
+  }
+  for (int k = 0; k < 6; ++k) F.B[k] = w + pl.off_B[k];
+  for (int k = 0; k < 3; ++k) F.anu[k] = w + pl.off_anu[k];
+  F.cell = (int32_t*)(w + pl.off_cell);
+  Scratch& S = c->S;
+  S.key = (int32_t*)(w + pl.off_key);
+  S.slot = (int32_t*)(w + pl.off_slot);
+  S.perm = (int32_t*)(w + pl.off_perm);
+  S.dec = (uint32_t*)(w + pl.off_dec);
+  S.count = (int32_t*)(w + pl.off_count);
+  S.cell_start = (int32_t*)(w + pl.off_cstart);
+  S.block_sums = (int32_t*)(w + pl.off_bsums);
+  S.cand_cells = (int32_t*)(w + pl.off_cand);
+  S.n_cand_cells = pl.n_cand;
+  S.inj_key = (uint64_t*)(w + pl.off_injk);
+  S.inj_idx = (int32_t*)(w + pl.off_inji);
+  S.counters = (int32_t*)(w + pl.off_counters);
+  S.flags = (uint32_t*)(w + pl.off_flags);
+  S.red = (double*)(w + pl.off_red);
+  S.pairs = (long long*)(w + pl.off_pairs);
+  S.next_pid = (uint64_t*)(w + pl.off_npid);
+  S.bufs = (BufDev*)(w + pl.off_bufs);
+  S.bidx = (int32_t*)(w + pl.off_bidx);
+
+  // buffer table with derived values
+  c->bufdev_h.resize(kMaxBuf);
+  std::vector<int32_t> bidx(256, -1);
+  for (int q = 0; q < nbuf; ++q) {
+    const sph_buffer_desc& b = bufs[q];
+    BufDev& d = c->bufdev_h[q];
+    std::memset(&d, 0, sizeof(d));
+    d.id = b.id;
+    d.vel_mode = b.vel_mode;
+    d.p_mode = b.p_mode;
+    d.turb_mode = b.turb_mode;
+    d.profile = b.profile;
+    d.n_coef = b.n_coef;
+    for (int k = 0; k < 3; ++k) d.origin[k] = b.origin[k];
+    for (int k = 0; k < 9; ++k) d.frame[k] = b.frame[k];
+    d.length = b.length;
+    d.hw[0] = b.half_width[0];
+    d.hw[1] = b.half_width[1];
+    d.fringe = b.fringe;
+    {
+      volatile double L = b.length, f = b.fringe;
+      d.gen = L + f;
+    }
+    d.p_ob = b.p_ob;
+    d.k_bc = b.k_bc;
+    d.eps_bc = b.eps_bc;
+    d.u0 = b.u0;
+    d.noise_amp = b.noise_amp;
+    d.ramp_time = b.ramp_time;
+    {
+      volatile double r0 = params->rho0, c0 = params->c0, pob = b.p_ob;
+      volatile double den = r0 * c0 * c0;
+      volatile double q1 = pob / den;
+      volatile double q2 = q1 + 1.0;
+      d.rho_bc = r0 * q2;
+    }
+    for (int m = 0; m < 16; ++m) d.coef[m] = b.coef[m];
+    lcll_box(params, c->grid, b, d.clo, d.chi);
+    bidx[b.id] = q;
+  }
+  std::vector<int32_t> cand = candidate_cells(params, c->grid, bufs, nbuf);
+  hipStream_t st = c->stream;
+  hipError_t e = hipSuccess;
+  if (nbuf > 0)
+    e = hipMemcpyAsync(S.bufs, c->bufdev_h.data(), sizeof(BufDev) * nbuf, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S.bidx, bidx.data(), 256 * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !cand.empty())
+    e = hipMemcpyAsync(S.cand_cells, cand.data(), cand.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.pairs, 0, 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 8192, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return SPH_E_HIP;
+  }
+  *out = c;
+  return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx* c) {
+  if (!c) return SPH_E_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->prof.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+  return SPH_OK;
+}
+
+const char* sph_last_error(const sph_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
+
+sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph_particles* src) {
+  if (!c) return SPH_E_ARG;
+  if (!src || n < 0 || n > c->cap) return fail(c, SPH_E_ARG, "bad particle count or source");
+  if (n > 0 && (!src->x || !src->v || !src->rho || !src->tag || !src->pid))
+    return fail(c, SPH_E_ARG, "x, v, rho, tag and pid are required");
+  if (c->P.turbulence && n > 0 && (!src->k || !src->eps))
+    return fail(c, SPH_E_ARG, "k and eps are required with turbulence");
+  HIPCHK(c, launch_set_particles(c, n, src), "set_particles");
+  // count walls / real particles on the host side of the copy
+  std::vector<uint32_t> tags((size_t)n);
+  if (n > 0)
+    HIPCHK(c, hipMemcpyAsync(tags.data(), src->tag, n * 4, hipMemcpyDeviceToHost, c->stream),
+           "set_particles tags");
+  uint64_t np = next_pid;
+  HIPCHK(c, hipMemcpyAsync(c->S.next_pid, &np, 8, hipMemcpyHostToDevice, c->stream), "next_pid");
+  HIPCHK(c, hipMemsetAsync(c->S.flags, 0, 4, c->stream), "flags");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "set_particles sync");
+  int64_t real = 0, dead = 0;
+  for (auto t : tags) {
+    if (tag_kind(t) <= kBuffer) real++;
+    if (tag_kind(t) == kDead) dead++;
+  }
+  c->n_total = n;
+  c->n_alive = n - dead;
+  c->n_real = real;
+  c->next_pid = next_pid;
+  c->cells_valid = false;
+  c->B_valid = false;
+  c->moved = false;
+  return SPH_OK;
+}
+
+sph_status sph_get_count(const sph_ctx* c, int64_t* n_total, int64_t* n_real) {
+  if (!c) return SPH_E_ARG;
+  if (n_total) *n_total = c->n_total;
+  if (n_real) *n_real = c->n_real;
+  return SPH_OK;
+}
+
+sph_status sph_get_particles(sph_ctx* c, const sph_particles* dst) {
+  if (!c) return SPH_E_ARG;
+  if (!dst) return fail(c, SPH_E_ARG, "dst is NULL");
+  HIPCHK(c, launch_get_particles(c, dst), "get_particles");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "get_particles sync");
+  return SPH_OK;
+}
+
+sph_status sph_set_clock(sph_ctx* c, int64_t step, double t) {
+  if (!c) return SPH_E_ARG;
+  c->step = step;
+  c->t = t;
+  return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx* c) {
+  if (!c) return SPH_E_ARG;
+  profile_launch(c, SPH_K_CELLS);
+  hipError_t e = launch_build_cells(c, c->n_total, c->n_alive);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "build_cells");
+  c->n_total = c->n_alive;
+  c->cells_valid = true;
+  c->moved = false;
+  c->B_valid = false;
+  return SPH_OK;
+}
+
+sph_status sph_correction(sph_ctx* c) {
+  if (!c) return SPH_E_ARG;
+  if (!c->cells_valid || c->moved)
+    return fail(c, SPH_E_STATE, "sph_correction needs a cell build after the last position change");
+  profile_launch(c, SPH_K_CORRECTION);
+  hipError_t e = launch_correction(c);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "correction");
+  c->B_valid = true;
+  return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
+  if (!c) return SPH_E_ARG;
+  if (!c->cells_valid || c->moved || !c->B_valid)
+    return fail(c, SPH_E_STATE, "sph_step needs sph_build_cells and sph_correction first");
+  if (ctrl && ctrl->dt_adv > 0 && ctrl->n_ac < 1) return fail(c, SPH_E_ARG, "ctrl->n_ac must be >= 1");
+  double* host = (double*)c->pinned;
+  profile_launch(c, SPH_K_REDUCE);
+  hipError_t e = launch_reduce(c, host);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "reduce");
+  HIPCHK(c, hipMemcpyAsync((char*)c->pinned + 64, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream),
+         "flags");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "step sync");
+  if (c->prof.on) resolve_events(c);
+  uint32_t flags = *(uint32_t*)((char*)c->pinned + 64);
+  sph_status fs = check_flags(c, flags);
+  if (fs != SPH_OK) return fs;
+  const double v2max = host[0], nutmax = host[1];
+  if (!std::isfinite(v2max) || !std::isfinite(nutmax))
+    return fail(c, SPH_E_NUMERIC, "non-finite velocity or density");
+  const sph_params& P = c->P;
+  // dual-criteria time step (Sec. 2.3; criteria are a reading of the cited scheme)
+  const double vmax = std::sqrt(v2max);
+  const double numax = P.nu_l + nutmax;
+  const double h = P.h;
+  double dt_adv = P.cfl_adv * std::fmin(h / std::fmax(vmax, P.u_ref), h * h / (2.0 * numax));
+  const double dt_ac = P.cfl_ac * h / (P.c0 + vmax);
+  int n_ac = (int)std::ceil(dt_adv / dt_ac);
+  if (n_ac < 1) n_ac = 1;
+  if (ctrl && ctrl->dt_adv > 0) {
+    dt_adv = ctrl->dt_adv;
+    n_ac = ctrl->n_ac;
+  }
+  const double dt = dt_adv / n_ac;
+
+  profile_launch(c, SPH_K_ADVECTION);
+  e = launch_advection(c, dt_adv, dt, false, nullptr);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "advection");
+  c->F.p.flip();
+  c->F.vol.flip();
+  if (P.turbulence) {
+    c->F.k.flip();
+    c->F.eps.flip();
+    c->F.nut.flip();
+  }
+  for (int s = 0; s < n_ac; ++s) {
+    profile_launch(c, SPH_K_PRESSURE);
+    e = launch_pressure(c, dt, false, nullptr);
+    prof_end(c);
+    if (e != hipSuccess) return hip_fail(c, e, "pressure");
+    profile_launch(c, SPH_K_DENSITY);
+    e = launch_density(c, dt, s == n_ac - 1, false, nullptr);
+    prof_end(c);
+    if (e != hipSuccess) return hip_fail(c, e, "density");
+  }
+  c->step += 1;
+  c->t += dt_adv;
+  c->moved = true;
+  c->B_valid = false;
+  if (out) {
+    out->dt_adv = dt_adv;
+    out->dt_ac = dt;
+    out->vmax = vmax;
+    out->numax = numax;
+    out->t = c->t;
+    out->n_ac = n_ac;
+    out->step = c->step;
+  }
+  return SPH_OK;
+}
+
+sph_status sph_buffer_update(sph_ctx* c, sph_buffer_counts* out) {
+  if (!c) return SPH_E_ARG;
+  if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_buffer_update needs sph_build_cells first");
+  profile_launch(c, SPH_K_BUFFER);
+  hipError_t e = launch_zero_i32(c, c->S.counters, 1040);
+  if (e == hipSuccess) e = launch_buffer_decide(c, false, nullptr);
+  if (e == hipSuccess) e = launch_buffer_apply(c);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
+  char* hb = (char*)c->pinned;
+  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4, hipMemcpyDeviceToHost, c->stream), "counts");
+  HIPCHK(c, hipMemcpyAsync(hb + 4200, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream), "flags");
+  HIPCHK(c, hipMemcpyAsync(hb + 4208, c->S.next_pid, 8, hipMemcpyDeviceToHost, c->stream), "pid");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "buffer sync");
+  if (c->prof.on) resolve_events(c);
+  const int32_t* cnt = (const int32_t*)hb;
+  uint32_t flags = *(uint32_t*)(hb + 4200);
+  if (flags & kFlagCapacity) {
+    // nothing was applied: clear the flag so that the state stays usable
+    uint32_t zero = 0;
+    (void)hipMemcpyAsync(c->S.flags, &zero, 4, hipMemcpyHostToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    return fail(c, SPH_E_CAPACITY, (flags & kFlagInjectOverflow)
+                                       ? "more injections than SPH_MAX_INJECT in one update"
+                                       : "particle capacity exceeded");
+  }
+  int64_t n_inj = cnt[1024], n_del = 0;
+  for (int b = 0; b < 256; ++b) n_del += cnt[512 + b];
+  c->next_pid = *(uint64_t*)(hb + 4208);
+  c->n_total += n_inj;
+  c->n_alive += n_inj - n_del;
+  c->n_real += n_inj - n_del;
+  c->cells_valid = false;
+  c->B_valid = false;
+  if (out) {
+    std::memcpy(out->n_relabel, cnt, 256 * 4);
+    std::memcpy(out->n_inject, cnt + 256, 256 * 4);
+    std::memcpy(out->n_delete, cnt + 512, 256 * 4);
+    std::memcpy(out->n_revert, cnt + 768, 256 * 4);
+    out->n_real = c->n_real;
+    out->n_total = c->n_alive;
+  }
+  return check_flags(c, flags);
+}
+
+sph_status sph_buffer_decisions(sph_ctx* c, uint32_t* dec) {
+  if (!c) return SPH_E_ARG;
+  if (!dec) return fail(c, SPH_E_ARG, "dec is NULL");
+  if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_buffer_decisions needs sph_build_cells");
+  HIPCHK(c, launch_zero_i32(c, (int32_t*)dec, c->n_total), "zero");
+  HIPCHK(c, launch_buffer_decide(c, true, dec), "decide");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "decide sync");
+  return SPH_OK;
+}
+
+sph_status sph_eval_rates(sph_ctx* c, const sph_rates* out) {
+  if (!c) return SPH_E_ARG;
+  if (!out) return fail(c, SPH_E_ARG, "out is NULL");
+  if (!c->cells_valid || c->moved || !c->B_valid)
+    return fail(c, SPH_E_STATE, "sph_eval_rates needs sph_build_cells and sph_correction");
+  HIPCHK(c, launch_prepare_pv(c, out), "prepare_pv");
+  if (out->anu || out->gradv || out->dk || out->deps)
+    HIPCHK(c, launch_advection(c, 0.0, 0.0, true, out), "advection rates");
+  if (out->ap) HIPCHK(c, launch_pressure(c, 0.0, true, out), "pressure rates");
+  if (out->drho) HIPCHK(c, launch_density(c, 0.0, false, true, out), "density rates");
+  if (out->B) HIPCHK(c, launch_export_B(c, out->B), "export B");
+  return SPH_OK;
+}
+
+sph_status sph_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap, int64_t* n_pairs) {
+  if (!c) return SPH_E_ARG;
+  if (!row_ptr || !n_pairs || cap < 0) return fail(c, SPH_E_ARG, "bad neighbour arguments");
+  if (!c->cells_valid || c->moved)
+    return fail(c, SPH_E_STATE, "sph_neighbors needs a cell build after the last position change");
+  HIPCHK(c, launch_neighbors(c, row_ptr, col, cap, n_pairs), "neighbors");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "neighbors sync");
+  if (*n_pairs > cap) return fail(c, SPH_E_CAPACITY, "neighbour list longer than cap");
+  return SPH_OK;
+}
+
+sph_status sph_profile_enable(sph_ctx* c, int32_t on) {
+  if (!c) return SPH_E_ARG;
+  c->prof.on = on != 0;
+  return SPH_OK;
+}
+
+sph_status sph_profile_read(sph_ctx* c, int32_t kernel, sph_kernel_stats* out) {
+  if (!c) return SPH_E_ARG;
+  if (kernel < 0 || kernel >= SPH_K_COUNT || !out) return fail(c, SPH_E_ARG, "bad kernel id");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "profile sync");
+  resolve_events(c);
+  out->total_ms = c->prof.total_ms[kernel];
+  out->launches = c->prof.launches[kernel];
+  out->bytes = c->prof.bytes[kernel];
+  out->particles = c->prof.particles[kernel];
+  return SPH_OK;
+}
+
+sph_status sph_pair_count(sph_ctx* c, int64_t* pairs) {
+  if (!c || !pairs) return SPH_E_ARG;
+  long long v = 0;
+  HIPCHK(c, hipMemcpyAsync(&v, c->S.pairs, 8, hipMemcpyDeviceToHost, c->stream), "pairs");
+  HIPCHK(c, hipMemsetAsync(c->S.pairs, 0, 8, c->stream), "pairs reset");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "pairs sync");
+  *pairs = v;
+  return SPH_OK;
+}
+
+}  // extern "C"

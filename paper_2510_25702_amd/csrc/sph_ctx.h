@@ -1,0 +1,130 @@
+// Host-side context of the gfx950 SPH pipeline and the launcher interface
+// between the C ABI (sph_abi.hip) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sph.h"
+#include "sph_device.h"
+
+namespace sphx {
+
+// Two-slot ("ping-pong") device array: cur() is the live copy.
+template <typename P>
+struct Slot2 {
+  P* a[2] = {nullptr, nullptr};
+  int cur = 0;
+  P* live() const { return a[cur]; }
+  P* other() const { return a[cur ^ 1]; }
+  void flip() { cur ^= 1; }
+};
+
+// Every per-particle field, as raw device pointers inside the workspace.  The
+// pair-precision arrays are typed void* here and cast by the launchers.
+struct Fields {
+  Slot2<double> x[3];      // master positions (FP64)
+  Slot2<void> xr[3];       // cell-relative positions (pair precision)
+  Slot2<void> v[3];        // velocity (pair precision)
+  Slot2<double> rho;       // density (FP64)
+  Slot2<void> drho;        // last continuity rate
+  Slot2<void> k, eps, nut; // RANS
+  Slot2<uint32_t> tag, pid;
+  Slot2<void> p, vol;      // effective pressure and volume, per sub-step
+  void* B[6];              // symmetric correction matrix (pair precision)
+  void* anu[3];            // viscous acceleration of the advection step
+  int32_t* cell;           // build-time cell id per particle
+};
+
+struct Scratch {
+  int32_t* key;            // [cap] cell id of a particle (-1: dropped)
+  int32_t* slot;           // [cap] rank inside the cell (atomic)
+  int32_t* perm;           // [cap] sorted position -> source index
+  int32_t* count;          // [ncell] particles per cell
+  int32_t* cell_start;     // [ncell + 1]
+  int32_t* block_sums;     // scan partials
+  uint32_t* dec;           // [cap] buffer decisions
+  int32_t* cand_cells;     // candidate cells of the buffer update
+  int32_t n_cand_cells;
+  uint64_t* inj_key;       // [kMaxInject]
+  int32_t* inj_idx;        // [kMaxInject]
+  int32_t* counters;       // [4 * 256 + 8] per-buffer counts + misc
+  uint32_t* flags;         // [1] error flags
+  double* red;             // reduction partials
+  long long* pairs;        // [1] pair counter
+  uint64_t* next_pid;      // [1]
+  BufDev* bufs;            // [kMaxBuf]
+  int32_t* bidx;           // [256] buffer index of an id (-1: none)
+};
+
+struct Profile {
+  bool on = false;
+  struct Rec { int kernel; hipEvent_t a, b; double bytes, particles; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[SPH_K_COUNT] = {0};
+  long long launches[SPH_K_COUNT] = {0};
+  double bytes[SPH_K_COUNT] = {0};
+  double particles[SPH_K_COUNT] = {0};
+};
+
+}  // namespace sphx
+
+struct sph_ctx {
+  sph_params P;
+  std::vector<sph_buffer_desc> bufs_h;
+  std::vector<sphx::BufDev> bufdev_h;
+  int nbuf = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  sphx::GridDev grid;
+  sphx::Fields F;
+  sphx::Scratch S;
+  int64_t cap = 0;
+  int64_t n_total = 0;       // used slots (incl. particles tagged dead)
+  int64_t n_alive = 0;       // slots that survive the next cell build
+  int64_t n_real = 0;
+  uint64_t next_pid = 0;
+  int64_t step = 0;
+  double t = 0.0;
+  bool cells_valid = false;  // cell list matches the current arrays
+  bool moved = false;        // positions changed since the cell build
+  bool B_valid = false;
+  bool need_pv0 = false;
+  int pv_half = 0;
+  uint32_t* pinned = nullptr;   // host staging (pinned)
+  std::string err;
+  sphx::Profile prof;
+};
+
+namespace sphx {
+
+// Launchers implemented in the kernel translation units.  Each enqueues on
+// ctx->stream and returns the HIP error of the launch.
+hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n);
+hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src);
+hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst);
+hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out);
+hipError_t launch_correction(sph_ctx* c);
+hipError_t launch_reduce(sph_ctx* c, double* out_host4);
+hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
+                            const sph_rates* out);
+hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rates* out);
+hipError_t launch_density(sph_ctx* c, double dt, bool last, bool rates_only,
+                          const sph_rates* out);
+hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out);
+hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out);
+hipError_t launch_buffer_apply(sph_ctx* c);
+hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                            int64_t* n_pairs);
+hipError_t launch_export_B(sph_ctx* c, double* B);
+
+size_t pair_bytes(const sph_ctx* c);
+void prof_begin(sph_ctx* c, int kernel, double bytes, double particles);
+void prof_end(sph_ctx* c);
+
+}  // namespace sphx

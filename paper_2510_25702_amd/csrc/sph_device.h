@@ -1,0 +1,205 @@
+// Device-side building blocks of the gfx950 SPH pipeline: constants,
+// kernel function, buffer geometry, counter-based random numbers and
+// wave64 scans.  Shared by the kernel translation units of this library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphx {
+
+constexpr int kMaxBuf = 32;
+constexpr int kMaxInject = 4096;
+constexpr int kWave = 64;
+
+enum : uint32_t { kFluid = 0, kBuffer = 1, kWall = 2, kDead = 3 };
+enum : uint32_t { kVelExtrapolate = 0, kVelPrescribed = 1 };
+enum : uint32_t { kPNone = 0, kPPrescribed = 1, kPExtrapolate = 2 };
+enum : uint32_t { kTurbZeroGradient = 0, kTurbFreestream = 1 };
+enum : uint32_t { kProfUniform = 0, kProfParabolic = 1, kProfSine = 2 };
+enum : uint32_t { kDecNone = 0, kDecRelabel = 1, kDecInject = 2, kDecDelete = 3,
+                  kDecRevert = 4, kDecRevertRelabel = 5 };
+
+// error flags raised by kernels (device word, read at synchronisation points)
+enum : uint32_t { kFlagOutOfGrid = 1u, kFlagSkin = 2u, kFlagNonFinite = 4u,
+                  kFlagInjectOverflow = 8u, kFlagCapacity = 16u,
+                  kFlagCountMismatch = 32u };
+
+__host__ __device__ inline uint32_t tag_kind(uint32_t t) { return t & 3u; }
+__host__ __device__ inline uint32_t tag_bid(uint32_t t) { return (t >> 8) & 0xFFu; }
+__host__ __device__ inline bool is_real(uint32_t t) { return (t & 3u) <= kBuffer; }
+
+// Buffer table entry in device memory (copied from sph_buffer_desc, plus
+// derived values computed once on the host).
+struct BufDev {
+  int32_t id, vel_mode, p_mode, turb_mode, profile, n_coef;
+  double origin[3];
+  double frame[9];
+  double length, hw[2], fringe;
+  double gen;          // length + fringe: particle-generation line
+  double p_ob, k_bc, eps_bc, u0, noise_amp, ramp_time;
+  double rho_bc;       // density of Eq. (eos) at p_ob
+  double coef[16];
+  int32_t clo[3], chi[3];   // local cell-linked-list box (cell coordinates)
+};
+
+struct GridDev {
+  double lo[3];
+  double cs;
+  int32_t n[3];
+  int32_t ncell;
+};
+
+// Scalars of the problem, in FP64 and in the pair precision T.
+template <typename T>
+struct Consts {
+  int32_t dim, turbulence, obc_mode, nbuf;
+  GridDev grid;
+  double h, rc2, dp, Vw, mass, rho0, c0, nu_l, eta, g[3];
+  double C1, C2, Cmu, sigma_k, sigma_eps, k_floor, eps_floor;
+  double skin;          // allowed distance of a particle outside its build cell
+  uint64_t seed;
+  T h_t, rc2_t, cs_t, inv_h_t, kf_t;  // kf = -5 alpha / h^2 (dW/dr / r prefactor)
+  T rho0_t, c0_t, eta_t, inv_2rc0_t, mu_R_t;   // mu_R_t = rho0 h / 2
+};
+
+// ---------------------------------------------------------------------------
+// Wendland C2 kernel: W = alpha (1 - q/2)^4 (2q + 1), q = r / h < 2;
+// (dW/dr) / r = -5 alpha (1 - q/2)^3 / h^2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dw_over_r(T r, T inv_h, T kf) {
+  T t = T(1) - T(0.5) * r * inv_h;
+  return kf * t * t * t;
+}
+
+// ---------------------------------------------------------------------------
+// Buffer geometry in FP64 without contraction (bit-reproducible predicates).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
+
+__device__ __forceinline__ void to_local(const BufDev& b, double x0, double x1, double x2,
+                                         double y[3]) {
+  double d0 = dsub(x0, b.origin[0]), d1 = dsub(x1, b.origin[1]), d2 = dsub(x2, b.origin[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    y[k] = dadd(dadd(dmul(b.frame[3 * k], d0), dmul(b.frame[3 * k + 1], d1)),
+                dmul(b.frame[3 * k + 2], d2));
+}
+
+__device__ __forceinline__ bool contained(int dim, const BufDev& b, const double y[3]) {
+  if (fabs(y[1]) > b.hw[0]) return false;
+  if (dim == 3 && fabs(y[2]) > b.hw[1]) return false;
+  return true;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double lo, double cs) {
+  return (int)floor(__ddiv_rn(dsub(x, lo), cs));
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014) and the counter-based uniform number
+// u = 2 (z >> 11) 2^-53 - 1, z = mix(mix(mix(seed) ^ pid) ^ (step << 2 | c)).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline double counter_uniform(uint64_t seed, uint32_t pid, int64_t step,
+                                                  uint32_t comp) {
+  uint64_t z = splitmix64(seed);
+  z = splitmix64(z ^ (uint64_t)pid);
+  z = splitmix64(z ^ (((uint64_t)step << 2) | (uint64_t)comp));
+  return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
+// Start-up ramp of a buffer's prescribed values: 0.5 (1 - cos(pi t / T)).
+__device__ __forceinline__ double buffer_ramp(const BufDev& b, double t) {
+  if (b.ramp_time > 0.0 && t < b.ramp_time) return 0.5 * (1.0 - cos(M_PI * t / b.ramp_time));
+  return 1.0;
+}
+
+// Density of Eq. (eos) at pressure p (laminar).
+__device__ __forceinline__ double rho_of_p(double rho0, double c0, double p) {
+  const double den = __dmul_rn(__dmul_rn(rho0, c0), c0);
+  return __dmul_rn(rho0, __dadd_rn(__ddiv_rn(p, den), 1.0));
+}
+
+// Prescribed speed along n_b of a buffer (Table 3 velocity inlets):
+// uniform / parabolic / parabola + sine series, times the optional noise and
+// start-up ramp.  y = local coordinates of the particle.
+__device__ inline double profile_speed(int dim, const BufDev& b, const double y[3],
+                                       uint64_t seed, uint32_t pid, int64_t step, double t) {
+  double s = (y[1] + b.hw[0]) / (2.0 * b.hw[0]);
+  double u;
+  if (b.profile == kProfParabolic) {
+    u = 4.0 * b.u0 * s * (1.0 - s);
+    if (dim == 3) {
+      double tt = (y[2] + b.hw[1]) / (2.0 * b.hw[1]);
+      u *= 4.0 * tt * (1.0 - tt);
+    }
+  } else if (b.profile == kProfSine) {
+    u = 4.0 * b.u0 * s * (1.0 - s);
+    for (int m = 1; m <= b.n_coef; ++m) u += b.coef[m - 1] * sin((double)m * M_PI * s);
+  } else {
+    u = b.u0;
+  }
+  if (b.noise_amp != 0.0) u *= 1.0 + b.noise_amp * counter_uniform(seed, pid, step, 0);
+  return u * buffer_ramp(b, t);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / block scans
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over the block; `sm` holds >= blockDim.x / 64 ints.
+__device__ __forceinline__ int block_excl_scan(int v, int* sm, int* total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  int inc = wave_incl_scan(v);
+  if (lane == kWave - 1) sm[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    int s = lane < nw ? sm[lane] : 0;
+    int si = wave_incl_scan(s);
+    if (lane < nw) sm[lane] = si - s;
+    if (lane == nw - 1) sm[nw] = si;
+  }
+  __syncthreads();
+  int r = inc - v + sm[wid];
+  if (total) *total = sm[nw];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o, kWave);
+    v = v > t ? v : t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+}  // namespace sphx

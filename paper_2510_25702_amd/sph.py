@@ -1,0 +1,430 @@
+"""Python binding of the gfx950 SPH library (include/sph.h, libsphx.so).
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+kernels of libsphx.so.  PyTorch supplies device memory (one workspace
+tensor per context, plus the exchange arrays) and the stream.  There is no
+fallback: if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphx.so")
+
+SPH_OK, SPH_E_ARG, SPH_E_CAPACITY, SPH_E_HIP, SPH_E_NUMERIC, SPH_E_STATE = range(6)
+SPH_FP64, SPH_FP32_MIXED = 0, 1
+SPH_FLUID, SPH_BUFFER, SPH_WALL, SPH_DEAD = 0, 1, 2, 3
+(SPH_K_CELLS, SPH_K_CORRECTION, SPH_K_ADVECTION, SPH_K_PRESSURE, SPH_K_DENSITY,
+ SPH_K_BUFFER, SPH_K_REDUCE) = range(7)
+KERNEL_NAMES = ["cells", "correction", "advection", "pressure", "density",
+                "buffer", "reduce"]
+STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_CAPACITY", 3: "SPH_E_HIP",
+          4: "SPH_E_NUMERIC", 5: "SPH_E_STATE"}
+
+
+class SphError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sph_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32),
+                ("turbulence", C.c_int32), ("obc_mode", C.c_int32),
+                ("dp", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
+                ("c0", C.c_double), ("nu_l", C.c_double), ("eta", C.c_double),
+                ("g", C.c_double * 3), ("C1", C.c_double), ("C2", C.c_double),
+                ("Cmu", C.c_double), ("sigma_k", C.c_double),
+                ("sigma_eps", C.c_double), ("k_floor", C.c_double),
+                ("eps_floor", C.c_double), ("cfl_adv", C.c_double),
+                ("cfl_ac", C.c_double), ("u_ref", C.c_double),
+                ("cell_size", C.c_double), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("capacity", C.c_int64),
+                ("seed", C.c_uint64)]
+
+
+class sph_buffer_desc(C.Structure):
+    _fields_ = [("id", C.c_int32), ("vel_mode", C.c_int32), ("p_mode", C.c_int32),
+                ("turb_mode", C.c_int32), ("profile", C.c_int32),
+                ("n_coef", C.c_int32), ("origin", C.c_double * 3),
+                ("frame", C.c_double * 9), ("length", C.c_double),
+                ("half_width", C.c_double * 2), ("fringe", C.c_double),
+                ("p_ob", C.c_double), ("k_bc", C.c_double), ("eps_bc", C.c_double),
+                ("u0", C.c_double), ("noise_amp", C.c_double),
+                ("coef", C.c_double * 16), ("ramp_time", C.c_double)]
+
+
+class sph_particles(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in
+                ("x", "v", "rho", "drho", "k", "eps", "tag", "pid")]
+
+
+class sph_rates(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in
+                ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p")]
+
+
+class sph_buffer_counts(C.Structure):
+    _fields_ = [("n_relabel", C.c_int32 * 256), ("n_inject", C.c_int32 * 256),
+                ("n_delete", C.c_int32 * 256), ("n_revert", C.c_int32 * 256),
+                ("n_real", C.c_int64), ("n_total", C.c_int64)]
+
+
+class sph_step_ctrl(C.Structure):
+    _fields_ = [("dt_adv", C.c_double), ("n_ac", C.c_int32), ("pad", C.c_int32)]
+
+
+class sph_step_info(C.Structure):
+    _fields_ = [("dt_adv", C.c_double), ("dt_ac", C.c_double), ("vmax", C.c_double),
+                ("numax", C.c_double), ("t", C.c_double), ("n_ac", C.c_int32),
+                ("pad", C.c_int32), ("step", C.c_int64)]
+
+
+class sph_kernel_stats(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("launches", C.c_int64),
+                ("bytes", C.c_double), ("particles", C.c_double)]
+
+
+EXPORTS = {
+    "sph_workspace_size": (C.c_size_t, [C.POINTER(sph_params), C.POINTER(sph_buffer_desc), C.c_int32]),
+    "sph_create": (C.c_int, [C.POINTER(sph_params), C.POINTER(sph_buffer_desc), C.c_int32,
+                             C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "sph_destroy": (C.c_int, [C.c_void_p]),
+    "sph_last_error": (C.c_char_p, [C.c_void_p]),
+    "sph_set_particles": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(sph_particles)]),
+    "sph_get_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sph_get_particles": (C.c_int, [C.c_void_p, C.POINTER(sph_particles)]),
+    "sph_set_clock": (C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
+    "sph_build_cells": (C.c_int, [C.c_void_p]),
+    "sph_correction": (C.c_int, [C.c_void_p]),
+    "sph_step": (C.c_int, [C.c_void_p, C.POINTER(sph_step_ctrl), C.POINTER(sph_step_info)]),
+    "sph_buffer_update": (C.c_int, [C.c_void_p, C.POINTER(sph_buffer_counts)]),
+    "sph_buffer_decisions": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sph_eval_rates": (C.c_int, [C.c_void_p, C.POINTER(sph_rates)]),
+    "sph_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.POINTER(C.c_int64)]),
+    "sph_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sph_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sph_kernel_stats)]),
+    "sph_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libsphx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+def _check(ctx, st):
+    if st != SPH_OK:
+        msg = lib().sph_last_error(ctx)
+        raise SphError(st, msg.decode() if msg else "")
+
+
+def sph_workspace_size(params, bufs, nbuf):
+    return lib().sph_workspace_size(C.byref(params), bufs, nbuf)
+
+
+def sph_create(params, bufs, nbuf, ws_ptr, ws_bytes, stream_ptr):
+    out = C.c_void_p()
+    st = lib().sph_create(C.byref(params), bufs, nbuf, C.c_void_p(ws_ptr), ws_bytes,
+                          C.c_void_p(stream_ptr), C.byref(out))
+    if st != SPH_OK:
+        raise SphError(st, "sph_create failed (invalid parameters, buffers or workspace)")
+    return out
+
+
+def sph_destroy(ctx):
+    _check(ctx, lib().sph_destroy(ctx))
+
+
+def sph_set_particles(ctx, n, next_pid, parts):
+    _check(ctx, lib().sph_set_particles(ctx, n, next_pid, C.byref(parts)))
+
+
+def sph_get_count(ctx):
+    a, b = C.c_int64(), C.c_int64()
+    _check(ctx, lib().sph_get_count(ctx, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def sph_get_particles(ctx, parts):
+    _check(ctx, lib().sph_get_particles(ctx, C.byref(parts)))
+
+
+def sph_set_clock(ctx, step, t):
+    _check(ctx, lib().sph_set_clock(ctx, step, t))
+
+
+def sph_build_cells(ctx):
+    _check(ctx, lib().sph_build_cells(ctx))
+
+
+def sph_correction(ctx):
+    _check(ctx, lib().sph_correction(ctx))
+
+
+def sph_step(ctx, ctrl=None):
+    info = sph_step_info()
+    st = lib().sph_step(ctx, C.byref(ctrl) if ctrl is not None else None, C.byref(info))
+    _check(ctx, st)
+    return info
+
+
+def sph_buffer_update(ctx):
+    cnt = sph_buffer_counts()
+    _check(ctx, lib().sph_buffer_update(ctx, C.byref(cnt)))
+    return cnt
+
+
+def sph_buffer_decisions(ctx, dec_ptr):
+    _check(ctx, lib().sph_buffer_decisions(ctx, C.c_void_p(dec_ptr)))
+
+
+def sph_eval_rates(ctx, rates):
+    _check(ctx, lib().sph_eval_rates(ctx, C.byref(rates)))
+
+
+def sph_neighbors(ctx, row_ptr, col_ptr, cap):
+    n = C.c_int64()
+    _check(ctx, lib().sph_neighbors(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
+                                    C.byref(n)))
+    return n.value
+
+
+def sph_profile_enable(ctx, on):
+    _check(ctx, lib().sph_profile_enable(ctx, int(on)))
+
+
+def sph_profile_read(ctx, kernel):
+    s = sph_kernel_stats()
+    _check(ctx, lib().sph_profile_read(ctx, kernel, C.byref(s)))
+    return s
+
+
+def sph_pair_count(ctx):
+    n = C.c_int64()
+    _check(ctx, lib().sph_pair_count(ctx, C.byref(n)))
+    return n.value
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def make_params(p: dict, precision: int, capacity: int) -> sph_params:
+    P = sph_params()
+    P.dim, P.precision = int(p["dim"]), int(precision)
+    P.turbulence, P.obc_mode = int(p["turbulence"]), int(p["obc_mode"])
+    for name in ("dp", "h", "rho0", "c0", "nu_l", "eta", "C1", "C2", "Cmu", "sigma_k",
+                 "sigma_eps", "k_floor", "eps_floor", "cfl_adv", "cfl_ac", "u_ref",
+                 "cell_size"):
+        setattr(P, name, float(p[name]))
+    for k in range(3):
+        P.g[k], P.lo[k], P.hi[k] = p["g"][k], p["lo"][k], p["hi"][k]
+    P.capacity = int(capacity)
+    P.seed = int(p["seed"])
+    return P
+
+
+def make_buffers(bufs):
+    arr = (sph_buffer_desc * max(1, len(bufs)))()
+    for q, b in enumerate(bufs):
+        d = arr[q]
+        d.id, d.vel_mode, d.p_mode, d.turb_mode = b.id, b.vel_mode, b.p_mode, b.turb_mode
+        d.profile, d.n_coef = b.profile, len(b.coef)
+        for k in range(3):
+            d.origin[k] = b.origin[k]
+            for c in range(3):
+                d.frame[3 * k + c] = b.frame[k][c]
+        d.length = b.length
+        d.half_width[0], d.half_width[1] = b.half_width
+        d.fringe, d.p_ob, d.k_bc, d.eps_bc = b.fringe, b.p_ob, b.k_bc, b.eps_bc
+        d.u0, d.noise_amp, d.ramp_time = b.u0, b.noise_amp, b.ramp_time
+        for m, a in enumerate(b.coef):
+            d.coef[m] = a
+    return arr
+
+
+class Simulation:
+    """One context on the current torch device and stream.
+
+    ``case`` supplies ``params`` (dict), ``buffers`` and the particle arrays
+    (x, v [n][3], rho, k, eps, tag, pid).  State is exchanged as FP64 numpy
+    arrays ordered like the library's current (cell-sorted) order.
+    """
+
+    def __init__(self, case, precision=SPH_FP32_MIXED, capacity=None, device=None,
+                 params=None, buffers=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the SPH library needs a GPU (torch.cuda is not available)")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.case = case
+        self.pdict = dict(case.params if params is None else params)
+        self.bufs = list(case.buffers if buffers is None else buffers)
+        self.capacity = case.capacity() if capacity is None else int(capacity)
+        self.precision = precision
+        self.P = make_params(self.pdict, precision, self.capacity)
+        self.B = make_buffers(self.bufs)
+        self.nbuf = len(self.bufs)
+        nbytes = sph_workspace_size(self.P, self.B, self.nbuf)
+        if nbytes == 0:
+            raise SphError(SPH_E_ARG, "invalid parameters or buffers")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self.ws_ptr = (base + 255) & ~255
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ctx = sph_create(self.P, self.B, self.nbuf, self.ws_ptr, nbytes,
+                                  self.stream.cuda_stream)
+        self.load(case.x, case.v, case.rho, case.k, case.eps, case.tag, case.pid,
+                  case.next_pid, drho=getattr(case, "drho", None),
+                  step=int(getattr(case, "step", 0)), t=float(getattr(case, "t", 0.0)))
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                lib().sph_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # -- state exchange -----------------------------------------------------
+    def _dev(self, a, dtype):
+        t = self.torch.as_tensor(np.ascontiguousarray(a), dtype=dtype)
+        return t.to(self.device)
+
+    def load(self, x, v, rho, k, eps, tag, pid, next_pid, drho=None, step=0, t=0.0):
+        torch = self.torch
+        n = int(np.asarray(x).shape[0])
+        f64 = torch.float64
+        self._in = dict(
+            x=self._dev(np.asarray(x, dtype=np.float64).T.copy(), f64),
+            v=self._dev(np.asarray(v, dtype=np.float64).T.copy(), f64),
+            rho=self._dev(np.asarray(rho, dtype=np.float64), f64),
+            drho=self._dev(np.zeros(n) if drho is None else np.asarray(drho, np.float64), f64),
+            k=self._dev(np.asarray(k, dtype=np.float64), f64),
+            eps=self._dev(np.asarray(eps, dtype=np.float64), f64),
+            tag=self._dev(np.asarray(tag, dtype=np.uint32).view(np.int32), torch.int32),
+            pid=self._dev(np.asarray(pid, dtype=np.uint32).view(np.int32), torch.int32))
+        parts = sph_particles(*[self._in[f].data_ptr() for f in
+                                ("x", "v", "rho", "drho", "k", "eps", "tag", "pid")])
+        sph_set_particles(self.ctx, n, int(next_pid), parts)
+        sph_set_clock(self.ctx, int(step), float(t))
+        self._in = None
+
+    def state(self):
+        torch = self.torch
+        n, _ = sph_get_count(self.ctx)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        out = dict(x=torch.zeros(3, max(n, 1), **f64), v=torch.zeros(3, max(n, 1), **f64),
+                   rho=torch.zeros(max(n, 1), **f64), drho=torch.zeros(max(n, 1), **f64),
+                   k=torch.zeros(max(n, 1), **f64), eps=torch.zeros(max(n, 1), **f64),
+                   tag=torch.zeros(max(n, 1), dtype=torch.int32, device=self.device),
+                   pid=torch.zeros(max(n, 1), dtype=torch.int32, device=self.device))
+        parts = sph_particles(*[out[f].data_ptr() for f in
+                                ("x", "v", "rho", "drho", "k", "eps", "tag", "pid")])
+        sph_get_particles(self.ctx, parts)
+        res = {}
+        for f, t in out.items():
+            a = t.cpu().numpy()
+            if f in ("x", "v"):
+                a = a[:, :n].T.copy()
+            else:
+                a = a[:n].copy()
+            if f in ("tag", "pid"):
+                a = a.view(np.uint32)
+            res[f] = a
+        return res
+
+    @property
+    def n(self):
+        return sph_get_count(self.ctx)[0]
+
+    # -- pipeline -------------------------------------------------------------
+    def build_cells(self):
+        sph_build_cells(self.ctx)
+
+    def correction(self):
+        sph_correction(self.ctx)
+
+    def step(self, dt_adv=0.0, n_ac=0):
+        ctrl = None
+        if dt_adv > 0:
+            ctrl = sph_step_ctrl(float(dt_adv), int(n_ac), 0)
+        return sph_step(self.ctx, ctrl)
+
+    def buffer_update(self):
+        return sph_buffer_update(self.ctx)
+
+    def advance(self, dt_adv=0.0, n_ac=0):
+        """build cells, correction, one advection step, buffer update."""
+        self.build_cells()
+        self.correction()
+        info = self.step(dt_adv, n_ac)
+        cnt = self.buffer_update()
+        return info, cnt
+
+    def decisions(self):
+        torch = self.torch
+        n = self.n
+        d = torch.zeros(max(n, 1), dtype=torch.int32, device=self.device)
+        sph_buffer_decisions(self.ctx, d.data_ptr())
+        return d.cpu().numpy()[:n].view(np.uint32)
+
+    def rates(self):
+        torch = self.torch
+        n = self.n
+        f64 = dict(dtype=torch.float64, device=self.device)
+        out = dict(ap=torch.zeros(3, n, **f64), drho=torch.zeros(n, **f64),
+                   anu=torch.zeros(3, n, **f64), gradv=torch.zeros(9, n, **f64),
+                   dk=torch.zeros(n, **f64), deps=torch.zeros(n, **f64),
+                   B=torch.zeros(9, n, **f64), p=torch.zeros(n, **f64))
+        turb = bool(self.pdict["turbulence"])
+        ptr = lambda f: out[f].data_ptr() if (turb or f not in ("gradv", "dk", "deps")) else None
+        R = sph_rates(*[ptr(f) for f in ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p")])
+        sph_eval_rates(self.ctx, R)
+        self.stream.synchronize()
+        res = {f: t.cpu().numpy() for f, t in out.items()}
+        for f in ("ap", "anu", "gradv", "B"):
+            res[f] = res[f].T.copy()
+        return res
+
+    def neighbors(self):
+        torch = self.torch
+        n = self.n
+        row = torch.zeros(n + 1, dtype=torch.int32, device=self.device)
+        cap = max(64, n * (160 if self.pdict["dim"] == 3 else 48))
+        col = torch.zeros(cap, dtype=torch.int32, device=self.device)
+        m = sph_neighbors(self.ctx, row.data_ptr(), col.data_ptr(), cap)
+        return row.cpu().numpy(), col.cpu().numpy()[:m]
+
+    def profile(self, on=True):
+        sph_profile_enable(self.ctx, on)
+
+    def kernel_stats(self):
+        return {KERNEL_NAMES[k]: sph_profile_read(self.ctx, k) for k in range(7)}
+
+    def pair_count(self):
+        return sph_pair_count(self.ctx)

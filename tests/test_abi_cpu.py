@@ -1,0 +1,71 @@
+"""Host-side checks of the C-ABI library (no GPU compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import cases
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph.h")
+
+
+@pytest.fixture(scope="module")
+def sphmod():
+    from paper_2510_25702_amd import build, sph
+    if not os.path.exists(sph.LIB_PATH):
+        build.build()
+    return sph
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function(sphmod):
+    names = declared_functions()
+    assert len(names) >= 18
+    L = C.CDLL(sphmod.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert set(names) == set(sphmod.EXPORTS)
+
+
+def _params(sphmod, case, **over):
+    P = sphmod.make_params(case.params, sphmod.SPH_FP32_MIXED, case.capacity())
+    for k, v in over.items():
+        setattr(P, k, v)
+    return P
+
+
+def test_workspace_size_validates_parameters(sphmod):
+    c = cases.make_channel()
+    B = sphmod.make_buffers(c.buffers)
+    good = sphmod.sph_workspace_size(_params(sphmod, c), B, len(c.buffers))
+    assert good > 100 * c.capacity()
+    for bad in (dict(dim=4), dict(obc_mode=0), dict(h=-1.0), dict(cell_size=0.01),
+                dict(capacity=0), dict(precision=7)):
+        assert sphmod.sph_workspace_size(_params(sphmod, c, **bad), B, len(c.buffers)) == 0
+    # buffers: ids must be unique, ascending and 1..255
+    B2 = sphmod.make_buffers(c.buffers)
+    B2[1].id = B2[0].id
+    assert sphmod.sph_workspace_size(_params(sphmod, c), B2, 2) == 0
+    # FP64 needs more space than FP32-mixed
+    P64 = _params(sphmod, c, precision=sphmod.SPH_FP64)
+    assert sphmod.sph_workspace_size(P64, B, 2) > good
+
+
+def test_create_rejects_bad_workspace_without_touching_the_gpu(sphmod):
+    c = cases.make_channel()
+    P = _params(sphmod, c)
+    B = sphmod.make_buffers(c.buffers)
+    out = C.c_void_p()
+    L = sphmod.lib()
+    assert L.sph_create(C.byref(P), B, 2, None, 0, None, C.byref(out)) == sphmod.SPH_E_ARG
+    assert L.sph_create(C.byref(P), B, 2, C.c_void_p(257), 1 << 40, None,
+                        C.byref(out)) == sphmod.SPH_E_ARG
+    assert L.sph_destroy(None) == sphmod.SPH_E_ARG
+    assert L.sph_last_error(None)

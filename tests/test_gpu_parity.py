@@ -1,0 +1,416 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (from the method's statement of the target):
+  * neighbour sets and buffer decisions: bit-exact, compared by particle id;
+  * FP64 path: correction matrix and pair-operator outputs within 1e-12 of
+    the oracle (normwise, max_i |dF_i| / max_i |F_i|);
+  * FP32-mixed path: within 1e-5 on the same measure;
+  * steady Poiseuille flow within 2 % (L2) of the analytic profile.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import cases
+from tests.helpers import block_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU in this environment")
+    from paper_2510_25702_amd import sph as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ora():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+PREC = [("fp64", 0, 1e-12), ("fp32", 1, 1e-5)]
+
+
+def from_oracle(case, sim):
+    """Case whose particle arrays, counters and clock are the oracle's."""
+    s = sim.snapshot()
+    return dataclasses.replace(case, x=s["x"], v=s["v"], rho=s["rho"], k=s["k"],
+                               eps=s["eps"], tag=s["tag"], pid=s["pid"],
+                               drho=s["drho"], npid=int(sim.S.next_pid),
+                               step=int(sim.S.step), t=float(sim.S.t))
+
+
+def gpu_sim(sph, case, prec, capacity=None):
+    return sph.Simulation(case, precision=prec, capacity=capacity)
+
+
+def pid_index(pid):
+    return {int(p): i for i, p in enumerate(pid)}
+
+
+def normwise(a, b):
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / scale) if scale > 0 else float(np.abs(a).max())
+
+
+def relabelled(ora, case):
+    s = ora.OracleSim(case, threads=8)
+    s.buffer_update()
+    return from_oracle(case, s)
+
+
+def small_jet():
+    return cases.make_jet(dp=0.2, L=12.0, W=4.0)
+
+
+def small_mixer():
+    return cases.make_mixer(dp=0.025)
+
+
+CASES = {
+    "channel": lambda: cases.make_channel(L=3.0),
+    "jet": small_jet,
+    "mixer3d": small_mixer,
+    "mixer3d_coarse": lambda: cases.make_mixer(dp=0.04),
+}
+
+
+# --------------------------------------------------------------------------
+# neighbour lists (FP64 predicate): bit-exact
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["channel", "jet", "mixer3d_coarse"])
+@pytest.mark.parametrize("jit", [0.0, 0.4])
+def test_neighbor_sets_bit_exact(sph, ora, name, jit):
+    c = CASES[name]()
+    if jit:
+        c = cases.jittered(c, jit, seed=21)
+    g = gpu_sim(sph, c, sph.SPH_FP64)
+    g.build_cells()
+    row, col = g.neighbors()
+    gp = g.state()["pid"].astype(np.int64)
+    rows = np.repeat(np.arange(len(gp)), np.diff(row))
+    gpu_pairs = np.sort((gp[rows] << 32) | gp[col.astype(np.int64)])
+    off, idx = ora.neighbors(c.params, c.x)
+    op = c.pid.astype(np.int64)
+    orows = np.repeat(np.arange(c.n), np.diff(off))
+    ora_pairs = np.sort((op[orows] << 32) | op[idx])
+    assert len(ora_pairs) > 10 * c.n
+    assert np.array_equal(gpu_pairs, ora_pairs)
+
+
+# --------------------------------------------------------------------------
+# correction matrix with the mirror treatment
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["channel", "jet", "mixer3d"])
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_correction_matrix(sph, ora, name, pname, prec, tol):
+    c = relabelled(ora, cases.jittered(CASES[name](), 0.2, seed=3))
+    ref = ora.OracleSim(c, threads=8)
+    Bo, _ = ref.correction()
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    r = g.rates()
+    st = g.state()
+    gi = pid_index(st["pid"])
+    idx = np.array([gi[int(p)] for p in c.pid])
+    real = (c.tag & 3) != 2
+    Bg = r["B"][idx][real]
+    assert normwise(Bg, Bo[real]) < tol
+
+
+# --------------------------------------------------------------------------
+# pair operators on perturbed states
+# --------------------------------------------------------------------------
+def perturbed(name, turbulence=None, mode=None):
+    c = cases.perturbed_state(CASES[name](), seed=5)
+    if turbulence is not None:
+        c.params["turbulence"] = turbulence
+        c.k[:] = np.where((c.tag & 3) != 2, 1e-3 * (1 + 0.3 * np.sin(c.x[:, 0])), 0.0)
+        c.eps[:] = np.where((c.tag & 3) != 2, 1e-3 * (1 + 0.3 * np.cos(c.x[:, 1])), 0.0)
+    if mode is not None:
+        c.params["obc_mode"] = mode
+    return c
+
+
+RATE_CASES = [("channel", None, None), ("channel", None, 1), ("channel", None, 2),
+              ("channel", 1, None), ("jet", None, None), ("mixer3d", None, None),
+              ("mixer3d", 1, 3)]
+
+
+@pytest.mark.parametrize("name,turb,mode", RATE_CASES)
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_pair_operators(sph, ora, name, turb, mode, pname, prec, tol):
+    c = relabelled(ora, perturbed(name, turb, mode))
+    ref = ora.OracleSim(c, threads=8)
+    ro = ref.rates()
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    rg = g.rates()
+    gi = pid_index(g.state()["pid"])
+    idx = np.array([gi[int(p)] for p in c.pid])
+    real = (c.tag & 3) != 2
+    fields = ["ap", "drho", "anu", "p"]
+    if c.params["turbulence"]:
+        fields += ["gradv", "dk", "deps"]
+    errs = {f: normwise(rg[f][idx][real], ro[f][real]) for f in fields}
+    assert max(errs.values()) < tol, errs
+
+
+@pytest.mark.parametrize("name", ["uchannel", "jet_full"])
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_pair_operators_full_size(sph, ora, name, pname, prec, tol):
+    # the benchmark's workload sizes, in the launch configuration it times
+    c = cases.make_uchannel() if name == "uchannel" else cases.make_jet()
+    c = relabelled(ora, cases.perturbed_state(c, seed=9))
+    ref = ora.OracleSim(c, threads=16)
+    ro = ref.rates()
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    rg = g.rates()
+    gi = pid_index(g.state()["pid"])
+    idx = np.array([gi[int(p)] for p in c.pid])
+    real = (c.tag & 3) != 2
+    fields = ["ap", "drho", "anu", "B"] + (["gradv", "dk", "deps"] if c.params["turbulence"] else [])
+    errs = {f: normwise(rg[f][idx][real], ro[f][real]) for f in fields}
+    assert max(errs.values()) < tol, errs
+
+
+# --------------------------------------------------------------------------
+# buffer decisions and update: bit-exact by particle id
+# --------------------------------------------------------------------------
+def running_state(ora, make, nsteps, seed):
+    c = make()
+    s = ora.OracleSim(c, threads=8)
+    s.buffer_update()
+    for _ in range(nsteps):
+        s.step()
+        s.buffer_update()
+    s.step()          # leave the decisions of this step pending
+    c2 = from_oracle(c, s)
+    # shake the positions a little so that every predicate fires somewhere
+    rng = np.random.default_rng(seed)
+    fl = (c2.tag & 3) != 2
+    c2.x = c2.x.copy()
+    dim = c.params["dim"]
+    c2.x[fl, :dim] += 0.6 * c.params["dp"] * rng.uniform(-1, 1, (fl.sum(), dim))
+    return c2
+
+
+DEC_CASES = {
+    "channel": lambda ora: running_state(ora, lambda: cases.make_channel(L=3.0, ramp_time=0.5), 80, 1),
+    "uchannel": lambda ora: running_state(ora, lambda: cases.make_uchannel(dp=0.05, Lleg=3.0), 60, 2),
+    "jet": lambda ora: running_state(ora, small_jet, 30, 3),
+    "mixer3d": lambda ora: running_state(ora, small_mixer, 10, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(DEC_CASES))
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_buffer_decisions_and_update_bit_exact(sph, ora, name, pname, prec, tol):
+    c = DEC_CASES[name](ora)
+    ref = ora.OracleSim(c, threads=8)
+    dec_o = ref.decisions()
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    dec_g = g.decisions()
+    st = g.state()
+    go = {int(p): int(d) for p, d in zip(st["pid"], dec_g)}
+    oo = {int(p): int(d) for p, d in zip(c.pid, dec_o)}
+    assert go == oo
+    acts = {d & 0xFF for d in oo.values()} - {0}
+    assert len(acts) >= 2, acts
+    # apply: same particle set, same tags, bit-identical recycled positions
+    cnt_o = ref.buffer_update()
+    cnt_g = g.buffer_update()
+    for f in ("n_relabel", "n_inject", "n_delete", "n_revert"):
+        assert list(getattr(cnt_o, f)) == list(getattr(cnt_g, f))
+    so, sg = ref.snapshot(), g.state()
+    alive = (sg["tag"] & 3) != 3
+    gi = {int(p): i for i, p in enumerate(sg["pid"]) if alive[i]}
+    assert sorted(gi) == sorted(int(p) for p in so["pid"])
+    idx = np.array([gi[int(p)] for p in so["pid"]])
+    assert np.array_equal(sg["tag"][idx], so["tag"])
+    assert np.array_equal(sg["x"][idx], so["x"])
+    assert np.array_equal(sg["rho"][idx], so["rho"])
+    if prec == sph.SPH_FP64:   # recycled velocities go through sin / cos
+        assert np.abs(sg["v"][idx] - so["v"]).max() <= 1e-14 * max(1.0, np.abs(so["v"]).max())
+    else:
+        assert np.abs(sg["v"][idx] - so["v"]).max() <= 1e-6 * max(1.0, np.abs(so["v"]).max())
+
+
+def test_crafted_decisions_bit_exact(sph, ora):
+    from tests.test_oracle_buffer import crafted, inlet
+    from cases import BUFFER, FLUID, make_tag
+    b1 = inlet(1, origin=(0.0, 0.25), hw=0.25)
+    b2 = inlet(2, origin=(0.0, 0.75), hw=0.25)
+    b3 = cases.Buffer(3, (1.0, 0.5, 0.0), cases._frame2(1.0, 0.0), 0.2, (0.5, 0.0), 0.025)
+    L, gen = b1.length, b1.length + b1.fringe
+    up = lambda a: float(np.nextafter(a, np.inf))
+    dn = lambda a: float(np.nextafter(a, -np.inf))
+    pts, tags = [], []
+    F, B1, B2, B3 = make_tag(FLUID), make_tag(BUFFER, 1), make_tag(BUFFER, 2), make_tag(BUFFER, 3)
+    for y in (0.1, 0.25, 0.5, 0.6, dn(0.5), up(0.5), 1.0, 1.0 + 1e-9):
+        for x in (dn(0.0), 0.0, 0.1, L, up(L), dn(gen), gen, 0.5, 0.95, 1.0, 1.1):
+            for t in (F, B1, B2, B3):
+                pts.append((x, y))
+                tags.append(t)
+    c = crafted(pts, tags, [b1, b2, b3])
+    ref = ora.OracleSim(c)
+    dec_o = ref.decisions()
+    g = gpu_sim(sph, c, sph.SPH_FP64)
+    g.build_cells()
+    dec_g = g.decisions()
+    go = {int(p): int(d) for p, d in zip(g.state()["pid"], dec_g)}
+    oo = {int(p): int(d) for p, d in zip(c.pid, dec_o)}
+    assert go == oo
+    assert len({d & 0xFF for d in oo.values()}) == 6
+
+
+# --------------------------------------------------------------------------
+# whole advection steps
+# --------------------------------------------------------------------------
+def developing_channel(ora, nsteps=20):
+    c = cases.make_channel(L=3.0, ramp_time=0.5)
+    s = ora.OracleSim(c, threads=8)
+    s.buffer_update()
+    for _ in range(nsteps):
+        s.step()
+        s.buffer_update()
+    return from_oracle(c, s)
+
+
+@pytest.mark.parametrize("pname,prec,tol", [("fp64", 0, 1e-10), ("fp32", 1, 2e-5)])
+def test_one_step_matches_oracle(sph, ora, pname, prec, tol):
+    c = developing_channel(ora)
+    ref = ora.OracleSim(c, threads=8)
+    g = gpu_sim(sph, c, prec)
+    Io = ref.step()
+    g.build_cells()
+    g.correction()
+    Ig = g.step()
+    assert Ig.n_ac == Io.n_ac
+    assert abs(Ig.dt_adv - Io.dt_adv) <= (1e-14 if prec == sph.SPH_FP64 else 1e-6) * Io.dt_adv
+    so, sg = ref.snapshot(), g.state()
+    gi = pid_index(sg["pid"])
+    idx = np.array([gi[int(p)] for p in so["pid"]])
+    vmax = np.abs(so["v"]).max()
+    assert np.abs(sg["v"][idx] - so["v"]).max() < tol * vmax
+    assert np.abs(sg["x"][idx] - so["x"]).max() < tol * c.params["dp"]
+    assert np.abs(sg["rho"][idx] - so["rho"]).max() < tol
+
+
+def test_determinism(sph, ora):
+    c = relabelled(ora, cases.make_channel(L=3.0, ramp_time=0.5))
+    out = []
+    for _ in range(2):
+        g = gpu_sim(sph, c, sph.SPH_FP32_MIXED)
+        for _ in range(30):
+            g.advance()
+        g.build_cells()
+        out.append(g.state())
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f]), f
+
+
+def test_capacity_error_leaves_state_unchanged(sph, ora):
+    from tests.test_oracle_buffer import crafted, inlet
+    from cases import BUFFER, make_tag
+    b = inlet(1)
+    gen = b.length + b.fringe
+    pts = [(gen + 0.01, 0.2 + 0.1 * k) for k in range(5)]
+    c = crafted(pts, [make_tag(BUFFER, 1)] * 5, [b])
+    g = gpu_sim(sph, c, sph.SPH_FP64, capacity=7)
+    g.build_cells()
+    before = g.state()
+    with pytest.raises(sph.SphError) as e:
+        g.buffer_update()
+    assert e.value.status == sph.SPH_E_CAPACITY
+    after = g.state()
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    # the context stays usable: a larger capacity accepts the same update
+    g2 = gpu_sim(sph, c, sph.SPH_FP64, capacity=16)
+    g2.build_cells()
+    cnt = g2.buffer_update()
+    assert cnt.n_inject[1] == 5
+
+
+def test_empty_and_tiny_domains(sph):
+    c = block_case(dim=2, n_side=1)
+    g = sph.Simulation(c, precision=sph.SPH_FP32_MIXED)
+    g.load(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0),
+           np.zeros(0, np.uint32), np.zeros(0, np.uint32), 0)
+    info, cnt = g.advance()
+    assert g.n == 0 and info.n_ac >= 1
+    # one isolated particle: guarded correction (B = I), no neighbours
+    c1 = block_case(dim=3, n_side=1)
+    g1 = sph.Simulation(c1, precision=sph.SPH_FP64)
+    g1.build_cells()
+    g1.correction()
+    r = g1.rates()
+    assert np.allclose(r["B"][0], np.eye(3).ravel())
+    assert np.all(r["ap"] == 0.0)
+
+
+def test_state_errors(sph):
+    c = cases.make_channel(L=2.0)
+    g = sph.Simulation(c)
+    with pytest.raises(sph.SphError) as e:
+        g.step()
+    assert e.value.status == sph.SPH_E_STATE
+    g.build_cells()
+    with pytest.raises(sph.SphError):
+        g.step()                 # correction missing
+    g.correction()
+    g.step()
+    with pytest.raises(sph.SphError):
+        g.correction()           # positions moved since the cell build
+
+
+# --------------------------------------------------------------------------
+# steady Poiseuille flow and buffer balance on the GPU, both precisions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_poiseuille_gpu(sph, prec):
+    L, dp, nsteps, navg = 4.0, 0.05, 3000, 600
+    c = cases.make_channel(L=L, dp=dp)
+    g = sph.Simulation(c, precision=prec)
+    g.build_cells()
+    g.buffer_update()
+    nb = int(round(1.0 / dp))
+    acc = np.zeros(nb)
+    cnt = np.zeros(nb)
+    inj = dele = 0
+    for k in range(nsteps):
+        _, cn = g.advance()
+        if k < nsteps - navg:
+            continue
+        inj += cn.n_inject[1] + cn.n_inject[2]
+        dele += cn.n_delete[1] + cn.n_delete[2]
+        if k % 5:
+            continue
+        st = g.state()
+        x, v, tag = st["x"], st["v"], st["tag"]
+        fl = ((tag & 3) == 0) | ((tag & 3) == 1)
+        sel = fl & (x[:, 0] > 0.4 * L) & (x[:, 0] < 0.8 * L)
+        b = np.clip((x[sel, 1] / dp).astype(int), 0, nb - 1)
+        np.add.at(acc, b, v[sel, 0])
+        np.add.at(cnt, b, 1)
+    u = acc / cnt
+    y = (np.arange(nb) + 0.5) * dp
+    ua = 4.0 * y * (1.0 - y)
+    l2 = np.sqrt(np.mean((u - ua) ** 2)) / np.sqrt(np.mean(ua ** 2))
+    assert l2 < 0.02
+    assert inj > 100 and abs(inj - dele) <= max(5, 0.02 * inj)
