@@ -109,7 +109,7 @@ def base_params(dim, dp, rho0=1.0, c0=10.0, nu_l=1e-3, u_ref=1.0,
     p = dict(dim=dim, turbulence=turbulence, obc_mode=obc_mode, dp=dp, h=h,
              rho0=rho0, c0=c0, nu_l=nu_l, eta=3.0, g=(0.0, 0.0, 0.0),
              k_floor=1e-10, eps_floor=1e-10, cfl_adv=0.25, cfl_ac=0.6,
-             u_ref=u_ref, cell_size=2.5 * h, lo=(0.0, 0.0, 0.0),
+             u_ref=u_ref, cell_size=2.6 * h, lo=(0.0, 0.0, 0.0),
              hi=(0.0, 0.0, 0.0), seed=seed)
     p.update(KEPS)
     return p
