@@ -160,17 +160,17 @@ __global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t*
   perm[cell_start[k] + slot[i]] = i;
 }
 
-// K3b: deterministic order inside every cell (ascending particle id).
+// K3b: deterministic order inside every cell: ascending source index, i.e.
+// the (deterministic) order of the previous layout, new particles last.
 __global__ void k_sort_cells(int ncell, const int32_t* __restrict__ cell_start,
-                             int32_t* __restrict__ perm, const uint32_t* __restrict__ pid) {
+                             int32_t* __restrict__ perm) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   int b = cell_start[c], e = cell_start[c + 1];
   for (int a = b + 1; a < e; ++a) {
     int ia = perm[a];
-    uint32_t pa = pid[ia];
     int q = a - 1;
-    while (q >= b && pid[perm[q]] > pa) {
+    while (q >= b && perm[q] > ia) {
       perm[q + 1] = perm[q];
       --q;
     }
@@ -263,7 +263,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   if (n_in > 0) {
     k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>((int)n_in, S.key, S.slot,
                                                           S.cell_start, S.perm);
-    k_sort_cells<<<(nc + 255) / 256, 256, 0, st>>>(nc, S.cell_start, S.perm, F.pid.live());
+    k_sort_cells<<<(nc + 255) / 256, 256, 0, st>>>(nc, S.cell_start, S.perm);
   }
   GatherArgs<T, DIM> a;
   a.perm = S.perm;

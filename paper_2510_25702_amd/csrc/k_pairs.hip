@@ -30,19 +30,42 @@ struct PairCtx {
   long long* pairs;   // directed pairs counter (NULL: not counted)
 };
 
+// Sum over the L lanes of a team (butterfly: the same order in every run).
+template <int L, typename T>
+__device__ __forceinline__ T team_sum(T v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Directed-pair counter: one atomic per block, spread over kPairShards
+// counters 128 bytes apart, so the passes do not serialise on one address.
+// Every thread of the block must reach this call.
 __device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
   if (!ctr) return;
+  __shared__ long long part[16];
   m = wave_sum_ll(m);
-  if ((threadIdx.x & (kWave - 1)) == 0 && m)
-    atomicAdd(reinterpret_cast<unsigned long long*>(ctr), (unsigned long long)m);
+  const int nw = blockDim.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < nw; ++w) s += part[w];
+    if (s)
+      atomicAdd(reinterpret_cast<unsigned long long*>(ctr + (blockIdx.x & (kPairShards - 1)) *
+                                                               kPairShardStride),
+                (unsigned long long)s);
+  }
 }
 
 // Visit every j != i with |r_ij|^2 < (2h)^2 among the particles of the
 // 3^DIM build cells around i's cell; r = x_i - x_j from cell-relative
 // positions: r = (xr_i - xr_j) - (cell_j - cell_i) * cs.
-template <typename T, int DIM, typename Fn>
-__device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, const T xi[3],
-                                              Fn&& fn) {
+// A team of L consecutive lanes shares particle i: lane l visits the
+// candidates l, l + L, l + 2L, ... of every row.
+template <typename T, int DIM, int L, typename Fn>
+__device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int lane,
+                                              const T xi[3], Fn&& fn) {
   const int c = pc.cell[i];
   const int cx = c % pc.nx;
   const int cyz = c / pc.nx;
@@ -57,7 +80,7 @@ __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, const
       const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
                 j3 = pc.cs[base + 2];
       const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
-      for (int j = j0; j < j3; ++j) {
+      for (int j = j0 + lane; j < j3; j += L) {
         const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
         T r[3];
         r[0] = (xi[0] - pc.xr[0][j]) + ox;
@@ -160,14 +183,17 @@ __device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
   for (int k = 0; k < 6; ++k) B[k] = w * inv[k] + (1.0 - w) * id[k];
 }
 
-template <typename T, int DIM>
-__device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const CorrArgs<T>& a) {
+template <typename T, int DIM, int L>
+__device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
+                                               const Consts<T>& C, const CorrArgs<T>& a) {
   if (i >= n) return 0;
   int m_pairs = 0;
   const uint32_t ti = pc.tag[i];
   if (!is_real(ti)) {
-    a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
-    if (DIM == 3) { a.B[2][i] = T(0); a.B[4][i] = T(0); a.B[5][i] = T(1); }
+    if (lane == 0) {
+      a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
+      if (DIM == 3) { a.B[2][i] = T(0); a.B[4][i] = T(0); a.B[5][i] = T(1); }
+    }
     return m_pairs;
   }
   const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
@@ -184,7 +210,7 @@ __device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& p
       A[5] -= Vf * r[2] * r[2];
     }
   };
-  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
     acc(r, r2, pc.vol[j]);
     ++m_pairs;
   });
@@ -213,7 +239,7 @@ __device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& p
         for (int dy = -1; dy <= 1; ++dy) {
           const int base = ((cm[2] + dz) * pc.ny + (cm[1] + dy)) * pc.nx + cm[0];
           const int j0 = pc.cs[base - 1], j3 = pc.cs[base + 2];
-          for (int j = j0; j < j3; ++j) {
+          for (int j = j0 + lane; j < j3; j += L) {
             if (!is_real(pc.tag[j])) continue;
             double yj[3];
             const double xj0 = a.x[0][j], xj1 = a.x[1][j], xj2 = a.x[2][j];
@@ -230,6 +256,9 @@ __device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& p
         }
     }
   }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) A[k] = team_sum<L>(A[k]);
+  if (lane != 0) return m_pairs;
   double Ad[6] = {(double)A[0], (double)A[1], (double)A[2],
                   (double)A[3], (double)A[4], (double)A[5]};
   double Bd[6];
@@ -245,10 +274,10 @@ __device__ __forceinline__ int correction_body(int i, int n, const PairCtx<T>& p
   return m_pairs;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int L>
 __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = correction_body<T, DIM>(i, n, pc, C, a);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = correction_body<T, DIM, L>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
 
@@ -278,13 +307,14 @@ struct AdvArgs {
   int64_t n_out;
 };
 
-template <typename T, int DIM, int TURB>
-__device__ __forceinline__ int advection_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const AdvArgs<T>& a) {
+template <typename T, int DIM, int TURB, int L>
+__device__ __forceinline__ int advection_body(int i, int lane, int n, const PairCtx<T>& pc,
+                                              const Consts<T>& C, const AdvArgs<T>& a) {
   if (i >= n) return 0;
   int m_pairs = 0;
   const uint32_t ti = pc.tag[i];
   if (!is_real(ti)) {
-    if (!a.rates_only) {
+    if (!a.rates_only && lane == 0) {
       for (int k = 0; k < 3; ++k) a.anu[k][i] = T(0);
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
@@ -308,7 +338,7 @@ __device__ __forceinline__ int advection_body(int i, int n, const PairCtx<T>& pc
     Dk_i = (T)C.nu_l + nut_i / (T)C.sigma_k;
     De_i = (T)C.nu_l + nut_i / (T)C.sigma_eps;
   }
-  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
     ++m_pairs;
     const T rr = sqrt(r2);
     const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
@@ -359,6 +389,15 @@ __device__ __forceinline__ int advection_body(int i, int n, const PairCtx<T>& pc
       }
     }
   });
+#pragma unroll
+  for (int k = 0; k < 3; ++k) av[k] = team_sum<L>(av[k]);
+  if (TURB) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] = team_sum<L>(G[k]);
+    dfk = team_sum<L>(dfk);
+    dfe = team_sum<L>(dfe);
+  }
+  if (lane != 0) return m_pairs;
   const double two_over_rho = 2.0 / rho_i;
   double anu_d[3] = {two_over_rho * (double)av[0], two_over_rho * (double)av[1],
                      two_over_rho * (double)av[2]};
@@ -412,10 +451,10 @@ __device__ __forceinline__ int advection_body(int i, int n, const PairCtx<T>& pc
   return m_pairs;
 }
 
-template <typename T, int DIM, int TURB>
+template <typename T, int DIM, int TURB, int L>
 __global__ __launch_bounds__(256) void k_advection(int n, PairCtx<T> pc, Consts<T> C, AdvArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = advection_body<T, DIM, TURB>(i, n, pc, C, a);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = advection_body<T, DIM, TURB, L>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
 
@@ -447,13 +486,14 @@ struct PressArgs {
   int64_t n_out;
 };
 
-template <typename T, int DIM, int MODE>
-__device__ __forceinline__ int pressure_body(int i, int n, const PairCtx<T>& pc, const Consts<T>& C, const PressArgs<T>& a) {
+template <typename T, int DIM, int MODE, int L>
+__device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairCtx<T>& pc,
+                                             const Consts<T>& C, const PressArgs<T>& a) {
   if (i >= n) return 0;
   int m_pairs = 0;
   const uint32_t ti = pc.tag[i];
   if (!is_real(ti)) {
-    if (!a.rates_only) {
+    if (!a.rates_only && lane == 0) {
       for (int k = 0; k < 3; ++k) {
         a.xo[k][i] = a.x[k][i];
         a.xro[k][i] = pc.xr[k][i];
@@ -466,7 +506,7 @@ __device__ __forceinline__ int pressure_body(int i, int n, const PairCtx<T>& pc,
   T Bi[6];
   if (MODE >= 2) load_B<T, DIM>(a.B, i, Bi);
   T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
-  for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
     ++m_pairs;
     const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
     const T Vj = pc.vol[j];
@@ -502,6 +542,12 @@ __device__ __forceinline__ int pressure_body(int i, int n, const PairCtx<T>& pc,
     s[1] += Vj * gW[1];
     s[2] += Vj * gW[2];
   });
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    acc[k] = team_sum<L>(acc[k]);
+    s[k] = team_sum<L>(s[k]);
+  }
+  if (lane != 0) return m_pairs;
   int q = -1;
   if (tag_kind(ti) == kBuffer) q = a.bidx[tag_bid(ti)];
   if (q >= 0 && a.bufs[q].p_mode != kPNone) {
@@ -553,10 +599,10 @@ __device__ __forceinline__ int pressure_body(int i, int n, const PairCtx<T>& pc,
   return m_pairs;
 }
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int L>
 __global__ __launch_bounds__(256) void k_pressure(int n, PairCtx<T> pc, Consts<T> C, PressArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = pressure_body<T, DIM, MODE>(i, n, pc, C, a);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = pressure_body<T, DIM, MODE, L>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
 
@@ -582,10 +628,11 @@ struct DensArgs {
   double* o_drho;
 };
 
-template <typename T, int DIM, int TURB>
+template <typename T, int DIM, int TURB, int L>
 __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T> C,
                                                  DensArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / L, lane = g % L;
   long long cnt = 0;
   if (i < n) {
     const uint32_t ti = pc.tag[i];
@@ -595,7 +642,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       const T pi = a.p[i];
       T sum = T(0);
       int m = 0;
-      for_neighbors<T, DIM>(pc, i, xi, [&](int j, const T r[3], T r2) {
+      for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
         const T rr = sqrt(r2);
         const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
         const bool wall = tag_kind(pc.tag[j]) == kWall;
@@ -612,21 +659,24 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
         ++m;
       });
       cnt = m;
-      const double rho_i = a.rho[i];
-      const double drho = 2.0 * rho_i * (double)sum;
-      if (a.rates_only) {
-        a.o_drho[i] = drho;
-      } else {
-        a.drho[i] = (T)drho;
-        double rho_n = rho_i + a.half_dt * drho;
-        if (!a.last) {
-          rho_n = rho_n + a.half_dt * drho;
-          a.p_out[i] = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
-          a.vol_out[i] = (T)(C.mass / rho_n);
+      sum = team_sum<L>(sum);
+      if (lane == 0) {
+        const double rho_i = a.rho[i];
+        const double drho = 2.0 * rho_i * (double)sum;
+        if (a.rates_only) {
+          a.o_drho[i] = drho;
+        } else {
+          a.drho[i] = (T)drho;
+          double rho_n = rho_i + a.half_dt * drho;
+          if (!a.last) {
+            rho_n = rho_n + a.half_dt * drho;
+            a.p_out[i] = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
+            a.vol_out[i] = (T)(C.mass / rho_n);
+          }
+          a.rho[i] = rho_n;
         }
-        a.rho[i] = rho_n;
       }
-    } else if (!a.rates_only && !a.last) {
+    } else if (!a.rates_only && !a.last && lane == 0) {
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
     }
@@ -829,6 +879,28 @@ PairCtx<T> make_pc(const sph_ctx* c, const sphx::Slot2<void>* xr, int xslot) {
 
 inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
 
+// Lanes per particle of the neighbour passes: enough wavefronts to hide the
+// latency of the candidate loads on 256 CUs at small particle counts, one
+// lane per particle once the grid alone fills the machine (measured on
+// MI355X: 2D, 57k particles: L = 8 takes 0.47x the time of L = 1; 640k
+// and 2.56M particles: L = 1 is fastest).
+inline int team_lanes(const sph_ctx* c) {
+  if (c->team_override > 0) return c->team_override;
+  const int64_t n = c->n_total;
+  if (n <= 120000) return 8;
+  if (n <= 260000) return 4;
+  if (n <= 450000) return 2;
+  return 1;
+}
+
+#define SPHX_TEAM_SWITCH(L, ...)                                   \
+  switch (L) {                                                     \
+    case 1: { constexpr int TL = 1; __VA_ARGS__; } break;          \
+    case 2: { constexpr int TL = 2; __VA_ARGS__; } break;          \
+    case 4: { constexpr int TL = 4; __VA_ARGS__; } break;          \
+    default: { constexpr int TL = 8; __VA_ARGS__; } break;         \
+  }
+
 template <typename T, int DIM>
 hipError_t correction_impl(sph_ctx* c) {
   Consts<T> C = make_consts<T>(c);
@@ -840,7 +912,8 @@ hipError_t correction_impl(sph_ctx* c) {
   a.flags = c->S.flags;
   a.mirror = c->P.obc_mode >= 3 ? 1 : 0;
   const int64_t n = c->n_total;
-  k_correction<T, DIM><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  const int L = team_lanes(c);
+  SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
   return hipGetLastError();
 }
 
@@ -878,10 +951,12 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   a.o_deps = out ? out->deps : nullptr;
   a.n_out = c->n_total;
   const int64_t n = c->n_total;
-  if (c->P.turbulence)
-    k_advection<T, DIM, 1><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
-  else
-    k_advection<T, DIM, 0><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  const int L = team_lanes(c);
+  if (c->P.turbulence) {
+    SPHX_TEAM_SWITCH(L, k_advection<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+  } else {
+    SPHX_TEAM_SWITCH(L, k_advection<T, DIM, 0, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+  }
   return hipGetLastError();
 }
 
@@ -913,12 +988,12 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
   if (rates_only) pc.pairs = nullptr;
   a.n_out = c->n_total;
   const int64_t n = c->n_total;
-  const int nb = nblk(n);
+  const int L = team_lanes(c);
   switch (c->P.obc_mode) {
-    case 1: k_pressure<T, DIM, 1><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
-    case 2: k_pressure<T, DIM, 2><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
-    case 3: k_pressure<T, DIM, 3><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
-    default: k_pressure<T, DIM, 4><<<nb, 256, 0, c->stream>>>((int)n, pc, C, a); break;
+    case 1: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
+    case 2: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 2, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
+    case 3: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 3, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
+    default: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 4, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
   }
   if (!rates_only)
     for (int k = 0; k < 3; ++k) {
@@ -948,10 +1023,12 @@ hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
   a.o_drho = out ? out->drho : nullptr;
   if (rates_only) pc.pairs = nullptr;
   const int64_t n = c->n_total;
-  if (c->P.turbulence)
-    k_density<T, DIM, 1><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
-  else
-    k_density<T, DIM, 0><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, C, a);
+  const int L = team_lanes(c);
+  if (c->P.turbulence) {
+    SPHX_TEAM_SWITCH(L, k_density<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+  } else {
+    SPHX_TEAM_SWITCH(L, k_density<T, DIM, 0, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+  }
   if (!rates_only && !last) {
     F.p.flip();
     F.vol.flip();

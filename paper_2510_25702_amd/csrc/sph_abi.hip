@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -205,7 +206,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_counters = L.take(1040 * 4);
   pl->off_flags = L.take(4);
   pl->off_red = L.take((C / 256 + 8) * 2 * 8 + 64);
-  pl->off_pairs = L.take(8);
+  pl->off_pairs = L.take(sizeof(long long) * kPairShards * kPairShardStride);
   pl->off_npid = L.take(8);
   pl->off_bufs = L.take(sizeof(BufDev) * kMaxBuf);
   pl->off_bidx = L.take(256 * 4);
@@ -343,6 +344,10 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   c->cap = params->capacity;
   (void)hipGetDevice(&c->device);
   grid_of(params, &c->grid);
+  if (const char* tl = std::getenv("SPHX_TEAM_LANES")) {   // tuning knob: 1, 2, 4 or 8
+    int v = std::atoi(tl);
+    if (v == 1 || v == 2 || v == 4 || v == 8) c->team_override = v;
+  }
   char* w = c->ws;
   Fields& F = c->F;
   for (int k = 0; k < 3; ++k)
@@ -435,7 +440,8 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (e == hipSuccess && !cand.empty())
     e = hipMemcpyAsync(S.cand_cells, cand.data(), cand.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
-  if (e == hipSuccess) e = hipMemsetAsync(S.pairs, 0, 8, st);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 8192, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -714,11 +720,14 @@ sph_status sph_profile_read(sph_ctx* c, int32_t kernel, sph_kernel_stats* out) {
 
 sph_status sph_pair_count(sph_ctx* c, int64_t* pairs) {
   if (!c || !pairs) return SPH_E_ARG;
-  long long v = 0;
-  HIPCHK(c, hipMemcpyAsync(&v, c->S.pairs, 8, hipMemcpyDeviceToHost, c->stream), "pairs");
-  HIPCHK(c, hipMemsetAsync(c->S.pairs, 0, 8, c->stream), "pairs reset");
+  const size_t bytes = sizeof(long long) * kPairShards * kPairShardStride;
+  std::vector<long long> v((size_t)kPairShards * kPairShardStride);
+  HIPCHK(c, hipMemcpyAsync(v.data(), c->S.pairs, bytes, hipMemcpyDeviceToHost, c->stream), "pairs");
+  HIPCHK(c, hipMemsetAsync(c->S.pairs, 0, bytes, c->stream), "pairs reset");
   HIPCHK(c, hipStreamSynchronize(c->stream), "pairs sync");
-  *pairs = v;
+  long long s = 0;
+  for (int k = 0; k < kPairShards; ++k) s += v[(size_t)k * kPairShardStride];
+  *pairs = s;
   return SPH_OK;
 }
 

@@ -97,6 +97,7 @@ struct sph_ctx {
   bool need_pv0 = false;
   int pv_half = 0;
   uint32_t* pinned = nullptr;   // host staging (pinned)
+  int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
   std::string err;
   sphx::Profile prof;
 };

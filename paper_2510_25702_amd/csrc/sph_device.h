@@ -11,6 +11,8 @@ namespace sphx {
 constexpr int kMaxBuf = 32;
 constexpr int kMaxInject = 4096;
 constexpr int kWave = 64;
+constexpr int kPairShards = 64;        // pair counters, one per 128-byte line
+constexpr int kPairShardStride = 16;    // long longs between two counters
 
 enum : uint32_t { kFluid = 0, kBuffer = 1, kWall = 2, kDead = 3 };
 enum : uint32_t { kVelExtrapolate = 0, kVelPrescribed = 1 };
