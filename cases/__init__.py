@@ -80,6 +80,7 @@ class Case:
     npid: int = None              # id of the next injected particle
     step: int = 0                 # step counter of the state
     t: float = 0.0                # physical time of the state
+    objective: dict = None        # objective descriptor of a sensitivity case
 
     @property
     def n(self) -> int:
@@ -195,17 +196,28 @@ def make_channel(H=1.0, L=10.0, dp=None, Re=100.0, Umax=1.0, c0=10.0,
                      note=f"{L}Hx{H} channel dp={dp} Re={Re}")
 
 
-def make_adjoint_channel(dp=None, seed=4, steps=100, n_coef=16, amp=0.1):
-    """20H x H channel, Re 200, inlet profile 4Umax y(1-y) + sum a_m sin(m pi y)
-    with a_m ~ U[-amp, amp] (seeded)."""
+def make_adjoint_channel(dp=None, seed=4, steps=100, n_coef=16, amp=0.1, length=20.0,
+                         Umax=1.0):
+    """length x H channel (H = 1), Re 200, started from the developed Poiseuille
+    profile; inlet profile 4 Umax s(1-s) + sum a_m sin(m pi s) (s = y / H) with
+    a_m ~ U[-amp, amp] (seeded), no start-up ramp.  Objective slab: 4dp just
+    upstream of the outlet buffer; wall length: both walls over the length."""
     H = 1.0
     dp = H / 80 if dp is None else dp
     rng = np.random.default_rng(seed)
     coef = tuple(float(a) for a in rng.uniform(-amp, amp, n_coef))
-    c = make_channel(H=H, L=20.0, dp=dp, Re=200.0, steps=steps,
+    c = make_channel(H=H, L=length, dp=dp, Re=200.0, Umax=Umax, steps=steps,
                      profile=PROFILE_SINE, coef=coef, name="adjoint_channel",
-                     seed=seed)
-    c.note = f"20Hx{H} channel dp={dp} Re=200, {n_coef} sine coefficients"
+                     seed=seed, ramp_time=0.0)
+    fl = (c.tag & 3) != WALL
+    y = c.x[fl, 1]
+    c.v[fl, 0] = 4.0 * Umax * y * (H - y) / (H * H)
+    Lb = 4 * dp
+    c.objective = dict(slab_origin=(length - Lb - 4 * dp, 0.0, 0.0),
+                       slab_normal=(1.0, 0.0, 0.0), slab_width=4 * dp,
+                       shear_dir=(1.0, 0.0, 0.0), wall_length=2.0 * length)
+    c.note = (f"{length}Hx{H} channel dp={dp} Re=200, developed start, "
+              f"{n_coef} sine coefficients")
     return c
 
 

@@ -78,6 +78,22 @@ class StepInfo(C.Structure):
                 ("n_ac", C.c_int32), ("pad", C.c_int32), ("n_pairs", C.c_int64)]
 
 
+class Objective(C.Structure):
+    _fields_ = [("slab_origin", C.c_double * 3), ("slab_normal", C.c_double * 3),
+                ("slab_width", C.c_double), ("shear_dir", C.c_double * 3),
+                ("wall_length", C.c_double)]
+
+
+def make_objective(d: dict) -> Objective:
+    o = Objective()
+    for f in ("slab_origin", "slab_normal", "shear_dir"):
+        for k, a in enumerate(d[f]):
+            getattr(o, f)[k] = float(a)
+    o.slab_width = float(d["slab_width"])
+    o.wall_length = float(d["wall_length"])
+    return o
+
+
 class Counts(C.Structure):
     _fields_ = [("n_relabel", C.c_int32 * 256), ("n_inject", C.c_int32 * 256),
                 ("n_delete", C.c_int32 * 256), ("n_revert", C.c_int32 * 256),
@@ -96,6 +112,7 @@ def lib():
         dp = C.POINTER(C.c_double)
         i64p = C.POINTER(C.c_int64)
         u32p = C.POINTER(C.c_uint32)
+        u8p = C.POINTER(C.c_uint8)
         PP, BP, SP = C.POINTER(Params), C.POINTER(BufferDesc), C.POINTER(StateC)
         sig = {
             "ora_set_threads": (None, [C.c_int]),
@@ -115,6 +132,7 @@ def lib():
             "ora_buffer_decisions": (C.c_int, [PP, BP, C.c_int, SP, u32p]),
             "ora_buffer_update": (C.c_int, [PP, BP, C.c_int, SP, C.POINTER(Counts), u32p]),
             "ora_velocity_bc": (C.c_int, [PP, BP, C.c_int, SP]),
+            "ora_objective_eval": (C.c_int, [PP, SP, C.POINTER(Objective), u8p, u8p, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -306,6 +324,90 @@ class OracleSim:
 
     def velocity_bc(self):
         lib().ora_velocity_bc(C.byref(self.P), self.B, self.nbuf, C.byref(self.S))
+
+    def objective(self, desc: dict, member=None):
+        """([J_Q, J_tau], slab membership) of the current state; `member`
+        (0/1 per particle) freezes the slab membership."""
+        n = self.n
+        J = np.zeros(2)
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        m_in = None
+        if member is not None:
+            member = np.ascontiguousarray(member, dtype=np.uint8)
+            m_in = _ptr(member, C.c_uint8)
+        err = lib().ora_objective_eval(C.byref(self.P), C.byref(self.S),
+                                       C.byref(make_objective(desc)), m_in,
+                                       _ptr(out, C.c_uint8), _ptr(J))
+        if err:
+            raise RuntimeError(f"ora_objective_eval failed ({err})")
+        return J, out[:n]
+
+
+# ---------------------------------------------------------------------------
+# Inlet-profile sensitivity reference: rollouts with a frozen event log and
+# central finite differences of the step-averaged objectives.
+# ---------------------------------------------------------------------------
+def with_coef(buffers, bid, coef):
+    """Copy of the buffer list with buffer `bid`'s profile coefficients set."""
+    import dataclasses
+    out = []
+    for b in buffers:
+        if b.id == bid:
+            b = dataclasses.replace(b, coef=tuple(float(a) for a in coef))
+        out.append(b)
+    return out
+
+
+def rollout(case, steps, objective, buffers=None, replay=None, threads=1):
+    """Run `steps` advection steps (step, objective, buffer update) and return
+    the mean over steps of [J_Q, J_tau] with the run's event log.
+
+    replay: a log from an earlier rollout; its time steps, slab memberships
+    and buffer decisions are imposed (frozen) instead of being recomputed."""
+    sim = OracleSim(case, threads=threads, buffers=buffers)
+    J = np.zeros(2)
+    log = []
+    for s in range(steps):
+        if replay is None:
+            I = sim.step()
+            dt_adv, n_ac = I.dt_adv, I.n_ac
+        else:
+            dt_adv, n_ac = replay[s]["dt_adv"], replay[s]["n_ac"]
+            sim.step(dt_adv, n_ac)
+        Js, member = sim.objective(objective, None if replay is None else replay[s]["member"])
+        J += Js
+        n = sim.n
+        if replay is None:
+            dec = sim.decisions().copy()
+        else:
+            dec = replay[s]["dec"]
+        log.append(dict(dt_adv=float(dt_adv), n_ac=int(n_ac), dec=dec, member=member.copy(),
+                        pid=sim.pid[:n].copy(), next_pid=int(sim.S.next_pid)))
+        sim.buffer_update(forced=dec)
+    return J / max(steps, 1), log, sim
+
+
+def fd_gradient(case, steps, objective, bid, eps=1e-4, log=None, threads=1, coefs=None):
+    """Central differences d[J_Q, J_tau]/d a_m of the step-averaged objectives
+    with respect to the profile coefficients of buffer `bid`, decisions and
+    time steps frozen to `log` (the unperturbed run's, by default)."""
+    base = [b for b in case.buffers if b.id == bid][0]
+    a0 = np.array(base.coef, dtype=np.float64)
+    if coefs is None:
+        coefs = range(len(a0))
+    if log is None:
+        _, log, _ = rollout(case, steps, objective, threads=threads)
+    g = np.zeros((len(a0), 2))
+    for m in coefs:
+        Jp = []
+        for sgn in (1.0, -1.0):
+            a = a0.copy()
+            a[m] += sgn * eps
+            J, _, _ = rollout(case, steps, objective, with_coef(case.buffers, bid, a),
+                              replay=log, threads=threads)
+            Jp.append(J)
+        g[m] = (Jp[0] - Jp[1]) / (2.0 * eps)
+    return g, log
 
 
 def neighbors(params: dict, x: np.ndarray, brute=False):

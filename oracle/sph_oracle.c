@@ -1153,3 +1153,55 @@ int ora_buffer_update(const ora_params* P, const ora_buffer* B, int nbuf,
   free(del);
   return ORA_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Objectives of the inlet-profile sensitivity study (see the header):       */
+/* slab mass flux J_Q and mean wall shear stress J_tau, the latter being the  */
+/* wall pairs of the viscous sum of Eq. (eq-discretize-momentum-ARD2) with    */
+/* the antisymmetric dummy-wall velocity, summed over the fluid and turned    */
+/* into the force on the wall.  Slab membership is an FP64 predicate taken in */
+/* a fixed order without contraction.                                         */
+/* ------------------------------------------------------------------------ */
+int ora_objective_eval(const ora_params* P, const ora_state* S, const ora_objective* O,
+                       const uint8_t* member_in, uint8_t* member_out, double J[2]) {
+  if (P->turbulence || !(O->slab_width > 0.0) || !(O->wall_length > 0.0)) return ORA_E_ARG;
+  int dim = P->dim;
+  double Vw = pow_dim(P->dp, dim);
+  double m = P->rho0 * Vw;
+  double mu = P->rho0 * P->nu_l;
+  double h = P->h, rc2 = cutoff2(P);
+  double jq = 0.0, jt = 0.0;
+  int64_t nb[MAXNB];
+  grid_t g;
+  int err = grid_build(&g, P, S->n, S->x);
+  if (err != ORA_OK) { grid_free(&g); return err; }
+  for (int64_t i = 0; i < S->n; ++i) {
+    if (member_out) member_out[i] = 0;
+    if (!is_real(S->tag[i])) continue;
+    const double* xi = S->x + 3 * i;
+    const double* vi = S->v + 3 * i;
+    double s = (O->slab_normal[0] * (xi[0] - O->slab_origin[0]) +
+                O->slab_normal[1] * (xi[1] - O->slab_origin[1])) +
+               O->slab_normal[2] * (xi[2] - O->slab_origin[2]);
+    int in = member_in ? member_in[i] != 0 : (s >= 0.0 && s < O->slab_width);
+    if (member_out) member_out[i] = (uint8_t)in;
+    if (in) {
+      double un = (O->slab_normal[0] * vi[0] + O->slab_normal[1] * vi[1]) +
+                  O->slab_normal[2] * vi[2];
+      jq += m * un / O->slab_width;
+    }
+    double ve = (O->shear_dir[0] * vi[0] + O->shear_dir[1] * vi[1]) + O->shear_dir[2] * vi[2];
+    int k = neighbors_of(&g, S->x, i, rc2, nb);
+    if (k < 0) { err = ORA_E_NUMERIC; break; }
+    for (int a = 0; a < k; ++a) {
+      int64_t j = nb[a];
+      if (KIND(S->tag[j]) != ORA_WALL) continue;
+      double f = kernel_dW_over_r(sqrt(dist2(xi, S->x + 3 * j)), h, dim);
+      jt -= m * (2.0 / S->rho[i]) * mu * f * Vw * (2.0 * ve);
+    }
+  }
+  grid_free(&g);
+  J[0] = jq;
+  J[1] = jt / O->wall_length;
+  return err;
+}

@@ -88,6 +88,22 @@ typedef struct {
   int64_t n_real;
 } ora_counts;
 
+/* Objectives of the inlet-profile sensitivity study (laminar runs):
+ *   J_Q   = sum over real i with 0 <= n.(x_i - o) < w of m (v_i . n) / w,
+ *           the mass flux through a slab of width w (per unit depth in 2D);
+ *   J_tau = -(1 / L_w) sum over real i, wall j, |x_i - x_j| < 2h of
+ *           m (2 / rho_i) mu f(r_ij) V_j (2 v_i . e),  f = W'(r) / r,
+ *           the e-component of the viscous force that the fluid exerts on the
+ *           dummy walls (antisymmetric wall velocity) per unit wall length,
+ *           i.e. the mean wall shear stress; mu = rho0 nu_l. */
+typedef struct {
+  double slab_origin[3];  /* a point on the slab's upstream plane */
+  double slab_normal[3];  /* unit normal n (flux direction) */
+  double slab_width;      /* w > 0 */
+  double shear_dir[3];    /* unit direction e of the wall force */
+  double wall_length;     /* L_w > 0: wetted wall length (2D) or area (3D) */
+} ora_objective;
+
 /* status codes */
 enum { ORA_OK = 0, ORA_E_ARG = 1, ORA_E_CAPACITY = 2, ORA_E_NUMERIC = 4 };
 
@@ -121,6 +137,12 @@ int ora_buffer_update(const ora_params* P, const ora_buffer* B, int nbuf,
                       ora_state* S, ora_counts* C, const uint32_t* forced_dec);
 int ora_velocity_bc(const ora_params* P, const ora_buffer* B, int nbuf,
                     ora_state* S);
+/* J[0] = J_Q, J[1] = J_tau of the current state (laminar runs only).
+ * Slab membership: taken from member_in[i] (0/1) when given (a frozen event
+ * of a replayed run), else from the positions; written to member_out when
+ * given. */
+int ora_objective_eval(const ora_params* P, const ora_state* S, const ora_objective* O,
+                       const uint8_t* member_in, uint8_t* member_out, double J[2]);
 
 #ifdef __cplusplus
 }
