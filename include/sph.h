@@ -207,6 +207,10 @@ sph_status sph_get_particles(sph_ctx* ctx, const sph_particles* dst);
  * argument of the inflow ramp). */
 sph_status sph_set_clock(sph_ctx* ctx, int64_t step, double t);
 
+/* Step counter, physical time and id of the next injected particle
+ * (checkpoint / resume: with sph_get_particles this is the whole state). */
+sph_status sph_get_clock(const sph_ctx* ctx, int64_t* step, double* t, uint64_t* next_pid);
+
 /* Cell-linked-list build (Sec. 2.4.3: rebuilt after deletion every advection
  * step): counting sort of all particles by cell id (ties by particle id),
  * dropping particles tagged SPH_DEAD, and permutation of every field into
@@ -238,6 +242,20 @@ sph_status sph_step(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* out)
  * NULL.  Synchronises once to read the counts. */
 sph_status sph_buffer_update(sph_ctx* ctx, sph_buffer_counts* out);
 
+/* sph_buffer_update with an event log and replay, for sensitivity runs.
+ * log_by_pid (device uint32 [pid_cap], or NULL): zeroed, then receives the
+ * decision code of every particle examined, indexed by particle id.
+ * forced_by_pid (device uint32 [pid_cap], or NULL): the decisions to apply
+ * instead of the predicates (a log of an earlier run), looked up by
+ * particle id for every slot; ids >= pid_cap and non-real particles get
+ * SPH_DEC_NONE.  pid_cap must be >= the next particle id when either array
+ * is given (SPH_E_ARG).  After an update with injections, the children are
+ * the copies of the parents in canonical order (see sph_buffer_update).
+ * Synchronises once. */
+sph_status sph_buffer_update_ex(sph_ctx* ctx, const uint32_t* forced_by_pid,
+                                uint32_t* log_by_pid, int64_t pid_cap,
+                                sph_buffer_counts* out);
+
 /* Decision codes of sph_buffer_update for the current state without
  * applying them (device uint32 [n_total], current order; particles outside
  * every local cell list get SPH_DEC_NONE).  Requires sph_build_cells. */
@@ -265,6 +283,79 @@ sph_status sph_profile_read(sph_ctx* ctx, int32_t kernel, sph_kernel_stats* out)
  * call (counted in the continuity pass x 2 + correction + advection).
  * Synchronises. */
 sph_status sph_pair_count(sph_ctx* ctx, int64_t* pairs);
+
+/* ---------------------------------------------------------------------
+ * Inlet-profile sensitivity (laminar, FP64 contexts).
+ *
+ * Objectives at the state after sph_step (before the buffer update):
+ *   J_Q   = sum over real i with 0 <= n.(x_i - o) < w of m (v_i . n) / w,
+ *           the mass flux through a slab (per unit depth in 2D);
+ *   J_tau = -(1 / L_w) sum over real i and wall j with |x_i - x_j| < 2h of
+ *           m (2 / rho_i) mu f(r_ij) V_j (2 v_i . e),  f = W'(r) / r,
+ *           mu = rho0 nu_l: the e-component of the viscous force of the
+ *           fluid on the dummy walls (Eq. (eq-discretize-momentum-ARD2) with
+ *           the antisymmetric wall velocity) per unit wall length.
+ * Parameters: the sine coefficients a_1..a_n of the control buffer's
+ * SPH_PROFILE_SINE inlet profile u(s) = 4 u0 s (1 - s) + sum a_m sin(m pi s).
+ * --------------------------------------------------------------------- */
+typedef struct {
+  double slab_origin[3];   /* a point on the slab's upstream plane */
+  double slab_normal[3];   /* unit normal n */
+  double slab_width;       /* w > 0 */
+  double shear_dir[3];     /* unit direction e */
+  double wall_length;      /* L_w > 0 */
+  int32_t control_buffer;  /* id of the buffer whose coefficients are the parameters */
+  int32_t pad;
+} sph_objective_desc;
+
+/* Replaces the profile coefficients of buffer `buffer_id` (host array of
+ * n_coef <= 16 values; the rest are zeroed).  Synchronises. */
+sph_status sph_set_profile_coef(sph_ctx* ctx, int32_t buffer_id, int32_t n_coef,
+                                const double* coef);
+
+/* Adds [J_Q, J_tau] of the current state to J (device FP64 [2]).  Slab
+ * membership is taken from member_by_pid (device uint8 [pid_cap], a frozen
+ * event of a replayed run) when given, else from the positions; it is
+ * written to member_out_by_pid (device uint8 [pid_cap], zeroed first) when
+ * given.  Laminar contexts only (SPH_E_ARG).  Deterministic.  Asynchronous. */
+sph_status sph_objective(sph_ctx* ctx, const sph_objective_desc* obj,
+                         const uint8_t* member_by_pid, uint8_t* member_out_by_pid,
+                         int64_t pid_cap, double* J);
+
+/* One recorded advection step, as the adjoint replays it. */
+typedef struct {
+  int64_t step;            /* step counter of the pre-step state */
+  double t;                /* time of the pre-step state */
+  uint64_t next_pid;       /* next particle id of the pre-step state */
+  double dt_adv;           /* the step's advection time step */
+  int32_t n_ac;            /* and its acoustic sub-steps */
+  int32_t pad;
+  const uint32_t* dec_by_pid;    /* device [pid_cap]: the step's buffer decisions */
+  const uint8_t* member_by_pid;  /* device [pid_cap]: the step's slab membership */
+  int64_t pid_cap;
+  double w_flux, w_shear;  /* dL/dJ_Q and dL/dJ_tau of this step's objectives */
+} sph_adjoint_ctrl;
+
+/* Device workspace of sph_adjoint_step for steps of up to max_nac acoustic
+ * sub-steps; 0 when the context cannot run the adjoint (FP32-mixed or
+ * turbulent). */
+size_t sph_adjoint_workspace_size(const sph_ctx* ctx, int32_t max_nac);
+
+/* Discrete adjoint of one advection step followed by its buffer update
+ * (decisions, time step and slab membership frozen), on the fixed neighbour
+ * sets of the step: the reverse of the continuity, pressure, viscous and
+ * correction passes and of the velocity boundary conditions.
+ *   pre, n_pre: the state at the start of the step (device FP64 /
+ *       uint32 component-major, as sph_get_particles writes it);
+ *   lam (device FP64 [8][pid_cap], rows x0 x1 x2 v0 v1 v2 rho drho, by
+ *       particle id): on entry the cotangent of the state after the step's
+ *       buffer update; on return that of the state at the start of the step
+ *       (entries of particles created by the update are zeroed);
+ *   grad (device FP64 [16]): receives += dL/da through the step.
+ * The replay overwrites the context's particle state.  Synchronises. */
+sph_status sph_adjoint_step(sph_ctx* ctx, const sph_particles* pre, int64_t n_pre,
+                            const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
+                            double* lam, double* grad, void* adj_ws, size_t adj_bytes);
 
 #ifdef __cplusplus
 }

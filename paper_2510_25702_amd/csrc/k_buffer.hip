@@ -37,6 +37,10 @@ struct BufArgs {
   uint32_t* flags;
   int dry;
   uint32_t* dec_out;
+  const uint32_t* forced;   // decisions by particle id (replay), or NULL
+  uint32_t* log;            // decisions by particle id (record), or NULL
+  int64_t pid_cap;          // length of forced / log
+  int n;                    // particle slots (forced replay: every slot)
 };
 
 __device__ __forceinline__ bool in_box(const int c[3], const BufDev& b, int dim) {
@@ -86,6 +90,31 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
   return kDecNone;
 }
 
+// Count a decision and queue an injection.
+__device__ __forceinline__ void record(const BufArgs& a, int i, uint32_t d) {
+  a.dec[i] = d;
+  const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
+  switch (act) {
+    case kDecRelabel: atomicAdd(&a.counters[id], 1); break;
+    case kDecInject: {
+      atomicAdd(&a.counters[256 + id], 1);
+      const int slot = atomicAdd(&a.counters[1024], 1);
+      if (slot < kMaxInject) {
+        a.inj_key[slot] = ((uint64_t)id << 32) | (uint64_t)a.pid[i];
+        a.inj_idx[slot] = i;
+      }
+      break;
+    }
+    case kDecDelete: atomicAdd(&a.counters[512 + id], 1); break;
+    case kDecRevert: atomicAdd(&a.counters[768 + id], 1); break;
+    case kDecRevertRelabel:
+      atomicAdd(&a.counters[768 + id], 1);
+      atomicAdd(&a.counters[id2], 1);
+      break;
+    default: break;
+  }
+}
+
 // K12: one wavefront per candidate cell.
 __global__ __launch_bounds__(kWave) void k_buffer_decide(BufArgs a) {
   const int cell = a.cand[blockIdx.x];
@@ -96,43 +125,45 @@ __global__ __launch_bounds__(kWave) void k_buffer_decide(BufArgs a) {
       a.dec_out[i] = d;
       continue;
     }
-    a.dec[i] = d;
-    const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
-    switch (act) {
-      case kDecRelabel: atomicAdd(&a.counters[id], 1); break;
-      case kDecInject: {
-        atomicAdd(&a.counters[256 + id], 1);
-        const int slot = atomicAdd(&a.counters[1024], 1);
-        if (slot < kMaxInject) {
-          a.inj_key[slot] = ((uint64_t)id << 32) | (uint64_t)a.pid[i];
-          a.inj_idx[slot] = i;
-        }
-        break;
-      }
-      case kDecDelete: atomicAdd(&a.counters[512 + id], 1); break;
-      case kDecRevert: atomicAdd(&a.counters[768 + id], 1); break;
-      case kDecRevertRelabel:
-        atomicAdd(&a.counters[768 + id], 1);
-        atomicAdd(&a.counters[id2], 1);
-        break;
-      default: break;
-    }
+    if (a.log && a.pid[i] < a.pid_cap) a.log[a.pid[i]] = d;
+    record(a, i, d);
   }
 }
 
+// K12 (replay): the decisions of a recorded update, looked up by particle id
+// for every slot, in place of the predicates.
+__global__ __launch_bounds__(256) void k_buffer_forced(BufArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint32_t p = a.pid[i];
+  uint32_t d = p < a.pid_cap ? a.forced[p] : kDecNone;
+  if (!is_real(a.tag[i])) d = kDecNone;
+  if (a.log && p < a.pid_cap) a.log[p] = d;
+  record(a, i, d);
+}
+
 // K14: apply tag changes (after K13 succeeded).
+__device__ __forceinline__ void apply_one(const BufArgs& a, int i) {
+  const uint32_t d = a.dec[i];
+  const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
+  if (act == kDecRelabel) a.tag[i] = kBuffer | (id << 8);
+  else if (act == kDecRevert) a.tag[i] = kFluid;
+  else if (act == kDecRevertRelabel) a.tag[i] = kBuffer | (id2 << 8);
+  else if (act == kDecDelete) a.tag[i] = kDead;
+}
+
 __global__ __launch_bounds__(kWave) void k_buffer_apply(BufArgs a) {
   if (*a.flags & kFlagCapacity) return;
   const int cell = a.cand[blockIdx.x];
   const int b = a.cstart[cell], e = a.cstart[cell + 1];
-  for (int i = b + (int)threadIdx.x; i < e; i += kWave) {
-    const uint32_t d = a.dec[i];
-    const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
-    if (act == kDecRelabel) a.tag[i] = kBuffer | (id << 8);
-    else if (act == kDecRevert) a.tag[i] = kFluid;
-    else if (act == kDecRevertRelabel) a.tag[i] = kBuffer | (id2 << 8);
-    else if (act == kDecDelete) a.tag[i] = kDead;
-  }
+  for (int i = b + (int)threadIdx.x; i < e; i += kWave) apply_one(a, i);
+}
+
+// K14 (replay): every slot.
+__global__ __launch_bounds__(256) void k_buffer_apply_all(BufArgs a) {
+  if (*a.flags & kFlagCapacity) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) apply_one(a, i);
 }
 
 template <typename T>
@@ -200,6 +231,9 @@ __global__ __launch_bounds__(kInjThreads) void k_buffer_inject(InjArgs<T> a) {
       __syncthreads();
     }
   }
+  // the sorted order is kept: child r of this update is the copy of slot
+  // inj_idx[r] and has particle id base_pid + r
+  for (int r = threadIdx.x; r < m; r += blockDim.x) a.inj_idx[r] = sidx[r];
   const uint64_t base_pid = *a.next_pid;
   // new fluid particles: exact copies of the parents, appended in order
   for (int r = threadIdx.x; r < m; r += blockDim.x) {
@@ -267,6 +301,10 @@ BufArgs make_bufargs(sph_ctx* c, bool dry, uint32_t* dec_out) {
   a.flags = c->S.flags;
   a.dry = dry ? 1 : 0;
   a.dec_out = dec_out;
+  a.forced = nullptr;
+  a.log = nullptr;
+  a.pid_cap = 0;
+  a.n = (int)c->n_total;
   return a;
 }
 
@@ -308,19 +346,38 @@ hipError_t inject_impl(sph_ctx* c) {
 
 }  // namespace
 
-hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out) {
+hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_t* log,
+                                int64_t pid_cap) {
   if (c->S.n_cand_cells == 0) return hipSuccess;
   BufArgs a = make_bufargs(c, dry, dec_out);
+  a.log = log;
+  a.pid_cap = pid_cap;
   k_buffer_decide<<<c->S.n_cand_cells, kWave, 0, c->stream>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_buffer_apply(sph_ctx* c) {
+hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log,
+                                int64_t pid_cap) {
+  if (c->n_total == 0) return hipSuccess;
+  BufArgs a = make_bufargs(c, false, nullptr);
+  a.forced = forced;
+  a.log = log;
+  a.pid_cap = pid_cap;
+  k_buffer_forced<<<(int)((c->n_total + 255) / 256), 256, 0, c->stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots) {
   hipError_t e = c->P.precision == SPH_FP64 ? inject_impl<double>(c) : inject_impl<float>(c);
   if (e != hipSuccess) return e;
-  if (c->S.n_cand_cells == 0) return hipSuccess;
   BufArgs a = make_bufargs(c, false, nullptr);
-  k_buffer_apply<<<c->S.n_cand_cells, kWave, 0, c->stream>>>(a);
+  if (all_slots) {
+    if (c->n_total == 0) return hipSuccess;
+    k_buffer_apply_all<<<(int)((c->n_total + 255) / 256), 256, 0, c->stream>>>(a);
+  } else {
+    if (c->S.n_cand_cells == 0) return hipSuccess;
+    k_buffer_apply<<<c->S.n_cand_cells, kWave, 0, c->stream>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -523,6 +523,14 @@ sph_status sph_set_clock(sph_ctx* c, int64_t step, double t) {
   return SPH_OK;
 }
 
+sph_status sph_get_clock(const sph_ctx* c, int64_t* step, double* t, uint64_t* next_pid) {
+  if (!c) return SPH_E_ARG;
+  if (step) *step = c->step;
+  if (t) *t = c->t;
+  if (next_pid) *next_pid = c->next_pid;
+  return SPH_OK;
+}
+
 sph_status sph_build_cells(sph_ctx* c) {
   if (!c) return SPH_E_ARG;
   profile_launch(c, SPH_K_CELLS);
@@ -621,12 +629,23 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
 }
 
 sph_status sph_buffer_update(sph_ctx* c, sph_buffer_counts* out) {
+  return sph_buffer_update_ex(c, nullptr, nullptr, 0, out);
+}
+
+sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* log_by_pid,
+                                int64_t pid_cap, sph_buffer_counts* out) {
   if (!c) return SPH_E_ARG;
   if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_buffer_update needs sph_build_cells first");
+  if ((forced_by_pid || log_by_pid) && pid_cap < (int64_t)c->next_pid)
+    return fail(c, SPH_E_ARG, "pid_cap must cover every particle id (>= next_pid)");
   profile_launch(c, SPH_K_BUFFER);
   hipError_t e = launch_zero_i32(c, c->S.counters, 1040);
-  if (e == hipSuccess) e = launch_buffer_decide(c, false, nullptr);
-  if (e == hipSuccess) e = launch_buffer_apply(c);
+  if (e == hipSuccess && log_by_pid) e = launch_zero_i32(c, (int32_t*)log_by_pid, pid_cap);
+  if (e == hipSuccess) {
+    if (forced_by_pid) e = launch_buffer_forced(c, forced_by_pid, log_by_pid, pid_cap);
+    else e = launch_buffer_decide(c, false, nullptr, log_by_pid, pid_cap);
+  }
+  if (e == hipSuccess) e = launch_buffer_apply(c, forced_by_pid != nullptr);
   prof_end(c);
   if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
   char* hb = (char*)c->pinned;
@@ -729,6 +748,99 @@ sph_status sph_pair_count(sph_ctx* c, int64_t* pairs) {
   for (int k = 0; k < kPairShards; ++k) s += v[(size_t)k * kPairShardStride];
   *pairs = s;
   return SPH_OK;
+}
+
+sph_status sph_set_profile_coef(sph_ctx* c, int32_t buffer_id, int32_t n_coef, const double* coef) {
+  if (!c) return SPH_E_ARG;
+  if (n_coef < 0 || n_coef > 16 || (n_coef > 0 && !coef))
+    return fail(c, SPH_E_ARG, "n_coef must be 0..16 with a coefficient array");
+  int q = -1;
+  for (int k = 0; k < c->nbuf; ++k)
+    if (c->bufs_h[k].id == buffer_id) q = k;
+  if (q < 0) return fail(c, SPH_E_ARG, "no buffer with this id");
+  BufDev& d = c->bufdev_h[q];
+  d.n_coef = n_coef;
+  c->bufs_h[q].n_coef = n_coef;
+  for (int m = 0; m < 16; ++m) {
+    d.coef[m] = m < n_coef ? coef[m] : 0.0;
+    c->bufs_h[q].coef[m] = d.coef[m];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->S.bufs + q, &d, sizeof(BufDev), hipMemcpyHostToDevice, c->stream),
+         "profile coefficients");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "profile sync");
+  return SPH_OK;
+}
+
+sph_status sph_objective(sph_ctx* c, const sph_objective_desc* obj, const uint8_t* member_by_pid,
+                         uint8_t* member_out_by_pid, int64_t pid_cap, double* J) {
+  if (!c) return SPH_E_ARG;
+  if (!obj || !J) return fail(c, SPH_E_ARG, "obj and J are required");
+  if (c->P.turbulence) return fail(c, SPH_E_ARG, "the objectives are defined for laminar runs");
+  if (!(obj->slab_width > 0) || !(obj->wall_length > 0))
+    return fail(c, SPH_E_ARG, "slab_width and wall_length must be > 0");
+  if ((member_by_pid || member_out_by_pid) && pid_cap < (int64_t)c->next_pid)
+    return fail(c, SPH_E_ARG, "pid_cap must cover every particle id (>= next_pid)");
+  if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_objective needs the cell list of the step");
+  HIPCHK(c, launch_objective(c, obj, member_by_pid, member_out_by_pid, pid_cap, J), "objective");
+  return SPH_OK;
+}
+
+size_t sph_adjoint_workspace_size(const sph_ctx* c, int32_t max_nac) {
+  if (!c) return 0;
+  return adjoint_ws_bytes(c, max_nac);
+}
+
+sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
+                            const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
+                            double* lam, double* grad, void* adj_ws, size_t adj_bytes) {
+  if (!c) return SPH_E_ARG;
+  if (!pre || !obj || !ctl || !lam || !grad) return fail(c, SPH_E_ARG, "null argument");
+  if (c->P.precision != SPH_FP64 || c->P.turbulence)
+    return fail(c, SPH_E_ARG, "the adjoint needs an FP64 laminar context");
+  if (ctl->n_ac < 1 || !(ctl->dt_adv > 0)) return fail(c, SPH_E_ARG, "bad dt_adv / n_ac");
+  if (!ctl->dec_by_pid || ctl->pid_cap < (int64_t)ctl->next_pid)
+    return fail(c, SPH_E_ARG, "dec_by_pid with pid_cap >= next_pid is required");
+  const size_t need = adjoint_ws_bytes(c, ctl->n_ac);
+  if (!adj_ws || adj_bytes < need || ((uintptr_t)adj_ws & 255))
+    return fail(c, SPH_E_ARG, "adjoint workspace too small or not 256-byte aligned");
+  if (!(obj->slab_width > 0) || !(obj->wall_length > 0))
+    return fail(c, SPH_E_ARG, "slab_width and wall_length must be > 0");
+  char* ws = (char*)adj_ws;
+  const int N = ctl->n_ac;
+  const double dt = ctl->dt_adv / N;
+  // replay the step from its start state, keeping the sub-step states
+  sph_status st = sph_set_particles(c, n_pre, ctl->next_pid, pre);
+  if (st != SPH_OK) return st;
+  c->step = ctl->step;
+  c->t = ctl->t;
+  if ((st = sph_build_cells(c)) != SPH_OK) return st;
+  if ((st = sph_correction(c)) != SPH_OK) return st;
+  HIPCHK(c, adjoint_snap_start(c, ws, N), "adjoint snapshot");
+  HIPCHK(c, launch_advection(c, ctl->dt_adv, dt, false, nullptr), "advection");
+  c->F.p.flip();
+  c->F.vol.flip();
+  HIPCHK(c, adjoint_snap_advection(c, ws, N), "adjoint snapshot");
+  for (int s = 0; s < N; ++s) {
+    HIPCHK(c, launch_pressure(c, dt, false, nullptr), "pressure");
+    HIPCHK(c, adjoint_snap_pressure(c, ws, N, s), "adjoint snapshot");
+    HIPCHK(c, launch_density(c, dt, s == N - 1, false, nullptr), "density");
+    HIPCHK(c, adjoint_snap_density(c, ws, N, s), "adjoint snapshot");
+  }
+  c->step += 1;
+  c->t += ctl->dt_adv;
+  c->moved = true;
+  c->B_valid = false;
+  const int n_step = (int)c->n_total;
+  if ((st = sph_buffer_update_ex(c, ctl->dec_by_pid, nullptr, ctl->pid_cap, nullptr)) != SPH_OK)
+    return st;
+  // and walk it backwards
+  HIPCHK(c, adjoint_reverse_launch(c, ws, obj, ctl, n_step, lam, grad), "adjoint");
+  HIPCHK(c, hipMemcpyAsync((char*)c->pinned + 64, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream),
+         "flags");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "adjoint sync");
+  const uint32_t flags = *(uint32_t*)((char*)c->pinned + 64);
+  if (flags & kFlagCapacity) return fail(c, SPH_E_ARG, "a particle id is not below pid_cap");
+  return check_flags(c, flags);
 }
 
 }  // extern "C"

@@ -118,11 +118,24 @@ hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rat
 hipError_t launch_density(sph_ctx* c, double dt, bool last, bool rates_only,
                           const sph_rates* out);
 hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out);
-hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out);
-hipError_t launch_buffer_apply(sph_ctx* c);
+hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_t* log = nullptr,
+                                int64_t pid_cap = 0);
+hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log, int64_t pid_cap);
+hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots = false);
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs);
 hipError_t launch_export_B(sph_ctx* c, double* B);
+
+// sensitivity (k_adjoint.hip)
+size_t adjoint_ws_bytes(const sph_ctx* c, int max_nac);
+hipError_t launch_objective(sph_ctx* c, const sph_objective_desc* obj, const uint8_t* member_in,
+                            uint8_t* member_out, int64_t pid_cap, double* J);
+hipError_t adjoint_snap_start(sph_ctx* c, char* ws, int N);
+hipError_t adjoint_snap_advection(sph_ctx* c, char* ws, int N);
+hipError_t adjoint_snap_pressure(sph_ctx* c, char* ws, int N, int s);
+hipError_t adjoint_snap_density(sph_ctx* c, char* ws, int N, int s);
+hipError_t adjoint_reverse_launch(sph_ctx* c, char* ws, const sph_objective_desc* obj,
+                                  const sph_adjoint_ctrl* ctl, int n, double* lam, double* grad);
 
 size_t pair_bytes(const sph_ctx* c);
 void prof_begin(sph_ctx* c, int kernel, double bytes, double particles);

@@ -1,0 +1,230 @@
+// Neighbour-pass building blocks shared by the forward passes (k_pairs.hip)
+// and their adjoints (k_adjoint.hip): the cell-stencil neighbour loop with
+// teams of lanes per particle, team reductions, the sharded pair counter,
+// small symmetric-matrix helpers, the equation of state and the guarded
+// inverse of the correction moment.
+#pragma once
+
+#include "sph_ctx.h"
+
+namespace sphx {
+
+template <typename T>
+inline T* tp(void* p) { return static_cast<T*>(p); }
+
+template <typename T>
+struct PairCtx {
+  const T* xr[3];
+  const T* vol;
+  const uint32_t* tag;
+  const int32_t* cell;
+  const int32_t* cs;    // cell_start
+  int nx, ny;
+  T csz, rc2, inv_h, kf;
+  long long* pairs;   // directed pairs counter (NULL: not counted)
+};
+
+// Sum over the L lanes of a team (butterfly: the same order in every run).
+template <int L, typename T>
+__device__ __forceinline__ T team_sum(T v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Directed-pair counter: one atomic per block, spread over kPairShards
+// counters 128 bytes apart, so the passes do not serialise on one address.
+// Every thread of the block must reach this call.
+__device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
+  if (!ctr) return;
+  __shared__ long long part[16];
+  m = wave_sum_ll(m);
+  const int nw = blockDim.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < nw; ++w) s += part[w];
+    if (s)
+      atomicAdd(reinterpret_cast<unsigned long long*>(ctr + (blockIdx.x & (kPairShards - 1)) *
+                                                               kPairShardStride),
+                (unsigned long long)s);
+  }
+}
+
+// Visit every j != i with |r_ij|^2 < (2h)^2 among the particles of the
+// 3^DIM build cells around i's cell; r = x_i - x_j from cell-relative
+// positions: r = (xr_i - xr_j) - (cell_j - cell_i) * cs.
+// A team of L consecutive lanes shares particle i: lane l visits the
+// candidates l, l + L, l + 2L, ... of every row.
+template <typename T, int DIM, int L, typename Fn>
+__device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int lane,
+                                              const T xi[3], Fn&& fn) {
+  const int c = pc.cell[i];
+  const int cx = c % pc.nx;
+  const int cyz = c / pc.nx;
+  const int cy = cyz % pc.ny;
+  const int cz = cyz / pc.ny;
+  constexpr int zr = DIM == 3 ? 1 : 0;
+#pragma unroll
+  for (int dz = -zr; dz <= zr; ++dz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx;
+      const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
+                j3 = pc.cs[base + 2];
+      const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      for (int j = j0 + lane; j < j3; j += L) {
+        const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
+        T r[3];
+        r[0] = (xi[0] - pc.xr[0][j]) + ox;
+        r[1] = (xi[1] - pc.xr[1][j]) + oy;
+        r[2] = DIM == 3 ? (xi[2] - pc.xr[2][j]) + oz : T(0);
+        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                              : r[0] * r[0] + r[1] * r[1];
+        if (r2 < pc.rc2 && j != i) fn(j, r, r2);
+      }
+    }
+  }
+}
+
+// B (symmetric, packed xx xy xz yy yz zz) times a vector.
+template <typename T, int DIM>
+__device__ __forceinline__ void symv(const T B[6], const T a[3], T o[3]) {
+  if (DIM == 2) {
+    o[0] = B[0] * a[0] + B[1] * a[1];
+    o[1] = B[1] * a[0] + B[3] * a[1];
+    o[2] = T(0);
+  } else {
+    o[0] = B[0] * a[0] + B[1] * a[1] + B[2] * a[2];
+    o[1] = B[1] * a[0] + B[3] * a[1] + B[4] * a[2];
+    o[2] = B[2] * a[0] + B[4] * a[1] + B[5] * a[2];
+  }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void load_B(const T* const* Bp, int i, T B[6]) {
+  B[0] = Bp[0][i];
+  B[1] = Bp[1][i];
+  B[3] = Bp[3][i];
+  if (DIM == 3) {
+    B[2] = Bp[2][i];
+    B[4] = Bp[4][i];
+    B[5] = Bp[5][i];
+  } else {
+    B[2] = B[4] = B[5] = T(0);
+  }
+}
+
+__device__ __forceinline__ double eos(double rho, double k, double rho0, double c0, int turb) {
+  double p = rho0 * c0 * c0 * (rho / rho0 - 1.0);
+  if (turb) p += (2.0 / 3.0) * rho * k;
+  return p;
+}
+
+// B = A^-1 for a well-conditioned moment; with d = det A / (tr A / dim)^dim
+// below 0.25 the inverse is blended towards the identity with weight
+// (d / 0.25)^2, and B = I when tr A <= 0 or d <= 0.
+template <int DIM>
+__device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
+  constexpr double theta = 0.25;
+  double inv[6], det, tr, d;
+  if (DIM == 2) {
+    tr = A[0] + A[3];
+    det = A[0] * A[3] - A[1] * A[1];
+    d = tr > 0.0 ? det / ((0.5 * tr) * (0.5 * tr)) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
+      B[0] = 1.0; B[1] = 0.0; B[3] = 1.0; B[2] = B[4] = B[5] = 0.0;
+      return;
+    }
+    inv[0] = A[3] / det; inv[1] = -A[1] / det; inv[3] = A[0] / det;
+    inv[2] = inv[4] = inv[5] = 0.0;
+  } else {
+    const double c00 = A[3] * A[5] - A[4] * A[4];
+    const double c01 = A[4] * A[2] - A[1] * A[5];
+    const double c02 = A[1] * A[4] - A[3] * A[2];
+    det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    tr = A[0] + A[3] + A[5];
+    const double t3 = tr / 3.0;
+    d = tr > 0.0 ? det / (t3 * t3 * t3) : 0.0;
+    if (!(tr > 0.0) || !(d > 0.0)) {
+      B[0] = 1.0; B[1] = 0.0; B[2] = 0.0; B[3] = 1.0; B[4] = 0.0; B[5] = 1.0;
+      return;
+    }
+    inv[0] = c00 / det;
+    inv[1] = c01 / det;
+    inv[2] = c02 / det;
+    inv[3] = (A[0] * A[5] - A[2] * A[2]) / det;
+    inv[4] = (A[2] * A[1] - A[0] * A[4]) / det;
+    inv[5] = (A[0] * A[3] - A[1] * A[1]) / det;
+  }
+  const double w = d >= theta ? 1.0 : (d / theta) * (d / theta);
+  const double id[6] = {1.0, 0.0, 0.0, 1.0, 0.0, DIM == 3 ? 1.0 : 0.0};
+  for (int k = 0; k < 6; ++k) B[k] = w * inv[k] + (1.0 - w) * id[k];
+}
+
+
+template <typename T>
+inline Consts<T> make_consts(const sph_ctx* c) {
+  Consts<T> C;
+  const sph_params& P = c->P;
+  C.dim = P.dim;
+  C.turbulence = P.turbulence;
+  C.obc_mode = P.obc_mode;
+  C.nbuf = c->nbuf;
+  C.grid = c->grid;
+  C.h = P.h;
+  const double rc = 2.0 * P.h;
+  C.rc2 = rc * rc;
+  C.dp = P.dp;
+  C.Vw = P.dim == 2 ? P.dp * P.dp : P.dp * P.dp * P.dp;
+  C.mass = P.rho0 * C.Vw;
+  C.rho0 = P.rho0;
+  C.c0 = P.c0;
+  C.nu_l = P.nu_l;
+  C.eta = P.eta;
+  for (int k = 0; k < 3; ++k) C.g[k] = P.g[k];
+  C.C1 = P.C1;
+  C.C2 = P.C2;
+  C.Cmu = P.Cmu;
+  C.sigma_k = P.sigma_k;
+  C.sigma_eps = P.sigma_eps;
+  C.k_floor = P.k_floor;
+  C.eps_floor = P.eps_floor;
+  C.skin = 0.5 * (P.cell_size - 2.0 * P.h);
+  C.seed = P.seed;
+  const double alpha = P.dim == 2 ? 7.0 / (4.0 * M_PI * P.h * P.h)
+                                  : 21.0 / (16.0 * M_PI * P.h * P.h * P.h);
+  C.h_t = (T)P.h;
+  C.rc2_t = (T)C.rc2;
+  C.cs_t = (T)P.cell_size;
+  C.inv_h_t = (T)(1.0 / P.h);
+  C.kf_t = (T)(-5.0 * alpha / (P.h * P.h));
+  C.rho0_t = (T)P.rho0;
+  C.c0_t = (T)P.c0;
+  C.eta_t = (T)P.eta;
+  C.inv_2rc0_t = (T)(1.0 / (2.0 * P.rho0 * P.c0));
+  C.mu_R_t = (T)(0.5 * P.rho0 * P.h);
+  return C;
+}
+
+template <typename T>
+inline PairCtx<T> make_pc(const sph_ctx* c, const sphx::Slot2<void>* xr, int xslot) {
+  PairCtx<T> pc;
+  for (int k = 0; k < 3; ++k) pc.xr[k] = tp<T>(xr[k].a[xslot]);
+  pc.vol = tp<T>(c->F.vol.live());
+  pc.tag = c->F.tag.live();
+  pc.cell = c->F.cell;
+  pc.cs = c->S.cell_start;
+  pc.nx = c->grid.n[0];
+  pc.ny = c->grid.n[1];
+  pc.csz = (T)c->P.cell_size;
+  const double rc = 2.0 * c->P.h;
+  pc.rc2 = (T)(rc * rc);
+  pc.inv_h = (T)(1.0 / c->P.h);
+  pc.kf = T(0);
+  pc.pairs = c->S.pairs;
+  return pc;
+}
+
+}  // namespace sphx

@@ -89,6 +89,20 @@ class sph_kernel_stats(C.Structure):
                 ("bytes", C.c_double), ("particles", C.c_double)]
 
 
+class sph_objective_desc(C.Structure):
+    _fields_ = [("slab_origin", C.c_double * 3), ("slab_normal", C.c_double * 3),
+                ("slab_width", C.c_double), ("shear_dir", C.c_double * 3),
+                ("wall_length", C.c_double), ("control_buffer", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class sph_adjoint_ctrl(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("next_pid", C.c_uint64),
+                ("dt_adv", C.c_double), ("n_ac", C.c_int32), ("pad", C.c_int32),
+                ("dec_by_pid", C.c_void_p), ("member_by_pid", C.c_void_p),
+                ("pid_cap", C.c_int64), ("w_flux", C.c_double), ("w_shear", C.c_double)]
+
+
 EXPORTS = {
     "sph_workspace_size": (C.c_size_t, [C.POINTER(sph_params), C.POINTER(sph_buffer_desc), C.c_int32]),
     "sph_create": (C.c_int, [C.POINTER(sph_params), C.POINTER(sph_buffer_desc), C.c_int32,
@@ -110,6 +124,17 @@ EXPORTS = {
     "sph_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sph_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sph_kernel_stats)]),
     "sph_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "sph_get_clock": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                C.POINTER(C.c_uint64)]),
+    "sph_buffer_update_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.POINTER(sph_buffer_counts)]),
+    "sph_set_profile_coef": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "sph_objective": (C.c_int, [C.c_void_p, C.POINTER(sph_objective_desc), C.c_void_p,
+                                C.c_void_p, C.c_int64, C.c_void_p]),
+    "sph_adjoint_workspace_size": (C.c_size_t, [C.c_void_p, C.c_int32]),
+    "sph_adjoint_step": (C.c_int, [C.c_void_p, C.POINTER(sph_particles), C.c_int64,
+                                   C.POINTER(sph_objective_desc), C.POINTER(sph_adjoint_ctrl),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
 }
 
 _lib = None
@@ -224,6 +249,52 @@ def sph_pair_count(ctx):
     n = C.c_int64()
     _check(ctx, lib().sph_pair_count(ctx, C.byref(n)))
     return n.value
+
+
+def sph_get_clock(ctx):
+    a, b, c = C.c_int64(), C.c_double(), C.c_uint64()
+    _check(ctx, lib().sph_get_clock(ctx, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def sph_buffer_update_ex(ctx, forced_ptr, log_ptr, pid_cap):
+    cnt = sph_buffer_counts()
+    _check(ctx, lib().sph_buffer_update_ex(ctx, C.c_void_p(forced_ptr), C.c_void_p(log_ptr),
+                                           int(pid_cap), C.byref(cnt)))
+    return cnt
+
+
+def sph_set_profile_coef(ctx, buffer_id, coef):
+    a = np.ascontiguousarray(coef, dtype=np.float64)
+    _check(ctx, lib().sph_set_profile_coef(ctx, int(buffer_id), int(a.size),
+                                           a.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def sph_objective(ctx, desc, member_in_ptr, member_out_ptr, pid_cap, J_ptr):
+    _check(ctx, lib().sph_objective(ctx, C.byref(desc), C.c_void_p(member_in_ptr),
+                                    C.c_void_p(member_out_ptr), int(pid_cap),
+                                    C.c_void_p(J_ptr)))
+
+
+def sph_adjoint_workspace_size(ctx, max_nac):
+    return lib().sph_adjoint_workspace_size(ctx, int(max_nac))
+
+
+def sph_adjoint_step(ctx, pre, n_pre, desc, ctrl, lam_ptr, grad_ptr, ws_ptr, ws_bytes):
+    _check(ctx, lib().sph_adjoint_step(ctx, C.byref(pre), int(n_pre), C.byref(desc),
+                                       C.byref(ctrl), C.c_void_p(lam_ptr), C.c_void_p(grad_ptr),
+                                       C.c_void_p(ws_ptr), int(ws_bytes)))
+
+
+def make_objective(d: dict, control_buffer: int) -> sph_objective_desc:
+    o = sph_objective_desc()
+    for f in ("slab_origin", "slab_normal", "shear_dir"):
+        for k, a in enumerate(d[f]):
+            getattr(o, f)[k] = float(a)
+    o.slab_width = float(d["slab_width"])
+    o.wall_length = float(d["wall_length"])
+    o.control_buffer = int(control_buffer)
+    return o
 
 
 # ---------------------------------------------------------------------------
@@ -428,3 +499,48 @@ class Simulation:
 
     def pair_count(self):
         return sph_pair_count(self.ctx)
+
+    # -- sensitivity ------------------------------------------------------------
+    def clock(self):
+        """(step, t, next_pid) of the current state."""
+        return sph_get_clock(self.ctx)
+
+    def save(self):
+        """Device copy of the whole state (checkpoint): particle arrays in the
+        current order, their count and the clock."""
+        torch = self.torch
+        n, _ = sph_get_count(self.ctx)
+        m = max(n, 1)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        snap = dict(x=torch.zeros(3, m, **f64), v=torch.zeros(3, m, **f64),
+                    rho=torch.zeros(m, **f64), drho=torch.zeros(m, **f64),
+                    k=torch.zeros(m, **f64), eps=torch.zeros(m, **f64),
+                    tag=torch.zeros(m, **i32), pid=torch.zeros(m, **i32))
+        sph_get_particles(self.ctx, self.parts_of(snap))
+        snap["n"] = n
+        snap["clock"] = self.clock()
+        return snap
+
+    def restore(self, snap):
+        step, t, next_pid = snap["clock"]
+        sph_set_particles(self.ctx, snap["n"], next_pid, self.parts_of(snap))
+        sph_set_clock(self.ctx, step, t)
+
+    @staticmethod
+    def parts_of(snap):
+        return sph_particles(*[snap[f].data_ptr() for f in
+                               ("x", "v", "rho", "drho", "k", "eps", "tag", "pid")])
+
+    def set_profile_coef(self, buffer_id, coef):
+        sph_set_profile_coef(self.ctx, buffer_id, coef)
+
+    def objective(self, desc, J, member_in=None, member_out=None, pid_cap=0):
+        """Adds [J_Q, J_tau] of the current state to the device tensor J."""
+        sph_objective(self.ctx, desc, 0 if member_in is None else member_in.data_ptr(),
+                      0 if member_out is None else member_out.data_ptr(), pid_cap,
+                      J.data_ptr())
+
+    def buffer_update_ex(self, forced=None, log=None, pid_cap=0):
+        return sph_buffer_update_ex(self.ctx, 0 if forced is None else forced.data_ptr(),
+                                    0 if log is None else log.data_ptr(), pid_cap)
