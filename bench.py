@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+PROFILE_EVERY = 10        # steps between two event-timed steps
 
 WORKLOADS = {
     # name: (generator, kwargs, label)
@@ -43,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: --steps)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--adjoint-checkpoint", type=int, default=10)
     return ap.parse_args()
 
 
@@ -61,21 +65,24 @@ def run_gpu(case, precision, steps, warmup, torch):
         g.advance()
     torch.cuda.synchronize()
     g.pair_count()                     # reset the pair counter
-    g.profile(True)
     n_real0 = sph.sph_get_count(g.ctx)[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n_ac = 0
     real_steps = 0
-    for _ in range(steps):
+    for i in range(steps):
+        # HIP events around every kernel of one step in PROFILE_EVERY (the
+        # event records cost host time; the sampled launches give the
+        # per-kernel averages)
+        g.profile(i % PROFILE_EVERY == 0)
         info, cnt = g.advance()
         n_ac += info.n_ac
         real_steps += cnt.n_real
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    g.profile(False)
     pairs = g.pair_count()
     stats = g.kernel_stats()
-    g.profile(False)
     dt = t1 - t0
     return dict(seconds=dt, particle_steps=real_steps, n_real=n_real0, pairs=pairs,
                 n_ac=n_ac, stats=stats, sim=g)
@@ -93,6 +100,51 @@ def roofline(stats):
                      kernel=dom, avg_launch_us=round(avg_ms * 1e3, 3),
                      algorithmic_bytes_per_launch=int(bytes_per_launch),
                      launches=int(s.launches))
+
+
+def adjoint_leg(steps, K, torch):
+    """Inlet-profile sensitivity on the adjoint channel (FP64): the recorded
+    forward rollout, the checkpointed reverse sweep, and a plain forward
+    rollout of the same steps for the cost ratio."""
+    import numpy as np
+    import cases
+    from paper_2510_25702_amd import sph, sensitivity as sens
+    case = cases.make_adjoint_channel(steps=steps)
+    sim = sph.Simulation(case, precision=sph.SPH_FP64)
+    start = sim.save()
+    desc = sph.make_objective(case.objective, 1)
+    pid_cap = sens.default_pid_cap(sim, steps)
+    # plain forward steps (cell build, correction, step, buffer update)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.advance()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sim.restore(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, recs, ckpts = sens.rollout(sim, steps, desc, pid_cap, checkpoint_every=K)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    tim = {}
+    t0 = time.perf_counter()
+    g = sens.adjoint(sim, desc, recs, ckpts, pid_cap, torch.tensor([1.0, 1.0], dtype=torch.float64),
+                     steps, K, timings=tim)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    g = g.cpu().numpy()
+    J = (J / steps).cpu().numpy()
+    ms = lambda t: round(1e3 * t / steps, 4)
+    return {"workload": "adjoint_channel", "particles_total": int(case.n), "steps": steps,
+            "checkpoint_every": K, "precision": "fp64",
+            "objective": "mean over steps of J_Q (outlet slab mass flux) + J_tau (wall shear)",
+            "J": [float(J[0]), float(J[1])], "grad_norm": float(np.linalg.norm(g)),
+            "forward_ms_per_step": ms(t_plain), "recorded_forward_ms_per_step": ms(t_fwd),
+            "backward_ms_per_step": ms(t_bwd),
+            "adjoint_step_ms": ms(tim["adjoint_s"]), "recompute_ms_per_step": ms(tim["recompute_s"]),
+            "adjoint_step_over_forward": round(tim["adjoint_s"] / t_plain, 3),
+            "backward_over_forward": round(t_bwd / t_plain, 3)}
 
 
 def cpu_baseline(case, seconds):
@@ -154,6 +206,7 @@ def main():
         "pairs_per_s": round(r32["pairs"] / r32["seconds"], 1),
         "pairs_per_step": round(r32["pairs"] / args.steps, 1),
         "roofline": roof,
+        "kernels_sampled_every": PROFILE_EVERY,
         "kernels": {k: {"ms": round(v.total_ms, 3), "launches": int(v.launches),
                         "avg_us": round(1e3 * v.total_ms / max(1, v.launches), 3),
                         "GBps_algorithmic": round(v.bytes / max(1e-12, v.total_ms * 1e-3) / 1e9, 1)}
@@ -169,6 +222,8 @@ def main():
                        "pairs_per_s": round(r64["pairs"] / r64["seconds"], 1),
                        "roofline": roof64}
         out["fp32_over_fp64"] = round(value / v64, 3)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_checkpoint, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -70,10 +70,12 @@ def rollout(sim, steps, desc, pid_cap, replay=None, checkpoint_every=0, J=None):
 
 
 def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_coef=16,
-            return_state_cotangent=False):
+            return_state_cotangent=False, timings=None):
     """Reverse sweep: returns d(gJ . mean J)/da (device FP64 [n_coef]) and, on
     request, the cotangent of the start state (device FP64 [8][pid_cap], rows
-    x0 x1 x2 v0 v1 v2 rho drho, by particle id)."""
+    x0 x1 x2 v0 v1 v2 rho drho, by particle id).  `timings` (a dict) receives
+    the wall time of the segment recomputations and of the adjoint steps."""
+    import time
     torch = sim.torch
     dev = sim.device
     lam = torch.zeros(8, pid_cap, dtype=torch.float64, device=dev)
@@ -88,8 +90,10 @@ def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_c
     wq, wt = float(g[0]) / steps, float(g[1]) / steps
     K = checkpoint_every if checkpoint_every > 0 else steps
     starts = list(range(0, steps, K))
+    t_re = t_adj = 0.0
     for s0 in reversed(starts):
         s1 = min(s0 + K, steps)
+        t0 = time.perf_counter()
         sim.restore(ckpts[s0])
         pres = []
         for n in range(s0, s1):
@@ -100,6 +104,9 @@ def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_c
                 sim.correction()
                 sim.step(r.dt_adv, r.n_ac)
                 sim.buffer_update_ex(forced=r.dec, pid_cap=pid_cap)
+        sim.stream.synchronize()
+        t1 = time.perf_counter()
+        t_re += t1 - t0
         for n in reversed(range(s0, s1)):
             r = records[n]
             pre = pres[n - s0]
@@ -107,6 +114,10 @@ def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_c
                                    r.dec.data_ptr(), r.member.data_ptr(), pid_cap, wq, wt)
             sph_adjoint_step(sim.ctx, sim.parts_of(pre), pre["n"], desc, ctl, lam.data_ptr(),
                              grad.data_ptr(), ws_ptr, nbytes)
+        t_adj += time.perf_counter() - t1
+    if timings is not None:
+        timings["recompute_s"] = t_re
+        timings["adjoint_s"] = t_adj
     if return_state_cotangent:
         return grad[:n_coef], lam
     return grad[:n_coef]
