@@ -431,7 +431,7 @@ struct SeedArgs {
 
 template <int DIM, int L>
 __global__ __launch_bounds__(256) void k_adj_seed(AdjDev A, SeedArgs s, int N) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) return;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_adj_dprep(AdjDev A, int last, double ha
 
 template <int DIM, int L>
 __global__ __launch_bounds__(256) void k_adj_density(AdjDev A, int s, double kappa) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) return;
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
 // ---------------------------------------------------------------------------
 template <int DIM, int MODE, int L>
 __global__ __launch_bounds__(256) void k_adj_pressure(AdjDev A, KickArgs a, int s) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   const uint32_t ti = A.tag[i];
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(256) void k_adj_vprep(AdjDev A, double two_mu, doub
 
 template <int DIM, int L>
 __global__ __launch_bounds__(256) void k_adj_viscous(AdjDev A) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) return;
@@ -863,7 +863,7 @@ __device__ __forceinline__ bool mirror_partners(const AdjDev& A, const CorrAdjAr
 
 template <int DIM, int L>
 __global__ __launch_bounds__(256) void k_adj_moment(AdjDev A, CorrAdjArgs c) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) {
@@ -969,7 +969,7 @@ __device__ __forceinline__ double quad(const double S[6], const double r[3], dou
 
 template <int DIM, int L>
 __global__ __launch_bounds__(256) void k_adj_correction(AdjDev A, CorrAdjArgs c) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) return;

@@ -356,6 +356,29 @@ hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_
   return hipGetLastError();
 }
 
+// Error flags and the next particle id copied beside the counters
+// (counters[1032], [1033..1034]) so that one read-back returns all three.
+// and the time-step reduction of the updated state (counters[1036..1039]).
+__global__ void k_stage_status(int32_t* counters, const uint32_t* flags, const uint64_t* next_pid,
+                               const double* red) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counters[1032] = (int32_t)*flags;
+    const uint64_t np = *next_pid;
+    counters[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
+    counters[1034] = (int32_t)(uint32_t)(np >> 32);
+    for (int k = 0; k < 2; ++k) {
+      const uint64_t b = __double_as_longlong(red[k]);
+      counters[1036 + 2 * k] = (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
+      counters[1037 + 2 * k] = (int32_t)(uint32_t)(b >> 32);
+    }
+  }
+}
+
+hipError_t launch_stage_status(sph_ctx* c) {
+  k_stage_status<<<1, 64, 0, c->stream>>>(c->S.counters, c->S.flags, c->S.next_pid, c->S.red);
+  return hipGetLastError();
+}
+
 hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log,
                                 int64_t pid_cap) {
   if (c->n_total == 0) return hipSuccess;

@@ -1,8 +1,9 @@
 // Cell-linked-list build (Sec. 2.4.1/2.4.3 of the paper: global cell list,
 // rebuilt after deletion every advection step) as a counting sort on gfx950:
 //   keys + per-cell histogram (integer atomics)  ->  exclusive scan  ->
-//   scatter  ->  per-cell ordering by particle id  ->  gather of every field
-// into cell order, emitting cell-relative positions in the pair precision.
+//   scatter to the cell's slots  ->  placement of every particle at its rank
+// inside the cell (ascending source index) with all its fields, emitting
+// cell-relative positions in the pair precision.
 // Also: particle upload / download and small fill kernels.
 #include "sph_ctx.h"
 
@@ -129,9 +130,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* __restrict
   if (threadIdx.x == 0) out[n] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __restrict__ in, int n,
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t* __restrict__ in, int n,
                                                              const int32_t* __restrict__ part,
-                                                             int32_t* __restrict__ out) {
+                                                             int32_t* __restrict__ out, int zero_in) {
   __shared__ int sm[kScanThreads / kWave + 1];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -145,9 +146,45 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __re
   int off = block_excl_scan(s, sm, &total) + part[blockIdx.x];
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    if (base + q < n) out[base + q] = off;
+    if (base + q < n) {
+      out[base + q] = off;
+      if (zero_in) in[base + q] = 0;
+    }
     off += v[q];
   }
+}
+
+// K2 (grids of at most kSmallScan cells): the whole exclusive scan in one
+// workgroup, tile by tile (kScanTile counts per tile, kScanItems contiguous
+// per thread) with a running carry; clears the counts for the next build.
+constexpr int kSmallScan = 16 * kScanTile;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(int32_t* __restrict__ in, int n,
+                                                             int32_t* __restrict__ out) {
+  __shared__ int sm[kScanThreads / kWave + 1];
+  int carry = 0;
+  for (int t0 = 0; t0 < n; t0 += kScanTile) {
+    const int base = t0 + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      v[q] = (base + q < n) ? in[base + q] : 0;
+      s += v[q];
+    }
+    int total;
+    int off = block_excl_scan(s, sm, &total) + carry;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      if (base + q < n) {
+        out[base + q] = off;
+        in[base + q] = 0;
+      }
+      off += v[q];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
 }
 
 // K3a: scatter to cell-sorted positions (arbitrary order inside a cell).
@@ -158,24 +195,6 @@ __global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t*
   int k = key[i];
   if (k < 0) return;
   perm[cell_start[k] + slot[i]] = i;
-}
-
-// K3b: deterministic order inside every cell: ascending source index, i.e.
-// the (deterministic) order of the previous layout, new particles last.
-__global__ void k_sort_cells(int ncell, const int32_t* __restrict__ cell_start,
-                             int32_t* __restrict__ perm) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  int b = cell_start[c], e = cell_start[c + 1];
-  for (int a = b + 1; a < e; ++a) {
-    int ia = perm[a];
-    int q = a - 1;
-    while (q >= b && perm[q] > ia) {
-      perm[q + 1] = perm[q];
-      --q;
-    }
-    perm[q + 1] = ia;
-  }
 }
 
 // K3c: gather every field into cell order; cell-relative positions in T.
@@ -206,14 +225,24 @@ struct GatherArgs {
   uint32_t* flags;
 };
 
+// K3b: place every particle at its cell-ordered slot and copy its fields
+// there.  Inside a cell the order is ascending source index (the previous,
+// deterministic layout; new particles last): the rank of particle s is the
+// number of particles of its cell with a smaller source index, counted over
+// the cell's (arbitrarily ordered) scatter slots.
 template <typename T, int DIM>
-__global__ void k_gather(int n_out, GatherArgs<T, DIM> a) {
-  int d = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T, DIM> a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = a.cell_start[a.ncell];
-  if (d == 0 && total != n_out) atomicOr(a.flags, kFlagCountMismatch);
-  if (d >= n_out || d >= total) return;
-  int s = a.perm[d];
-  int c = a.key[s];
+  if (s == 0 && total != n_out) atomicOr(a.flags, kFlagCountMismatch);
+  if (s >= n_in) return;
+  const int c = a.key[s];
+  if (c < 0) return;
+  const int b = a.cell_start[c], e = a.cell_start[c + 1];
+  int rank = 0;
+  for (int q = b; q < e; ++q) rank += a.perm[q] < s ? 1 : 0;
+  const int d = b + rank;
+  if (d >= n_out) return;
   int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -248,23 +277,22 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   Scratch& S = c->S;
   const GridDev& g = c->grid;
   const int nc = g.ncell;
-  if (n_in > 0) {
-    k_fill_i32<<<(nc + 255) / 256, 256, 0, st>>>(S.count, nc, 0);
+  // the counts are cleared by the scan of the previous build (and at create)
+  if (n_in > 0)
     k_cell_keys<DIM><<<(int)((n_in + 255) / 256), 256, 0, st>>>(
         (int)n_in, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.tag.live(), g, S.key, S.slot,
         S.count, S.flags);
+  if (nc <= kSmallScan) {
+    k_scan_small<<<1, kScanThreads, 0, st>>>(S.count, nc, S.cell_start);
   } else {
-    k_fill_i32<<<(nc + 255) / 256, 256, 0, st>>>(S.count, nc, 0);
+    int nb = (nc + kScanTile - 1) / kScanTile;
+    k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums);
+    k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc);
+    k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start, 1);
   }
-  int nb = (nc + kScanTile - 1) / kScanTile;
-  k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums);
-  k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc);
-  k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start);
-  if (n_in > 0) {
+  if (n_in > 0)
     k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>((int)n_in, S.key, S.slot,
                                                           S.cell_start, S.perm);
-    k_sort_cells<<<(nc + 255) / 256, 256, 0, st>>>(nc, S.cell_start, S.perm);
-  }
   GatherArgs<T, DIM> a;
   a.perm = S.perm;
   a.key = S.key;
@@ -299,7 +327,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   a.volo = tp<T>(F.vol.a[0]);
   a.cello = F.cell;
   a.flags = S.flags;
-  k_gather<T, DIM><<<(int)((n_out + 255) / 256) + (n_out == 0), 256, 0, st>>>((int)n_out, a);
+  k_place<T, DIM><<<(int)((n_in + 255) / 256) + (n_in == 0), 256, 0, st>>>((int)n_in, (int)n_out, a);
   for (int k = 0; k < 3; ++k) {
     F.x[k].flip();
     F.xr[k].cur = F.x[k].cur;
@@ -350,7 +378,8 @@ hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) 
   if (nb > kScanTile) return hipErrorInvalidValue;
   k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums);
   k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n);
-  k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums, out);
+  k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(const_cast<int32_t*>(in), n, c->S.block_sums,
+                                                    out, 0);
   return hipGetLastError();
 }
 

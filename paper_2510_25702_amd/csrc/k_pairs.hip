@@ -29,12 +29,14 @@ struct CorrArgs {
   int mirror;
 };
 
-template <typename T, int DIM, int L>
+template <typename T, int DIM, int L, bool BUILD>
 __device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
-                                               const Consts<T>& C, const CorrArgs<T>& a) {
+                                               const Consts<T>& C, const CorrArgs<T>& a,
+                                               const NbrOut<T>& nb) {
   if (i >= n) return 0;
   int m_pairs = 0;
   const uint32_t ti = pc.tag[i];
+  if (BUILD) build_begin<T, DIM>(pc, i, lane, nb);
   if (!is_real(ti)) {
     if (lane == 0) {
       a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
@@ -56,10 +58,12 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
       A[5] -= Vf * r[2] * r[2];
     }
   };
-  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
+  auto pair = [&](int j, const T r[3], T r2) {
     acc(r, r2, pc.vol[j]);
     ++m_pairs;
-  });
+  };
+  if (BUILD) scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair);
+  else for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
   if (a.mirror) {
     const double xi0 = a.x[0][i], xi1 = a.x[1][i], xi2 = a.x[2][i];
     const double twoh = 2.0 * C.h;
@@ -120,10 +124,15 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   return m_pairs;
 }
 
-template <typename T, int DIM, int L>
-__global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = correction_body<T, DIM, L>(g / L, g % L, n, pc, C, a);
+template <typename T, int DIM, int L, bool BUILD>
+__global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
+                                                    NbrOut<T> nb) {
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (BUILD && g == 0) {
+    nb.stale[0] = 0;
+    nb.stale[1] = 0;
+  }
+  const int m = correction_body<T, DIM, L, BUILD>(g / L, g % L, n, pc, C, a, nb);
   count_pairs(pc.pairs, m);
 }
 
@@ -299,7 +308,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
 
 template <typename T, int DIM, int TURB, int L>
 __global__ __launch_bounds__(256) void k_advection(int n, PairCtx<T> pc, Consts<T> C, AdvArgs<T> a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int m = advection_body<T, DIM, TURB, L>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
@@ -320,6 +329,8 @@ struct PressArgs {
   const double* x[3];
   double* xo[3];
   T* xro[3];
+  const T* xrb[3];          // positions at the neighbour-list build (NULL: no list)
+  uint32_t* stale_w;        // outgrown-list word of the next positions
   const uint32_t* pid;
   const BufDev* bufs;
   const int32_t* bidx;
@@ -427,6 +438,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   const int c = pc.cell[i];
   const int cc3[3] = {c % pc.nx, (c / pc.nx) % pc.ny, c / (pc.nx * pc.ny)};
   bool bad = false;
+  double d2 = 0.0;   // displacement since the neighbour-list build
   for (int k = 0; k < 3; ++k) {
     if (k < DIM) {
       const T vt = (T)vn[k];
@@ -435,19 +447,26 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       a.xo[k][i] = xn;
       const double rel = xn - (C.grid.lo[k] + (double)cc3[k] * C.grid.cs);
       if (!(rel >= -C.skin && rel <= C.grid.cs + C.skin)) bad = true;
+      if (a.xrb[0]) {
+        const double dd = rel - (double)a.xrb[k][i];
+        d2 += dd * dd;
+      }
       a.xro[k][i] = (T)rel;
     } else {
       a.xo[k][i] = xd[k];
       a.xro[k][i] = pc.xr[k][i];
     }
   }
+  if (a.xrb[0] && !(d2 <= C.skin * C.skin)) atomicOr(a.stale_w, 1u);
   if (bad) atomicOr(a.flags, kFlagSkin);
   return m_pairs;
 }
 
 template <typename T, int DIM, int MODE, int L>
 __global__ __launch_bounds__(256) void k_pressure(int n, PairCtx<T> pc, Consts<T> C, PressArgs<T> a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  // an outgrown list stays outgrown for the rest of the step
+  if (g == 0 && a.stale_w && pc.stale && *pc.stale) atomicOr(a.stale_w, 1u);
   const int m = pressure_body<T, DIM, MODE, L>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
@@ -477,7 +496,7 @@ struct DensArgs {
 template <typename T, int DIM, int TURB, int L>
 __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T> C,
                                                  DensArgs<T> a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int i = g / L, lane = g % L;
   long long cnt = 0;
   if (i < n) {
@@ -553,11 +572,14 @@ __global__ void k_prepare_pv(int n, Consts<T> C, const double* rho, const T* kk,
 // K11: max |v|^2, max nu_t over real particles and a non-finite flag.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_reduce_part(int n, const T* v0, const T* v1,
+__global__ __launch_bounds__(256) void k_reduce_part(int n, const int32_t* n_extra, int n_max,
+                                                     const T* v0, const T* v1,
                                                      const T* v2, const double* rho,
                                                      const T* nut, const uint32_t* tag,
                                                      int turb, double* part) {
   __shared__ double sm[2][256 / kWave];
+  // slots: n, plus the particles the buffer update just appended
+  if (n_extra) n = min(n + *n_extra, n_max);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double a = 0.0, b = 0.0;
   if (i < n && is_real(tag[i])) {
@@ -582,7 +604,53 @@ __global__ __launch_bounds__(256) void k_reduce_part(int n, const T* v0, const T
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(int nb, const double* part, double* out) {
+// K11 after a buffer update, in one launch: max |v|^2 and max nu_t of the
+// updated state (non-negative doubles: their bit patterns order like the
+// values, so integer atomic maxima give the exact, order-independent result),
+// the error flags and the next particle id, all staged beside the counters
+// (counters[1032..1039]) for the update's single read-back.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* counters,
+                                                     const T* v0, const T* v1, const T* v2,
+                                                     const double* rho, const T* nut,
+                                                     const uint32_t* tag, int turb,
+                                                     const uint32_t* flags,
+                                                     const uint64_t* next_pid) {
+  __shared__ double sm[2][256 / kWave];
+  n = min(n + counters[1024], n_max);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (i < n && is_real(tag[i])) {
+    const double x = v0[i], y = v1[i], z = v2[i];
+    a = (x * x + y * y) + z * z;
+    const double r = rho[i];
+    if (!(a == a) || !(r == r) || isinf(a) || isinf(r)) a = INFINITY;
+    if (turb && (double)nut[i] > 0.0) b = (double)nut[i];   // never -0.0
+  }
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) { sm[0][wid] = a; sm[1][wid] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      a = fmax(a, sm[0][w]);
+      b = fmax(b, sm[1][w]);
+    }
+    unsigned long long* m = reinterpret_cast<unsigned long long*>(counters + 1036);
+    atomicMax(m, (unsigned long long)__double_as_longlong(a));
+    atomicMax(m + 1, (unsigned long long)__double_as_longlong(b));
+    atomicOr(reinterpret_cast<unsigned int*>(counters + 1032), *flags);
+    if (blockIdx.x == 0) {
+      const uint64_t np = *next_pid;
+      counters[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
+      counters[1034] = (int32_t)(uint32_t)(np >> 32);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(int nb, const double* part, double* out,
+                                                      const uint32_t* flags) {
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < nb; q += blockDim.x) {
     a = fmax(a, part[2 * q]);
@@ -601,6 +669,8 @@ __global__ __launch_bounds__(256) void k_reduce_final(int nb, const double* part
     }
     out[0] = a;
     out[1] = b;
+    // the error flags travel with the maxima (one read-back per step)
+    reinterpret_cast<uint32_t*>(out + 2)[0] = *flags;
   }
 }
 
@@ -665,12 +735,11 @@ inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
 // Lanes per particle of the neighbour passes: enough wavefronts to hide the
 // latency of the candidate loads on 256 CUs at small particle counts, one
 // lane per particle once the grid alone fills the machine (measured on
-// MI355X: 2D, 57k particles: L = 8 takes 0.47x the time of L = 1; 640k
-// and 2.56M particles: L = 1 is fastest).
+// MI355X, 2D: at 57k particles L = 4 is fastest, 0.55x the step time of
+// L = 1; at 640k and 2.56M particles L = 1 is fastest).
 inline int team_lanes(const sph_ctx* c) {
   if (c->team_override > 0) return c->team_override;
   const int64_t n = c->n_total;
-  if (n <= 120000) return 8;
   if (n <= 260000) return 4;
   if (n <= 450000) return 2;
   return 1;
@@ -687,17 +756,34 @@ inline int team_lanes(const sph_ctx* c) {
 template <typename T, int DIM>
 hipError_t correction_impl(sph_ctx* c) {
   Consts<T> C = make_consts<T>(c);
-  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  c->nbr_valid = false;
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);   // stencil: no list yet
   CorrArgs<T> a;
   for (int k = 0; k < 3; ++k) a.x[k] = c->F.x[k].live();
   a.bufs = c->S.bufs;
   for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(c->F.B[k]);
   a.flags = c->S.flags;
   a.mirror = c->P.obc_mode >= 3 ? 1 : 0;
+  NbrOut<T> nb;
+  nb.nbr = c->F.nbr;
+  nb.ncnt = c->F.ncnt;
+  nb.stride = c->cap;
+  nb.K = c->F.nbr_k;
+  for (int k = 0; k < 3; ++k) nb.xb[k] = tp<T>(c->F.xrb[k]);
+  nb.flags = c->S.flags;
+  nb.stale = c->S.stale;
+  const double rl = c->P.cell_size * (1.0 + 2e-6);
+  nb.rl2 = (T)(rl * rl);
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
-  SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
-  return hipGetLastError();
+  if (c->use_nbr) {
+    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, true><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb));
+  } else {
+    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, false><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb));
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && c->use_nbr) c->nbr_valid = true;
+  return e;
 }
 
 template <typename T, int DIM>
@@ -758,6 +844,16 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
     a.x[k] = F.x[k].live();
     a.xo[k] = F.x[k].other();
     a.xro[k] = tp<T>(F.xr[k].other());
+    a.xrb[k] = pc.nbr ? tp<T>(F.xrb[k]) : nullptr;
+  }
+  // outgrown-list words by sub-step parity: this pass reads the word of its
+  // positions and writes the word of the positions it produces
+  if (pc.nbr && !rates_only) {
+    pc.stale = c->S.stale + (c->substep & 1);
+    a.stale_w = c->S.stale + ((c->substep + 1) & 1);
+  } else {
+    a.stale_w = nullptr;
+    if (pc.nbr) pc.stale = c->S.stale + (c->substep & 1);
   }
   a.pid = F.pid.live();
   a.bufs = c->S.bufs;
@@ -791,6 +887,7 @@ hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
                         const sph_rates* out) {
   Consts<T> C = make_consts<T>(c);
   PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  if (pc.nbr) pc.stale = c->S.stale + (rates_only ? 0 : ((c->substep + 1) & 1));
   Fields& F = c->F;
   DensArgs<T> a;
   for (int k = 0; k < 3; ++k) a.v[k] = tp<T>(F.v[k].live());
@@ -833,18 +930,27 @@ hipError_t prepare_pv_impl(sph_ctx* c, const sph_rates* out) {
 }
 
 template <typename T>
-hipError_t reduce_impl(sph_ctx* c, double* host2) {
+hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
   Fields& F = c->F;
   const int64_t n = c->n_total;
-  const int nb = nblk(n);
-  k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, tp<T>(F.v[0].live()),
+  const int64_t n_max = after_update ? std::min<int64_t>(c->cap, n + kMaxInject) : n;
+  const int nb = nblk(n_max);
+  if (after_update) {
+    k_reduce_post<T><<<nb, 256, 0, c->stream>>>(
+        (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
+        tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
+        c->S.flags, c->S.next_pid);
+    return hipGetLastError();
+  }
+  k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, after_update ? c->S.counters + 1024 : nullptr,
+                                               (int)n_max, tp<T>(F.v[0].live()),
                                                tp<T>(F.v[1].live()), tp<T>(F.v[2].live()),
                                                F.rho.live(), tp<T>(F.nut.live()), F.tag.live(),
                                                c->P.turbulence, c->S.red + 4);
-  k_reduce_final<<<1, 256, 0, c->stream>>>(nb, c->S.red + 4, c->S.red);
+  k_reduce_final<<<1, 256, 0, c->stream>>>(nb, c->S.red + 4, c->S.red, c->S.flags);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return hipMemcpyAsync(host2, c->S.red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess || !host2) return e;
+  return hipMemcpyAsync(host2, c->S.red, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
 }
 
 template <typename T, int DIM>
@@ -885,8 +991,9 @@ hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out) {
                                     : prepare_pv_impl<float>(c, out);
 }
 
-hipError_t launch_reduce(sph_ctx* c, double* host2) {
-  return c->P.precision == SPH_FP64 ? reduce_impl<double>(c, host2) : reduce_impl<float>(c, host2);
+hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update) {
+  return c->P.precision == SPH_FP64 ? reduce_impl<double>(c, host2, after_update)
+                                    : reduce_impl<float>(c, host2, after_update);
 }
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }

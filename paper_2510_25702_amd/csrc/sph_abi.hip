@@ -60,7 +60,7 @@ const char* validate(const sph_params* P, const sph_buffer_desc* B, int32_t nbuf
   if (!(P->cell_size >= 2.0 * P->h)) return "cell_size must be >= 2h";
   if (!(P->cfl_adv > 0) || !(P->cfl_ac > 0) || !(P->u_ref > 0)) return "cfl_adv, cfl_ac, u_ref must be > 0";
   if (P->turbulence && (!(P->k_floor > 0) || !(P->eps_floor > 0))) return "k/eps floors must be > 0";
-  if (P->capacity <= 0 || P->capacity > (int64_t)INT32_MAX / 2) return "capacity out of range";
+  if (P->capacity <= 0 || P->capacity >= ((int64_t)1 << kNbrIdxBits)) return "capacity out of range";
   for (int k = 0; k < P->dim; ++k)
     if (!(P->hi[k] - P->lo[k] >= 3.0 * P->cell_size)) return "grid must span >= 3 cells per axis";
   int64_t ncell = 1;
@@ -161,7 +161,7 @@ struct Plan {
       off_nut[2], off_tag[2], off_pid[2], off_p[2], off_vol[2], off_B[6], off_anu[3], off_cell,
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
-      off_bidx;
+      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale;
   int n_cand;
 };
 
@@ -191,6 +191,9 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   for (int k = 0; k < 6; ++k) pl->off_B[k] = L.take(C * sT);
   for (int k = 0; k < 3; ++k) pl->off_anu[k] = L.take(C * sT);
   pl->off_cell = L.take(C * 4);
+  pl->off_nbr = L.take(C * 4 * (size_t)(P->dim == 2 ? kNbrMax2 : kNbrMax3));
+  pl->off_ncnt = L.take(C * 4);
+  for (int k = 0; k < 3; ++k) pl->off_xrb[k] = L.take(C * sT);
   pl->off_key = L.take(C * 4);
   pl->off_slot = L.take(C * 4);
   pl->off_perm = L.take(C * 4);
@@ -205,6 +208,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_inji = L.take((size_t)kMaxInject * 4);
   pl->off_counters = L.take(1040 * 4);
   pl->off_flags = L.take(4);
+  pl->off_stale = L.take(8);
   pl->off_red = L.take((C / 256 + 8) * 2 * 8 + 64);
   pl->off_pairs = L.take(sizeof(long long) * kPairShards * kPairShardStride);
   pl->off_npid = L.take(8);
@@ -302,6 +306,7 @@ sph_status check_flags(sph_ctx* c, uint32_t f) {
   if (f & kFlagCapacity) return fail(c, SPH_E_CAPACITY, "particle capacity / injection limit exceeded");
   if (f & kFlagOutOfGrid) return fail(c, SPH_E_NUMERIC, "particle outside the cell grid");
   if (f & kFlagSkin) return fail(c, SPH_E_NUMERIC, "particle moved beyond the cell skin in one step");
+  if (f & kFlagNbrOverflow) return fail(c, SPH_E_NUMERIC, "neighbour list overflow");
   if (f & kFlagCountMismatch) return fail(c, SPH_E_NUMERIC, "cell count mismatch");
   if (f & kFlagNonFinite) return fail(c, SPH_E_NUMERIC, "non-finite value");
   return SPH_OK;
@@ -370,6 +375,11 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   for (int k = 0; k < 6; ++k) F.B[k] = w + pl.off_B[k];
   for (int k = 0; k < 3; ++k) F.anu[k] = w + pl.off_anu[k];
   F.cell = (int32_t*)(w + pl.off_cell);
+  F.nbr = (uint32_t*)(w + pl.off_nbr);
+  F.ncnt = (int32_t*)(w + pl.off_ncnt);
+  for (int k = 0; k < 3; ++k) F.xrb[k] = w + pl.off_xrb[k];
+  F.nbr_k = params->dim == 2 ? kNbrMax2 : kNbrMax3;
+  if (const char* nl = std::getenv("SPHX_NBR_LIST")) c->use_nbr = std::atoi(nl) != 0;
   Scratch& S = c->S;
   S.key = (int32_t*)(w + pl.off_key);
   S.slot = (int32_t*)(w + pl.off_slot);
@@ -384,6 +394,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   S.inj_idx = (int32_t*)(w + pl.off_inji);
   S.counters = (int32_t*)(w + pl.off_counters);
   S.flags = (uint32_t*)(w + pl.off_flags);
+  S.stale = (uint32_t*)(w + pl.off_stale);
   S.red = (double*)(w + pl.off_red);
   S.pairs = (long long*)(w + pl.off_pairs);
   S.next_pid = (uint64_t*)(w + pl.off_npid);
@@ -440,6 +451,8 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (e == hipSuccess && !cand.empty())
     e = hipMemcpyAsync(S.cand_cells, cand.data(), cand.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.stale, 0, 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.count, 0, (size_t)c->grid.ncell * 4, st);
   if (e == hipSuccess)
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
@@ -491,6 +504,7 @@ sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph
     if (tag_kind(t) <= kBuffer) real++;
     if (tag_kind(t) == kDead) dead++;
   }
+  c->red_valid = false;
   c->n_total = n;
   c->n_alive = n - dead;
   c->n_real = real;
@@ -541,6 +555,7 @@ sph_status sph_build_cells(sph_ctx* c) {
   c->cells_valid = true;
   c->moved = false;
   c->B_valid = false;
+  c->nbr_valid = false;
   return SPH_OK;
 }
 
@@ -561,19 +576,27 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
   if (!c->cells_valid || c->moved || !c->B_valid)
     return fail(c, SPH_E_STATE, "sph_step needs sph_build_cells and sph_correction first");
   if (ctrl && ctrl->dt_adv > 0 && ctrl->n_ac < 1) return fail(c, SPH_E_ARG, "ctrl->n_ac must be >= 1");
-  double* host = (double*)c->pinned;
-  profile_launch(c, SPH_K_REDUCE);
-  hipError_t e = launch_reduce(c, host);
-  prof_end(c);
-  if (e != hipSuccess) return hip_fail(c, e, "reduce");
-  HIPCHK(c, hipMemcpyAsync((char*)c->pinned + 64, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream),
-         "flags");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "step sync");
-  if (c->prof.on) resolve_events(c);
-  uint32_t flags = *(uint32_t*)((char*)c->pinned + 64);
-  sph_status fs = check_flags(c, flags);
-  if (fs != SPH_OK) return fs;
-  const double v2max = host[0], nutmax = host[1];
+  double v2max, nutmax;
+  hipError_t e;
+  if (c->red_valid) {
+    // reduced, and flags checked, by the buffer update that produced this state
+    v2max = c->red_v2;
+    nutmax = c->red_nut;
+  } else {
+    double* host = (double*)c->pinned;
+    profile_launch(c, SPH_K_REDUCE);
+    e = launch_reduce(c, host);
+    prof_end(c);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "step sync");
+    if (c->prof.on) resolve_events(c);
+    uint32_t flags = *(uint32_t*)(host + 2);
+    sph_status fs = check_flags(c, flags);
+    if (fs != SPH_OK) return fs;
+    v2max = host[0];
+    nutmax = host[1];
+  }
+  c->red_valid = false;
   if (!std::isfinite(v2max) || !std::isfinite(nutmax))
     return fail(c, SPH_E_NUMERIC, "non-finite velocity or density");
   const sph_params& P = c->P;
@@ -603,6 +626,7 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
     c->F.nut.flip();
   }
   for (int s = 0; s < n_ac; ++s) {
+    c->substep = s;
     profile_launch(c, SPH_K_PRESSURE);
     e = launch_pressure(c, dt, false, nullptr);
     prof_end(c);
@@ -649,13 +673,13 @@ sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint3
   prof_end(c);
   if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
   char* hb = (char*)c->pinned;
+  c->red_valid = false;
+  HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
   HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4, hipMemcpyDeviceToHost, c->stream), "counts");
-  HIPCHK(c, hipMemcpyAsync(hb + 4200, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream), "flags");
-  HIPCHK(c, hipMemcpyAsync(hb + 4208, c->S.next_pid, 8, hipMemcpyDeviceToHost, c->stream), "pid");
   HIPCHK(c, hipStreamSynchronize(c->stream), "buffer sync");
   if (c->prof.on) resolve_events(c);
   const int32_t* cnt = (const int32_t*)hb;
-  uint32_t flags = *(uint32_t*)(hb + 4200);
+  uint32_t flags = (uint32_t)cnt[1032];
   if (flags & kFlagCapacity) {
     // nothing was applied: clear the flag so that the state stays usable
     uint32_t zero = 0;
@@ -665,9 +689,15 @@ sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint3
                                        ? "more injections than SPH_MAX_INJECT in one update"
                                        : "particle capacity exceeded");
   }
+  {
+    uint64_t b0 = (uint64_t)(uint32_t)cnt[1036] | ((uint64_t)(uint32_t)cnt[1037] << 32);
+    uint64_t b1 = (uint64_t)(uint32_t)cnt[1038] | ((uint64_t)(uint32_t)cnt[1039] << 32);
+    std::memcpy(&c->red_v2, &b0, 8);
+    std::memcpy(&c->red_nut, &b1, 8);
+  }
   int64_t n_inj = cnt[1024], n_del = 0;
   for (int b = 0; b < 256; ++b) n_del += cnt[512 + b];
-  c->next_pid = *(uint64_t*)(hb + 4208);
+  c->next_pid = (uint64_t)(uint32_t)cnt[1033] | ((uint64_t)(uint32_t)cnt[1034] << 32);
   c->n_total += n_inj;
   c->n_alive += n_inj - n_del;
   c->n_real += n_inj - n_del;
@@ -681,7 +711,9 @@ sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint3
     out->n_real = c->n_real;
     out->n_total = c->n_alive;
   }
-  return check_flags(c, flags);
+  sph_status fs = check_flags(c, flags);
+  c->red_valid = fs == SPH_OK;
+  return fs;
 }
 
 sph_status sph_buffer_decisions(sph_ctx* c, uint32_t* dec) {
@@ -821,6 +853,7 @@ sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
   c->F.vol.flip();
   HIPCHK(c, adjoint_snap_advection(c, ws, N), "adjoint snapshot");
   for (int s = 0; s < N; ++s) {
+    c->substep = s;
     HIPCHK(c, launch_pressure(c, dt, false, nullptr), "pressure");
     HIPCHK(c, adjoint_snap_pressure(c, ws, N, s), "adjoint snapshot");
     HIPCHK(c, launch_density(c, dt, s == N - 1, false, nullptr), "density");

@@ -36,6 +36,11 @@ struct Fields {
   void* B[6];              // symmetric correction matrix (pair precision)
   void* anu[3];            // viscous acceleration of the advection step
   int32_t* cell;           // build-time cell id per particle
+  // per-step neighbour list (radius = cell size), built with B
+  uint32_t* nbr;           // [K][cap] j | stencil offset code << 27
+  int32_t* ncnt;           // [cap] entries of particle i
+  void* xrb[3];            // cell-relative positions at the list build
+  int nbr_k;               // K
 };
 
 struct Scratch {
@@ -52,6 +57,7 @@ struct Scratch {
   int32_t* inj_idx;        // [kMaxInject]
   int32_t* counters;       // [4 * 256 + 8] per-buffer counts + misc
   uint32_t* flags;         // [1] error flags
+  uint32_t* stale;         // [2] neighbour list outgrown (by sub-step parity)
   double* red;             // reduction partials
   long long* pairs;        // [1] pair counter
   uint64_t* next_pid;      // [1]
@@ -98,6 +104,11 @@ struct sph_ctx {
   int pv_half = 0;
   uint32_t* pinned = nullptr;   // host staging (pinned)
   int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
+  bool use_nbr = true;          // neighbour passes read the per-step list
+  bool nbr_valid = false;       // the list matches the current cell build
+  int substep = 0;              // acoustic sub-step being launched
+  bool red_valid = false;       // red_v2 / red_nut hold the reduction of the current state
+  double red_v2 = 0.0, red_nut = 0.0;
   std::string err;
   sphx::Profile prof;
 };
@@ -111,7 +122,10 @@ hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src)
 hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst);
 hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out);
 hipError_t launch_correction(sph_ctx* c);
-hipError_t launch_reduce(sph_ctx* c, double* out_host4);
+// time-step reduction (max |v|^2, max nu_t, flags) into S.red[0..2], and
+// into host memory when out_host3 is given; after_update also covers the
+// particles the last buffer update appended
+hipError_t launch_reduce(sph_ctx* c, double* out_host3, bool after_update = false);
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
                             const sph_rates* out);
 hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rates* out);
@@ -122,6 +136,7 @@ hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_
                                 int64_t pid_cap = 0);
 hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log, int64_t pid_cap);
 hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots = false);
+hipError_t launch_stage_status(sph_ctx* c);
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs);
 hipError_t launch_export_B(sph_ctx* c, double* B);

@@ -11,6 +11,10 @@ namespace sphx {
 constexpr int kMaxBuf = 32;
 constexpr int kMaxInject = 4096;
 constexpr int kWave = 64;
+constexpr int kNbrMax2 = 64;            // neighbour-list entries per particle (2D)
+constexpr int kNbrMax3 = 256;           // (3D)
+constexpr int kNbrIdxBits = 27;         // list entry = j | stencil offset code << 27
+constexpr uint32_t kNbrIdxMask = (1u << kNbrIdxBits) - 1u;
 constexpr int kPairShards = 64;        // pair counters, one per 128-byte line
 constexpr int kPairShardStride = 16;    // long longs between two counters
 
@@ -25,7 +29,7 @@ enum : uint32_t { kDecNone = 0, kDecRelabel = 1, kDecInject = 2, kDecDelete = 3,
 // error flags raised by kernels (device word, read at synchronisation points)
 enum : uint32_t { kFlagOutOfGrid = 1u, kFlagSkin = 2u, kFlagNonFinite = 4u,
                   kFlagInjectOverflow = 8u, kFlagCapacity = 16u,
-                  kFlagCountMismatch = 32u };
+                  kFlagCountMismatch = 32u, kFlagNbrOverflow = 64u };
 
 __host__ __device__ inline uint32_t tag_kind(uint32_t t) { return t & 3u; }
 __host__ __device__ inline uint32_t tag_bid(uint32_t t) { return (t >> 8) & 0xFFu; }
@@ -153,6 +157,22 @@ __device__ inline double profile_speed(int dim, const BufDev& b, const double y[
   }
   if (b.noise_amp != 0.0) u *= 1.0 + b.noise_amp * counter_uniform(seed, pid, step, 0);
   return u * buffer_ramp(b, t);
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block order.  Workgroups of a launch are dealt to the 8 XCDs in
+// turn (block b runs on XCD b mod 8), each XCD with its own L2.  Mapping the
+// hardware block id to a logical one so that each XCD receives one
+// contiguous range of logical blocks keeps neighbouring cells (whose
+// particles re-read each other's fields) in the same L2.  A bijection on
+// [0, nblocks).
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b % kXcds, q = b / kXcds;
+  const int per = nb / kXcds, rem = nb % kXcds;
+  return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
 }
 
 // ---------------------------------------------------------------------------

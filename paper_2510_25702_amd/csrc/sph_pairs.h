@@ -22,6 +22,10 @@ struct PairCtx {
   int nx, ny;
   T csz, rc2, inv_h, kf;
   long long* pairs;   // directed pairs counter (NULL: not counted)
+  const uint32_t* nbr;  // per-step neighbour list (NULL: scan the cell stencil)
+  const int32_t* ncnt;
+  int64_t nstride;
+  const uint32_t* stale;  // non-zero: the list no longer covers the positions
 };
 
 // Sum over the L lanes of a team (butterfly: the same order in every run).
@@ -56,10 +60,59 @@ __device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
 // 3^DIM build cells around i's cell; r = x_i - x_j from cell-relative
 // positions: r = (xr_i - xr_j) - (cell_j - cell_i) * cs.
 // A team of L consecutive lanes shares particle i: lane l visits the
-// candidates l, l + L, l + 2L, ... of every row.
+// candidates l, l + L, l + 2L, ... .  The candidates are taken kUnroll at a
+// time: their positions are loaded together before any is tested, so that
+// the loads of one batch are in flight at once.
+// With a neighbour list (built with B after the cell build, radius = cell
+// size) the candidates are its entries, in the same order as the stencil
+// scan: the same pairs are visited in the same order.  The list covers every
+// pair within 2h while no particle has moved more than (cell size - 2h) / 2
+// since it was built; the pressure pass flags the step's list as outgrown
+// otherwise, and the later passes of the step scan the stencil instead.
+constexpr int kUnroll = 4;
+
+// Stencil offset code of a list entry: (dx+1) + 3 (dy+1) + 9 (dz+1).
+__device__ __forceinline__ uint32_t nbr_code(int dx, int dy, int dz) {
+  return (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+}
+
 template <typename T, int DIM, int L, typename Fn>
 __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int lane,
                                               const T xi[3], Fn&& fn) {
+  if (pc.nbr && !(pc.stale && *pc.stale)) {
+    const int cnt = pc.ncnt[i];
+    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      uint32_t e[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = kb + u * L;
+        e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
+      }
+      T q0[kUnroll], q1[kUnroll], q2[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = (int)(e[u] & kNbrIdxMask);
+        q0[u] = pc.xr[0][j];
+        q1[u] = pc.xr[1][j];
+        q2[u] = DIM == 3 ? pc.xr[2][j] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (kb + u * L >= cnt) break;
+        const int j = (int)(e[u] & kNbrIdxMask);
+        const int code = (int)(e[u] >> kNbrIdxBits);
+        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+        T r[3];
+        r[0] = (xi[0] - q0[u]) + (-T(dx) * pc.csz);
+        r[1] = (xi[1] - q1[u]) + (-T(dy) * pc.csz);
+        r[2] = DIM == 3 ? (xi[2] - q2[u]) + (-T(dz) * pc.csz) : T(0);
+        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                              : r[0] * r[0] + r[1] * r[1];
+        if (r2 < pc.rc2) fn(j, r, r2);
+      }
+    }
+    return;
+  }
   const int c = pc.cell[i];
   const int cx = c % pc.nx;
   const int cyz = c / pc.nx;
@@ -74,18 +127,132 @@ __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int l
       const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
                 j3 = pc.cs[base + 2];
       const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
-      for (int j = j0 + lane; j < j3; j += L) {
-        const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
-        T r[3];
-        r[0] = (xi[0] - pc.xr[0][j]) + ox;
-        r[1] = (xi[1] - pc.xr[1][j]) + oy;
-        r[2] = DIM == 3 ? (xi[2] - pc.xr[2][j]) + oz : T(0);
-        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
-                              : r[0] * r[0] + r[1] * r[1];
-        if (r2 < pc.rc2 && j != i) fn(j, r, r2);
+      for (int jb = j0 + lane; jb < j3; jb += kUnroll * L) {
+        T q0[kUnroll], q1[kUnroll], q2[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L;
+          const int js = j < j3 ? j : jb;
+          q0[u] = pc.xr[0][js];
+          q1[u] = pc.xr[1][js];
+          q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L;
+          if (j >= j3) break;
+          const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
+          T r[3];
+          r[0] = (xi[0] - q0[u]) + ox;
+          r[1] = (xi[1] - q1[u]) + oy;
+          r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
+          const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                : r[0] * r[0] + r[1] * r[1];
+          if (r2 < pc.rc2 && j != i) fn(j, r, r2);
+        }
       }
     }
   }
+}
+
+// Output of a neighbour-list build.
+template <typename T>
+struct NbrOut {
+  uint32_t* nbr;
+  int32_t* ncnt;
+  int64_t stride;
+  int K;
+  T* xb[3];
+  uint32_t* flags;
+  uint32_t* stale;
+  T rl2;
+};
+
+// Cell-stencil scan of particle i that also writes its neighbour list: every
+// j != i with |r_ij|^2 < rl2 (rl = cell size, a little above to cover
+// rounding), in stencil order.  A team of L lanes scans a row together (lane
+// l takes every L-th candidate, in the order of for_neighbors) and appends
+// the accepted candidates in candidate order with a wavefront ballot, so the
+// list order does not depend on L.  fn(j, r, r2) is called for the pairs
+// within 2h, as for_neighbors calls it.
+template <typename T, int DIM, int L, typename Fn>
+__device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane, const T xi[3],
+                                           const NbrOut<T>& o, Fn&& fn) {
+  const int wl = (int)(threadIdx.x & (kWave - 1));
+  const int team0 = wl - lane;   // first lane of the team in the wavefront
+  const int c = pc.cell[i];
+  const int cx = c % pc.nx;
+  const int cyz = c / pc.nx;
+  const int cy = cyz % pc.ny;
+  const int cz = cyz / pc.ny;
+  constexpr int zr = DIM == 3 ? 1 : 0;
+  int cnt = 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx;
+      const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
+                j3 = pc.cs[base + 2];
+      const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      // the same trip count for every lane of the team
+      for (int jb = j0; jb < j3; jb += kUnroll * L) {
+        T q0[kUnroll], q1[kUnroll], q2[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L + lane;
+          const int js = j < j3 ? j : jb;
+          q0[u] = pc.xr[0][js];
+          q1[u] = pc.xr[1][js];
+          q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L + lane;
+          const int dx = j < j1 ? -1 : (j < j2 ? 0 : 1);
+          const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
+          T r[3];
+          r[0] = (xi[0] - q0[u]) + ox;
+          r[1] = (xi[1] - q1[u]) + oy;
+          r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
+          const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                : r[0] * r[0] + r[1] * r[1];
+          const bool in = j < j3 && j != i;
+          const bool acc = in && r2 < o.rl2;
+          int off = 0, tot = acc ? 1 : 0;
+          if (L > 1) {
+            const unsigned long long m = __ballot(acc);
+            const unsigned long long tm = (m >> team0) & ((1ull << L) - 1ull);
+            off = __popcll(tm & ((1ull << lane) - 1ull));
+            tot = __popcll(tm);
+          }
+          if (acc && cnt + off < o.K)
+            o.nbr[(int64_t)(cnt + off) * o.stride + i] =
+                (uint32_t)j | (nbr_code(dx, dy, dz) << kNbrIdxBits);
+          cnt += tot;
+          if (in && r2 < pc.rc2) fn(j, r, r2);
+        }
+      }
+    }
+  if (lane == 0) {
+    if (cnt > o.K) atomicOr(o.flags, kFlagNbrOverflow);
+    o.ncnt[i] = cnt < o.K ? cnt : o.K;
+  }
+}
+
+// Start of a list build for particle i: its reference position and, for
+// particles that are not real, an empty list.  Returns false for those.
+template <typename T, int DIM>
+__device__ __forceinline__ bool build_begin(const PairCtx<T>& pc, int i, int lane,
+                                            const NbrOut<T>& o) {
+  if (lane == 0) {
+    o.xb[0][i] = pc.xr[0][i];
+    o.xb[1][i] = pc.xr[1][i];
+    if (DIM == 3) o.xb[2][i] = pc.xr[2][i];
+  }
+  if (!is_real(pc.tag[i])) {
+    if (lane == 0) o.ncnt[i] = 0;
+    return false;
+  }
+  return true;
 }
 
 // B (symmetric, packed xx xy xz yy yz zz) times a vector.
@@ -224,6 +391,11 @@ inline PairCtx<T> make_pc(const sph_ctx* c, const sphx::Slot2<void>* xr, int xsl
   pc.inv_h = (T)(1.0 / c->P.h);
   pc.kf = T(0);
   pc.pairs = c->S.pairs;
+  const bool list = c->use_nbr && c->nbr_valid;
+  pc.nbr = list ? c->F.nbr : nullptr;
+  pc.ncnt = list ? c->F.ncnt : nullptr;
+  pc.nstride = c->cap;
+  pc.stale = nullptr;
   return pc;
 }
 
