@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: --steps)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device to device 5 times (HBM counter "
+                         "calibration under rocprofv3) and exit")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-checkpoint", type=int, default=10)
     return ap.parse_args()
@@ -147,6 +150,34 @@ def adjoint_leg(steps, K, torch):
             "backward_over_forward": round(t_bwd / t_plain, 3)}
 
 
+def kernel_source_hash():
+    """Digest of the HIP sources: a recorded traffic figure is used only
+    while the kernels are the ones it was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2510_25702_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or
+    None when there is none for these sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    e = rec.get("kernels", {}).get(f"{workload}/{precision}/{kernel}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
 def cpu_baseline(case, seconds):
     import oracle
     nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -180,11 +211,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20)
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n, "copies": 5}), flush=True)
+        return
     from paper_2510_25702_amd import sph
     case = make_case(args.workload)
     r32 = run_gpu(case, sph.SPH_FP32_MIXED, args.steps, args.warmup, torch)
     value = r32["particle_steps"] / r32["seconds"]
     dom, roof = roofline(r32["stats"])
+    roof["traffic"] = recorded_traffic(args.workload, dom, "fp32")
     out = {
         "metric": "particle-steps/s + neighbor pairs/s, FP32-mixed vs FP64 at stated error",
         "value": round(value, 1),

@@ -41,57 +41,41 @@ __device__ __forceinline__ void kernel_f(double r, double inv_h, double kf, doub
   fp = -1.5 * kf * inv_h * t * t;
 }
 
-// Prescribed speed of a buffer and its derivatives with respect to the two
-// transverse local coordinates and the sine coefficients (same factors as
-// profile_speed).
-__device__ inline double profile_speed_grad(int dim, const BufDev& b, const double y[3],
-                                            uint64_t seed, uint32_t pid, int64_t step, double t,
-                                            double& du1, double& du2, double dua[16]) {
+// Reverse of a prescribed velocity v = u(y(x)) n_b (same factors as
+// profile_speed): with c = n_b . lambda_v, adds c grad_x u to lx and, for the
+// control buffer, c du/da_m to abar[m * stride] (the sine coefficients).
+__device__ inline void bc_reverse(int dim, const BufDev& b, bool control, const double x[3],
+                                  double c, uint64_t seed, uint32_t pid, int64_t step, double t,
+                                  double lx[3], double* abar, int64_t stride) {
+  double y[3];
+  to_local(b, x[0], x[1], x[2], y);
   const double s = (y[1] + b.hw[0]) / (2.0 * b.hw[0]);
-  double F, dFs = 0.0, dFt = 0.0;
-  for (int m = 0; m < 16; ++m) dua[m] = 0.0;
+  double dFs = 0.0, dFt = 0.0;
+  double fac = 1.0;
+  if (b.noise_amp != 0.0) fac = 1.0 + b.noise_amp * counter_uniform(seed, pid, step, 0);
+  fac *= buffer_ramp(b, t);
   if (b.profile == kProfParabolic) {
-    F = 4.0 * b.u0 * s * (1.0 - s);
+    double F = 4.0 * b.u0 * s * (1.0 - s);
     dFs = 4.0 * b.u0 * (1.0 - 2.0 * s);
     if (dim == 3) {
       const double tt = (y[2] + b.hw[1]) / (2.0 * b.hw[1]);
       const double G = 4.0 * tt * (1.0 - tt);
       dFt = F * 4.0 * (1.0 - 2.0 * tt);
       dFs *= G;
-      F *= G;
     }
   } else if (b.profile == kProfSine) {
-    F = 4.0 * b.u0 * s * (1.0 - s);
     dFs = 4.0 * b.u0 * (1.0 - 2.0 * s);
     for (int m = 1; m <= b.n_coef; ++m) {
       const double a = (double)m * M_PI;
-      F += b.coef[m - 1] * sin(a * s);
-      dFs += b.coef[m - 1] * a * cos(a * s);
-      dua[m - 1] = sin(a * s);
+      double sn, cs;
+      sincos(a * s, &sn, &cs);
+      dFs += b.coef[m - 1] * a * cs;
+      if (control) abar[(int64_t)(m - 1) * stride] += c * sn * fac;
     }
-  } else {
-    F = b.u0;
   }
-  double fac = 1.0;
-  if (b.noise_amp != 0.0) fac = 1.0 + b.noise_amp * counter_uniform(seed, pid, step, 0);
-  fac *= buffer_ramp(b, t);
-  du1 = dFs * fac / (2.0 * b.hw[0]);
-  du2 = dim == 3 ? dFt * fac / (2.0 * b.hw[1]) : 0.0;
-  for (int m = 0; m < 16; ++m) dua[m] *= fac;
-  return F * fac;
-}
-
-// Adds c * d(u n_b)/d(x, a) for a particle whose velocity is the buffer's
-// prescribed u(y(x)) n_b: lx += c grad_x u, abar += c du/da (control buffer).
-__device__ inline void bc_reverse(int dim, const BufDev& b, bool control, const double x[3],
-                                  double c, uint64_t seed, uint32_t pid, int64_t step, double t,
-                                  double lx[3], double* abar) {
-  double y[3], du1, du2, dua[16];
-  to_local(b, x[0], x[1], x[2], y);
-  (void)profile_speed_grad(dim, b, y, seed, pid, step, t, du1, du2, dua);
+  const double du1 = dFs * fac / (2.0 * b.hw[0]);
+  const double du2 = dim == 3 ? dFt * fac / (2.0 * b.hw[1]) : 0.0;
   for (int k = 0; k < 3; ++k) lx[k] += c * (du1 * b.frame[3 + k] + du2 * b.frame[6 + k]);
-  if (control)
-    for (int m = 0; m < 16; ++m) abar[m] += c * dua[m];
 }
 
 // Frobenius product of two symmetric matrices in packed form.
@@ -172,6 +156,9 @@ struct AdjDev {
   const int32_t* cs;
   int nx, ny;
   double csz, rc2, inv_h, kf;
+  const uint32_t* nbr;       // the step's neighbour list (NULL: scan the stencil)
+  const int32_t* ncnt;
+  const uint32_t* stale;     // [2] outgrown-list words of the replayed step
   // snapshots
   double* X;                 // [(N+1)][3][cap]
   double* XR;                // [(N+1)][3][cap]
@@ -204,14 +191,49 @@ __device__ __forceinline__ void stencil_of(const AdjDev& A, int i, int& cx, int&
   cz = cyz / A.ny;
 }
 
-// Neighbours of i at the positions `xr` of a snapshot (same loop and
-// predicate as the forward passes), team of L lanes.
+// Neighbours of i at the positions `xr` of a snapshot (the same pairs as the
+// forward pass visited: the step's neighbour list while it covered every
+// sub-step of the replay, else the cell stencil), team of L lanes.
 template <int DIM, int L, typename Fn>
 __device__ __forceinline__ void adj_neighbors(const AdjDev& A, const double* const xr[3], int i,
                                               int lane, Fn&& fn) {
+  const double xi0 = xr[0][i], xi1 = xr[1][i], xi2 = DIM == 3 ? xr[2][i] : 0.0;
+  if (A.nbr && !(A.stale[0] | A.stale[1])) {
+    const int cnt = A.ncnt[i];
+    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      uint32_t e[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = kb + u * L;
+        e[u] = A.nbr[(int64_t)(k < cnt ? k : kb) * A.cap + i];
+      }
+      double q0[kUnroll], q1[kUnroll], q2[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = (int)(e[u] & kNbrIdxMask);
+        q0[u] = xr[0][j];
+        q1[u] = xr[1][j];
+        q2[u] = DIM == 3 ? xr[2][j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (kb + u * L >= cnt) break;
+        const int j = (int)(e[u] & kNbrIdxMask);
+        const int code = (int)(e[u] >> kNbrIdxBits);
+        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+        double r[3];
+        r[0] = (xi0 - q0[u]) + (-(double)dx * A.csz);
+        r[1] = (xi1 - q1[u]) + (-(double)dy * A.csz);
+        r[2] = DIM == 3 ? (xi2 - q2[u]) + (-(double)dz * A.csz) : 0.0;
+        const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                   : r[0] * r[0] + r[1] * r[1];
+        if (r2 < A.rc2) fn(j, r, r2);
+      }
+    }
+    return;
+  }
   int cx, cy, cz;
   stencil_of<DIM>(A, i, cx, cy, cz);
-  const double xi0 = xr[0][i], xi1 = xr[1][i], xi2 = DIM == 3 ? xr[2][i] : 0.0;
   constexpr int zr = DIM == 3 ? 1 : 0;
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy) {
@@ -384,9 +406,8 @@ __global__ __launch_bounds__(256) void k_adj_post(AdjDev A, PostArgs a, int N) {
         for (int k = 0; k < 3; ++k)
           xn[k] = __dsub_rn(snap3(A.X, cap, N, k)[i], __dmul_rn(b.length, b.frame[k]));
         const double c = b.frame[0] * l[3] + b.frame[1] * l[4] + b.frame[2] * l[5];
-        double ab[16] = {0};
-        bc_reverse(a.dim, b, q == a.control_q, xn, c, a.seed, p, a.step_post, a.t_post, l, ab);
-        for (int m = 0; m < 16; ++m) A.abar[(int64_t)m * cap + i] += ab[m];
+        bc_reverse(a.dim, b, q == a.control_q, xn, c, a.seed, p, a.step_post, a.t_post, l,
+                   A.abar + i, cap);
         l[3] = l[4] = l[5] = 0.0;
       }
       if (b.p_mode == kPPrescribed) l[6] = 0.0;
@@ -580,9 +601,8 @@ __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
     const double xs[3] = {snap3(A.X, cap, s, 0)[i], snap3(A.X, cap, s, 1)[i],
                           snap3(A.X, cap, s, 2)[i]};
     const double c = b.frame[0] * lv[0] + b.frame[1] * lv[1] + b.frame[2] * lv[2];
-    double ab[16] = {0};
-    bc_reverse(a.dim, b, q == a.control_q, xs, c, a.seed, A.pid[i], a.step, a.t, lx, ab);
-    for (int m = 0; m < 16; ++m) A.abar[(int64_t)m * cap + i] += ab[m];
+    bc_reverse(a.dim, b, q == a.control_q, xs, c, a.seed, A.pid[i], a.step, a.t, lx, A.abar + i,
+               cap);
     for (int k = 0; k < 3; ++k) {
       A.lx[k][i] = lx[k];
       A.lv[k][i] = 0.0;
@@ -755,6 +775,26 @@ __global__ __launch_bounds__(256) void k_adj_eos(AdjDev A, int s, double c02, do
   }
   A.lp[i] = 0.0;
   A.lV[i] = 0.0;
+}
+
+// k_adj_eos of sub-step s + 1 followed by k_adj_dprep of sub-step s (both
+// per particle, one launch).
+__global__ __launch_bounds__(256) void k_adj_eos_dprep(AdjDev A, int s1, double c02, double mass,
+                                                       double half) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  if (!is_real(A.tag[i])) {
+    A.lp[i] = 0.0;
+    A.lV[i] = 0.0;
+    A.lD[i] = 0.0;
+    return;
+  }
+  const double r = A.RH[(int64_t)s1 * A.cap + i];
+  const double lr = A.lr[i] + c02 * A.lp[i] - mass / (r * r) * A.lV[i];
+  A.lr[i] = lr;
+  A.lp[i] = 0.0;
+  A.lV[i] = 0.0;
+  A.lD[i] = 2.0 * half * lr;
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,13 +1146,29 @@ __global__ __launch_bounds__(256) void k_adj_zero_children(AdjDev A, double* lam
   for (int k = 0; k < 8; ++k) lam[(int64_t)k * A.pid_cap + cp] = 0.0;
 }
 
-// grad[m] += sum_i abar[m][i], one block per coefficient, fixed tree order.
-__global__ __launch_bounds__(256) void k_adj_grad(int n, int64_t cap, const double* abar,
-                                                  double* grad) {
+// grad[m] += sum_i abar[m][i] in a fixed order: per-block sums of all 16
+// coefficients (tree in LDS), then one block per coefficient over the blocks.
+__global__ __launch_bounds__(256) void k_adj_grad_part(int n, int64_t cap, const double* abar,
+                                                       double* part) {
+  __shared__ double sm[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  for (int m = 0; m < 16; ++m) {
+    sm[threadIdx.x] = i < n ? abar[(int64_t)m * cap + i] : 0.0;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)m * gridDim.x + blockIdx.x] = sm[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adj_grad(int nb, const double* part, double* grad) {
   __shared__ double sm[256];
   const int m = blockIdx.x;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += abar[(int64_t)m * cap + i];
+  for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)m * nb + b];
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -1175,6 +1231,9 @@ AdjDev make_adj(sph_ctx* c, char* ws, const AdjLayout& L, int n, int64_t pid_cap
   A.nx = c->grid.n[0];
   A.ny = c->grid.n[1];
   A.csz = c->P.cell_size;
+  A.nbr = c->use_nbr && c->nbr_valid ? c->F.nbr : nullptr;
+  A.ncnt = c->F.ncnt;
+  A.stale = c->S.stale;
   const double rc = 2.0 * c->P.h;
   A.rc2 = rc * rc;
   A.inv_h = 1.0 / c->P.h;
@@ -1306,7 +1365,8 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
   ka.dt = dt;
   const double kappa = 1.0 / (2.0 * P.rho0 * P.c0);
   for (int s = N - 1; s >= 0; --s) {
-    k_adj_dprep<<<nb, 256, 0, st>>>(A, s == N - 1 ? 1 : 0, 0.5 * dt);
+    if (s == N - 1) k_adj_dprep<<<nb, 256, 0, st>>>(A, 1, 0.5 * dt);
+    else k_adj_eos_dprep<<<nb, 256, 0, st>>>(A, s + 1, P.c0 * P.c0, mass, 0.5 * dt);
     ADJ_TEAM(Lt, k_adj_density<DIM, TL><<<nblk_a((int64_t)n * TL), 256, 0, st>>>(A, s, kappa));
     k_adj_kick<DIM><<<nb, 256, 0, st>>>(A, ka, s);
     switch (P.obc_mode) {
@@ -1315,8 +1375,8 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
       case 3: ADJ_TEAM(Lt, k_adj_pressure<DIM, 3, TL><<<nblk_a((int64_t)n * TL), 256, 0, st>>>(A, ka, s)); break;
       default: ADJ_TEAM(Lt, k_adj_pressure<DIM, 4, TL><<<nblk_a((int64_t)n * TL), 256, 0, st>>>(A, ka, s)); break;
     }
-    k_adj_eos<<<nb, 256, 0, st>>>(A, s, P.c0 * P.c0, mass);
   }
+  k_adj_eos<<<nb, 256, 0, st>>>(A, 0, P.c0 * P.c0, mass);
   k_adj_vprep<<<nb, 256, 0, st>>>(A, 2.0 * P.rho0 * P.nu_l, 0.5 * dt);
   ADJ_TEAM(Lt, k_adj_viscous<DIM, TL><<<nblk_a((int64_t)n * TL), 256, 0, st>>>(A));
   if (P.obc_mode >= 2) {
@@ -1333,7 +1393,11 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
   }
   k_adj_finish<<<nb, 256, 0, st>>>(A, lam, mass);
   k_adj_zero_children<<<nb, 256, 0, st>>>(A, lam);
-  k_adj_grad<<<16, 256, 0, st>>>(n, c->cap, A.abar, grad);
+  // per-block partials of the gradient reuse the (consumed) sub-step
+  // density snapshots: 16 x nb doubles
+  double* gpart = A.DD;
+  k_adj_grad_part<<<nb, 256, 0, st>>>(n, c->cap, A.abar, gpart);
+  k_adj_grad<<<16, 256, 0, st>>>(nb, gpart, grad);
   return hipGetLastError();
 }
 
