@@ -150,16 +150,18 @@ def adjoint_leg(steps, K, torch):
             "backward_over_forward": round(t_bwd / t_plain, 3)}
 
 
+TRAFFIC_SOURCES = ("k_pairs.hip", "sph_pairs.h", "sph_device.h", "sph_ctx.h")
+
+
 def kernel_source_hash():
-    """Digest of the HIP sources: a recorded traffic figure is used only
-    while the kernels are the ones it was measured on."""
+    """Digest of the sources of the neighbour-pass kernels: a recorded
+    traffic figure is used only while they are the ones it was measured on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2510_25702_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 

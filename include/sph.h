@@ -219,9 +219,10 @@ sph_status sph_build_cells(sph_ctx* ctx);
 
 /* Correction matrix B_i, Eq. (equ-B-matrix), with the mirror boundary
  * treatment of Sec. 3.3 at every buffer's open face when obc_mode >= 3
- * (pair sums in the configured precision, inversion in FP64).  Requires
- * sph_build_cells since the last position change (SPH_E_STATE).
- * Asynchronous. */
+ * (pair sums in the configured precision, inversion in FP64).  Also builds
+ * the step's neighbour list (every pair within the cell size), which the
+ * later passes of the step read.  Requires sph_build_cells since the last
+ * position change (SPH_E_STATE).  Asynchronous. */
 sph_status sph_correction(sph_ctx* ctx);
 
 /* One advection step of the dual-criteria scheme (Sec. 2.3): time-step
@@ -230,7 +231,9 @@ sph_status sph_correction(sph_ctx* ctx);
  * compensation of Eq. (eq-pressure-gradient-obc-B-final) and the velocity
  * boundary condition, drift, Riemann continuity).  ctrl may be NULL
  * (adaptive step).  Requires sph_build_cells and sph_correction
- * (SPH_E_STATE).  Synchronises once to read the time-step reduction. */
+ * (SPH_E_STATE).  The time-step reduction of a state produced by
+ * sph_buffer_update was computed and read back by that update; for any
+ * other state sph_step synchronises once to read it. */
 sph_status sph_step(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* out);
 
 /* Bidirectional buffer update (Secs. 2.4.2, 2.4.3, 3.1, 3.2): relabel,
@@ -239,7 +242,9 @@ sph_status sph_step(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* out)
  * (particle tagged SPH_DEAD, dropped by the next cell build), each decided
  * from one snapshot over the particles of the buffer's local cell list.
  * Requires sph_build_cells since the last update (SPH_E_STATE).  out may be
- * NULL.  Synchronises once to read the counts. */
+ * NULL.  Synchronises once, reading back the counts, the error flags (also
+ * those raised by the kernels since the previous read-back) and the
+ * time-step reduction of the updated state for the next sph_step. */
 sph_status sph_buffer_update(sph_ctx* ctx, sph_buffer_counts* out);
 
 /* sph_buffer_update with an event log and replay, for sensitivity runs.
