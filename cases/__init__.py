@@ -398,6 +398,50 @@ def make_mixer(dp=0.005, R=0.5, Hc=0.5, a=0.1, Lin=0.2, r_out=0.1,
                           f"outlet r={r_out} Re={Re}")
 
 
+def make_duct3d(dp=0.05, L=1.0, H=0.5, W=0.3, Umax=1.0, Re=100.0, c0=10.0, seed=5,
+                steps=20, n_coef=16, amp=0.1):
+    """3D rectangular duct along x (L x H x W), three wall layers on the four
+    side faces, SINE-profile velocity inlet at x = 0 (s = y / H; the profile
+    has no z factor) with a_m ~ U[-amp, amp] (seeded), zero-pressure outlet at
+    x = L, started from u = 4 Umax s (1 - s), no start-up ramp; objective slab
+    4dp upstream of the outlet buffer, wall area 2 (H + W) L."""
+    nu = Umax * H / Re
+    P = base_params(3, dp, c0=c0, nu_l=nu, u_ref=Umax, seed=seed)
+    ext = 4 * dp
+    wt = 3 * dp
+
+    def lattice3(x0, x1, y0, y1, z0, z1):
+        xs = (np.arange(int(round(x0 / dp)), int(round(x1 / dp))) + 0.5) * dp
+        ys = (np.arange(int(round(y0 / dp)), int(round(y1 / dp))) + 0.5) * dp
+        zs = (np.arange(int(round(z0 / dp)), int(round(z1 / dp))) + 0.5) * dp
+        X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+        return np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+
+    fluid = lattice3(0.0, L, 0.0, H, 0.0, W)
+    box = lattice3(-ext, L + ext, -wt, H + wt, -wt, W + wt)
+    inner = (box[:, 1] > 0.0) & (box[:, 1] < H) & (box[:, 2] > 0.0) & (box[:, 2] < W)
+    wall = box[~inner]
+    rng = np.random.default_rng(seed)
+    coef = tuple(float(a) for a in rng.uniform(-amp, amp, n_coef))
+    Lb = 4 * dp
+    frame = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+    inlet = Buffer(1, (0.0, H / 2, W / 2), frame, Lb, (H / 2, W / 2), 0.5 * dp,
+                   vel_mode=VEL_PRESCRIBED, p_mode=P_EXTRAPOLATE, profile=PROFILE_SINE,
+                   u0=Umax, coef=coef, ramp_time=0.0)
+    outlet = Buffer(2, (L, H / 2, W / 2), ((-1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)),
+                    Lb, (H / 2, W / 2), 0.5 * dp, vel_mode=VEL_EXTRAPOLATE,
+                    p_mode=P_PRESCRIBED, p_ob=0.0)
+    s_ = fluid[:, 1] / H
+    v = np.zeros((fluid.shape[0], 3))
+    v[:, 0] = 4.0 * Umax * s_ * (1.0 - s_)
+    c = _assemble("duct3d", P, [inlet, outlet], fluid, wall, steps, v=v,
+                  note=f"3D duct {L}x{H}x{W} dp={dp} Re={Re}, sine inlet")
+    c.objective = dict(slab_origin=(L - Lb - 4 * dp, 0.0, 0.0), slab_normal=(1.0, 0.0, 0.0),
+                       slab_width=4 * dp, shear_dir=(1.0, 0.0, 0.0),
+                       wall_length=2.0 * (H + W) * L)
+    return c
+
+
 def jittered(case: Case, amp: float, seed: int = 7) -> Case:
     """Copy of ``case`` with fluid positions jittered by amp*dp (uniform)."""
     rng = np.random.default_rng(seed)

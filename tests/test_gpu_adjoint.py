@@ -324,3 +324,69 @@ def test_adjoint_full_size_against_gpu_finite_differences(sph, sens):
             Jp.append(J[1])
         fd = (Jp[0] - Jp[1]) / (2 * eps)
         assert abs(g[m] - fd) <= 1e-4 * np.abs(g).max(), (m, g[m], fd)
+
+
+def test_adjoint_3d_matches_oracle_finite_differences(sph, sens, ora):
+    # the 3D duct (sine inlet on the transverse coordinate y, four walls)
+    import torch
+    steps = 8
+    c = cases.make_duct3d(steps=steps)
+    cf = [0, 1, 4]
+    g_fd, log = ora.fd_gradient(c, steps, c.objective, BID, eps=1e-5, threads=8, coefs=cf)
+    sim = sph.Simulation(c, precision=sph.SPH_FP64)
+    pid_cap = int(c.next_pid) + 4096
+    start = sim.save()
+    recs = oracle_records(torch, sens, log, pid_cap)
+    desc = sph.make_objective(c.objective, BID)
+    J, _ = gpu_rollout(sph, sens, sim, start, desc, pid_cap, steps, recs)
+    J_o, _, _ = ora.rollout(c, steps, c.objective, replay=log, threads=8)
+    assert np.abs(J - J_o).max() <= 1e-10 * np.abs(J_o).max()
+    for k in range(2):
+        gJ = [1.0, 0.0] if k == 0 else [0.0, 1.0]
+        g = gpu_gradient(sph, sens, sim, start, desc, pid_cap, steps, recs, gJ, K=3)
+        err = rel_max(g[cf], g_fd[cf, k])
+        print(f"3D objective {k}: max rel err {err:.3e}", flush=True)
+        assert err <= 1e-4
+
+
+@pytest.mark.parametrize("field", ["x", "v", "rho"])
+def test_state_cotangent_dot_product_3d(sph, sens, field):
+    import torch
+    steps = 2
+    c = cases.make_duct3d(steps=steps)
+    sim = sph.Simulation(c, precision=sph.SPH_FP64)
+    pid_cap = int(c.next_pid) + 4096
+    start = sim.save()
+    desc = sph.make_objective(c.objective, BID)
+    _, recs = gpu_rollout(sph, sens, sim, start, desc, pid_cap, steps, None)
+    sim.restore(start)
+    J, out, ckpts = sens.rollout(sim, steps, desc, pid_cap, replay=recs, checkpoint_every=1)
+    _, lam = sens.adjoint(sim, desc, out, ckpts, pid_cap, torch.tensor([1.0, 2.0],
+                          dtype=torch.float64), steps, 1, return_state_cotangent=True)
+    lam = lam.cpu().numpy()
+    n = start["n"]
+    tag = start["tag"].cpu().numpy()[:n].view(np.uint32)
+    pid = start["pid"].cpu().numpy()[:n].view(np.uint32)
+    real = (tag & 3) <= 1
+    rng = np.random.default_rng(11)
+    rows = {"x": [0, 1, 2], "v": [3, 4, 5], "rho": [6]}[field]
+    scale = {"x": c.params["dp"] * 1e-2, "v": 0.1, "rho": 1e-3}[field]
+    delta = np.zeros((len(rows), n))
+    delta[:, real] = rng.uniform(-1, 1, (len(rows), int(real.sum()))) * scale
+    pred = sum(float(np.dot(lam[r][pid], delta[q])) for q, r in enumerate(rows))
+
+    def run(sgn, eps):
+        snap = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in start.items()}
+        d = torch.as_tensor(delta, device="cuda")
+        if field in ("x", "v"):
+            snap[field][:, :n] += sgn * eps * d
+        else:
+            snap[field][:n] += sgn * eps * d[0]
+        sim.restore(snap)
+        Jr, _, _ = sens.rollout(sim, steps, desc, pid_cap, replay=recs)
+        Jr = (Jr / steps).cpu().numpy()
+        return Jr[0] + 2.0 * Jr[1]
+    eps = 1e-4
+    fd = (run(1, eps) - run(-1, eps)) / (2 * eps)
+    print(f"3D {field}: adjoint {pred:.12e} fd {fd:.12e}", flush=True)
+    assert abs(pred - fd) <= 1e-5 * max(abs(fd), 1e-12) + 1e-12
