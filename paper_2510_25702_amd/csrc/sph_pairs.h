@@ -69,7 +69,10 @@ __device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
 // pair within 2h while no particle has moved more than (cell size - 2h) / 2
 // since it was built; the pressure pass flags the step's list as outgrown
 // otherwise, and the later passes of the step scan the stencil instead.
-constexpr int kUnroll = 4;
+#ifndef SPHX_UNROLL
+#define SPHX_UNROLL 2
+#endif
+constexpr int kUnroll = SPHX_UNROLL;
 
 // Stencil offset code of a list entry: (dx+1) + 3 (dy+1) + 9 (dz+1).
 __device__ __forceinline__ uint32_t nbr_code(int dx, int dy, int dz) {
