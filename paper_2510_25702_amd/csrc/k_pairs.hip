@@ -160,6 +160,7 @@ struct AdvArgs {
   int rates_only;
   double *o_anu, *o_gradv, *o_dk, *o_deps;
   int64_t n_out;
+  V4<T>* prec[3];   // pressure records of sub-step 0 (written)
 };
 
 template <typename T, int DIM, int TURB, int L>
@@ -174,6 +175,9 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
       if (TURB) { a.ko[i] = T(0); a.epso[i] = T(0); a.nuto[i] = T(0); }
+      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      const T Iw[6] = {T(1), T(0), T(0), T(1), T(0), T(1)};
+      write_prec<T, DIM>(a.prec, i, xw, T(0), -(T)C.Vw, Iw);
     }
     return m_pairs;
   }
@@ -301,8 +305,13 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   // first half density update of the first acoustic sub-step
   const double rho_h = rho_i + a.half_dt * (double)a.drho[i];
   a.rho[i] = rho_h;
-  a.p_out[i] = (T)eos(rho_h, k_new, C.rho0, C.c0, TURB);
-  a.vol_out[i] = (T)(C.mass / rho_h);
+  const T p_h = (T)eos(rho_h, k_new, C.rho0, C.c0, TURB);
+  const T v_h = (T)(C.mass / rho_h);
+  a.p_out[i] = p_h;
+  a.vol_out[i] = v_h;
+  T Bw[6];
+  load_B<T, DIM>(a.B, i, Bw);
+  write_prec<T, DIM>(a.prec, i, xi, p_h, v_h, Bw);
   return m_pairs;
 }
 
@@ -329,6 +338,8 @@ struct PressArgs {
   const double* x[3];
   double* xo[3];
   T* xro[3];
+  const V4<T>* prec[3];     // pressure records of the neighbours (read)
+  V4<T>* drec[2];           // continuity records of the new state (written)
   const T* xrb[3];          // positions at the neighbour-list build (NULL: no list)
   uint32_t* stale_w;        // outgrown-list word of the next positions
   const uint32_t* pid;
@@ -355,6 +366,9 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
         a.xo[k][i] = a.x[k][i];
         a.xro[k][i] = pc.xr[k][i];
       }
+      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      const T vw[3] = {T(0), T(0), T(0)};
+      write_drec<T, DIM>(a.drec, i, xw, vw, T(0), -pc.vol[i]);
     }
     return m_pairs;
   }
@@ -363,11 +377,15 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   T Bi[6];
   if (MODE >= 2) load_B<T, DIM>(a.B, i, Bi);
   T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
-  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
+  constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);
+  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec,
+                                   [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
     const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
-    const T Vj = pc.vol[j];
-    const bool wall = tag_kind(pc.tag[j]) == kWall;
+    const T volw = DIM == 2 ? q[0].d : q[1].a;
+    const bool wall = volw < T(0);
+    const T Vj = wall ? -volw : volw;
+    const T pj_rec = DIM == 2 ? q[0].c : q[0].d;
     const T gW[3] = {f * r[0], f * r[1], DIM == 3 ? f * r[2] : T(0)};
     if (MODE >= 2) {
       // (p_i B_j + p_j B_i) gradW; wall: p_w = p_i, B_w = B_i
@@ -376,10 +394,16 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       if (wall) {
         pj = pi;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) Bj[q] = Bi[q];
+        for (int k = 0; k < 6; ++k) Bj[k] = Bi[k];
       } else {
-        pj = a.p[j];
-        load_B<T, DIM>(a.B, j, Bj);
+        pj = pj_rec;
+        if (DIM == 2) {
+          Bj[0] = q[1].a; Bj[1] = q[1].b; Bj[3] = q[1].c;
+          Bj[2] = Bj[4] = Bj[5] = T(0);
+        } else {
+          Bj[0] = q[1].b; Bj[1] = q[1].c; Bj[2] = q[1].d;
+          Bj[3] = q[NR - 1].a; Bj[4] = q[NR - 1].b; Bj[5] = q[NR - 1].c;
+        }
       }
       T bj[3], bi[3];
       symv<T, DIM>(Bj, gW, bj);
@@ -389,7 +413,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       acc[1] += vpi * bj[1] + vpj * bi[1];
       acc[2] += vpi * bj[2] + vpj * bi[2];
     } else {
-      const T pj = wall ? pi : a.p[j];
+      const T pj = wall ? pi : pj_rec;
       const T w = Vj * (pi + pj);
       acc[0] += w * gW[0];
       acc[1] += w * gW[1];
@@ -438,6 +462,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   const int c = pc.cell[i];
   const int cc3[3] = {c % pc.nx, (c / pc.nx) % pc.ny, c / (pc.nx * pc.ny)};
   bool bad = false;
+  T xnew[3], vnew[3] = {T(0), T(0), T(0)};
   double d2 = 0.0;   // displacement since the neighbour-list build
   for (int k = 0; k < 3; ++k) {
     if (k < DIM) {
@@ -452,11 +477,15 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
         d2 += dd * dd;
       }
       a.xro[k][i] = (T)rel;
+      xnew[k] = (T)rel;
+      vnew[k] = vt;
     } else {
       a.xo[k][i] = xd[k];
       a.xro[k][i] = pc.xr[k][i];
+      xnew[k] = pc.xr[k][i];
     }
   }
+  write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, pc.vol[i]);
   if (a.xrb[0] && !(d2 <= C.skin * C.skin)) atomicOr(a.stale_w, 1u);
   if (bad) atomicOr(a.flags, kFlagSkin);
   return m_pairs;
@@ -491,6 +520,9 @@ struct DensArgs {
   int last;
   int rates_only;
   double* o_drho;
+  const V4<T>* drec[2];   // continuity records of the neighbours (read)
+  V4<T>* prec[3];         // pressure records of the next sub-step (written)
+  const T* B[6];
 };
 
 template <typename T, int DIM, int TURB, int L>
@@ -507,20 +539,27 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       const T pi = a.p[i];
       T sum = T(0);
       int m = 0;
-      for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
+      for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec,
+                                      [&](int j, const T r[3], T r2, const V4<T>* q) {
         const T rr = sqrt(r2);
         const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
-        const bool wall = tag_kind(pc.tag[j]) == kWall;
+        const T volw = DIM == 2 ? q[1].b : q[1].d;
+        const bool wall = volw < T(0);
+        const T Vj = wall ? -volw : volw;
         T vr, dp;
         if (wall) {
           vr = vi[0] * r[0] + vi[1] * r[1] + vi[2] * r[2];
           dp = T(0);
         } else {
-          vr = (vi[0] - a.v[0][j]) * r[0] + (vi[1] - a.v[1][j]) * r[1] +
-               (DIM == 3 ? (vi[2] - a.v[2][j]) * r[2] : T(0));
-          dp = pi - a.p[j];
+          const T vj0 = DIM == 2 ? q[0].c : q[0].d;
+          const T vj1 = DIM == 2 ? q[0].d : q[1].a;
+          const T vj2 = DIM == 2 ? T(0) : q[1].b;
+          const T pj = DIM == 2 ? q[1].a : q[1].c;
+          vr = (vi[0] - vj0) * r[0] + (vi[1] - vj1) * r[1] +
+               (DIM == 3 ? (vi[2] - vj2) * r[2] : T(0));
+          dp = pi - pj;
         }
-        sum += pc.vol[j] * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr);
+        sum += Vj * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr);
         ++m;
       });
       cnt = m;
@@ -535,8 +574,13 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
           double rho_n = rho_i + a.half_dt * drho;
           if (!a.last) {
             rho_n = rho_n + a.half_dt * drho;
-            a.p_out[i] = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
-            a.vol_out[i] = (T)(C.mass / rho_n);
+            const T p_n = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
+            const T v_n = (T)(C.mass / rho_n);
+            a.p_out[i] = p_n;
+            a.vol_out[i] = v_n;
+            T Bw[6];
+            load_B<T, DIM>(a.B, i, Bw);
+            write_prec<T, DIM>(a.prec, i, xi, p_n, v_n, Bw);
           }
           a.rho[i] = rho_n;
         }
@@ -544,28 +588,56 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
     } else if (!a.rates_only && !a.last && lane == 0) {
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
+      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      const T Iw[6] = {T(1), T(0), T(0), T(1), T(0), T(1)};
+      write_prec<T, DIM>(a.prec, i, xw, T(0), -(T)C.Vw, Iw);
     }
   }
   count_pairs(pc.pairs, cnt);
 }
 
-// p and V from the current density (rates at a state).
 template <typename T>
-__global__ void k_prepare_pv(int n, Consts<T> C, const double* rho, const T* kk,
-                             const uint32_t* tag, T* p, T* vol, double* o_p) {
+struct PvArgs {
+  const double* rho;
+  const T* k;
+  const uint32_t* tag;
+  T *p, *vol;
+  double* o_p;
+  const T* xr[3];
+  const T* v[3];
+  const T* B[6];
+  V4<T>* prec[3];
+  V4<T>* drec[2];
+};
+
+// p and V from the current density, and the j-side records of the pressure
+// and continuity passes at the current state (rates at a state).
+template <typename T, int DIM>
+__global__ void k_prepare_pv(int n, Consts<T> C, PvArgs<T> a) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (!is_real(tag[i])) {
-    p[i] = T(0);
-    vol[i] = (T)C.Vw;
-    if (o_p) o_p[i] = 0.0;
+  const T x[3] = {a.xr[0][i], a.xr[1][i], DIM == 3 ? a.xr[2][i] : T(0)};
+  if (!is_real(a.tag[i])) {
+    a.p[i] = T(0);
+    a.vol[i] = (T)C.Vw;
+    if (a.o_p) a.o_p[i] = 0.0;
+    const T Iw[6] = {T(1), T(0), T(0), T(1), T(0), T(1)};
+    const T vw[3] = {T(0), T(0), T(0)};
+    write_prec<T, DIM>(a.prec, i, x, T(0), -(T)C.Vw, Iw);
+    write_drec<T, DIM>(a.drec, i, x, vw, T(0), -(T)C.Vw);
     return;
   }
-  const double r = rho[i];
-  const double pp = eos(r, C.turbulence ? (double)kk[i] : 0.0, C.rho0, C.c0, C.turbulence);
-  p[i] = (T)pp;
-  vol[i] = (T)(C.mass / r);
-  if (o_p) o_p[i] = pp;
+  const double r = a.rho[i];
+  const double pp = eos(r, C.turbulence ? (double)a.k[i] : 0.0, C.rho0, C.c0, C.turbulence);
+  const T pt = (T)pp, vt = (T)(C.mass / r);
+  a.p[i] = pt;
+  a.vol[i] = vt;
+  if (a.o_p) a.o_p[i] = pp;
+  T B[6];
+  load_B<T, DIM>(a.B, i, B);
+  const T v[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
+  write_prec<T, DIM>(a.prec, i, x, pt, vt, B);
+  write_drec<T, DIM>(a.drec, i, x, v, pt, vt);
 }
 
 // ---------------------------------------------------------------------------
@@ -819,6 +891,7 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   a.o_dk = out ? out->dk : nullptr;
   a.o_deps = out ? out->deps : nullptr;
   a.n_out = c->n_total;
+  for (int k = 0; k < 3; ++k) a.prec[k] = tp<V4<T>>(F.prec[k]);
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
@@ -845,7 +918,9 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
     a.xo[k] = F.x[k].other();
     a.xro[k] = tp<T>(F.xr[k].other());
     a.xrb[k] = pc.nbr ? tp<T>(F.xrb[k]) : nullptr;
+    a.prec[k] = tp<V4<T>>(F.prec[k]);
   }
+  for (int k = 0; k < 2; ++k) a.drec[k] = tp<V4<T>>(F.drec[k]);
   // outgrown-list words by sub-step parity: this pass reads the word of its
   // positions and writes the word of the positions it produces
   if (pc.nbr && !rates_only) {
@@ -902,6 +977,9 @@ hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
   a.rates_only = rates_only ? 1 : 0;
   a.o_drho = out ? out->drho : nullptr;
   if (rates_only) pc.pairs = nullptr;
+  for (int k = 0; k < 2; ++k) a.drec[k] = tp<V4<T>>(F.drec[k]);
+  for (int k = 0; k < 3; ++k) a.prec[k] = tp<V4<T>>(F.prec[k]);
+  for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(F.B[k]);
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
@@ -916,16 +994,28 @@ hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int DIM>
 hipError_t prepare_pv_impl(sph_ctx* c, const sph_rates* out) {
   Consts<T> C = make_consts<T>(c);
   Fields& F = c->F;
   F.p.cur = 0;
   F.vol.cur = 0;
   const int64_t n = c->n_total;
-  k_prepare_pv<T><<<nblk(n), 256, 0, c->stream>>>((int)n, C, F.rho.live(), tp<T>(F.k.live()),
-                                                   F.tag.live(), tp<T>(F.p.live()),
-                                                   tp<T>(F.vol.live()), out ? out->p : nullptr);
+  PvArgs<T> a;
+  a.rho = F.rho.live();
+  a.k = tp<T>(F.k.live());
+  a.tag = F.tag.live();
+  a.p = tp<T>(F.p.live());
+  a.vol = tp<T>(F.vol.live());
+  a.o_p = out ? out->p : nullptr;
+  for (int k = 0; k < 3; ++k) {
+    a.xr[k] = tp<T>(F.xr[k].live());
+    a.v[k] = tp<T>(F.v[k].live());
+    a.prec[k] = tp<V4<T>>(F.prec[k]);
+  }
+  for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(F.B[k]);
+  for (int k = 0; k < 2; ++k) a.drec[k] = tp<V4<T>>(F.drec[k]);
+  k_prepare_pv<T, DIM><<<nblk(n), 256, 0, c->stream>>>((int)n, C, a);
   return hipGetLastError();
 }
 
@@ -987,8 +1077,7 @@ hipError_t launch_density(sph_ctx* c, double dt, bool last, bool rates_only,
 }
 
 hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out) {
-  return c->P.precision == SPH_FP64 ? prepare_pv_impl<double>(c, out)
-                                    : prepare_pv_impl<float>(c, out);
+  return SPHX_DISPATCH(prepare_pv_impl, c, out);
 }
 
 hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update) {

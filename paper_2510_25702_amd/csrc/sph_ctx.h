@@ -41,6 +41,9 @@ struct Fields {
   int32_t* ncnt;           // [cap] entries of particle i
   void* xrb[3];            // cell-relative positions at the list build
   int nbr_k;               // K
+  // j-side records of the pressure / continuity passes (16-byte vectors of T)
+  void* prec[3];           // position, p, volume (negative: wall), B
+  void* drec[2];           // position, velocity, p, volume (negative: wall)
 };
 
 struct Scratch {

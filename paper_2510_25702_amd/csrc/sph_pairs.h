@@ -158,6 +158,124 @@ __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int l
   }
 }
 
+// Four pair-precision values, loaded and stored as one 16-byte (float) or
+// two 16-byte (double) vector accesses.
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T a, b, c, d;
+};
+
+// Record of particle j for the pressure pass: position, p, V (negative for
+// a wall), correction matrix.  2D: {x0, x1, p, Vw} {Bxx, Bxy, Byy, 0};
+// 3D: {x0, x1, x2, p} {Vw, Bxx, Bxy, Bxz} {Byy, Byz, Bzz, 0}.
+template <typename T, int DIM>
+__device__ __forceinline__ void write_prec(V4<T>* const* pr, int i, const T x[3], T p, T volw,
+                                           const T B[6]) {
+  if (DIM == 2) {
+    pr[0][i] = V4<T>{x[0], x[1], p, volw};
+    pr[1][i] = V4<T>{B[0], B[1], B[3], T(0)};
+  } else {
+    pr[0][i] = V4<T>{x[0], x[1], x[2], p};
+    pr[1][i] = V4<T>{volw, B[0], B[1], B[2]};
+    pr[2][i] = V4<T>{B[3], B[4], B[5], T(0)};
+  }
+}
+
+// Record of particle j for the continuity pass: position, velocity, p, V
+// (negative for a wall).  2D: {x0, x1, v0, v1} {p, Vw, 0, 0};
+// 3D: {x0, x1, x2, v0} {v1, v2, p, Vw}.
+template <typename T, int DIM>
+__device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3], const T v[3],
+                                           T p, T volw) {
+  if (DIM == 2) {
+    dr[0][i] = V4<T>{x[0], x[1], v[0], v[1]};
+    dr[1][i] = V4<T>{p, volw, T(0), T(0)};
+  } else {
+    dr[0][i] = V4<T>{x[0], x[1], x[2], v[0]};
+    dr[1][i] = V4<T>{v[1], v[2], p, volw};
+  }
+}
+
+// for_neighbors over j-side records: the NR record vectors of every
+// candidate of a batch are loaded together (the first holds its position),
+// then the candidates are tested; fn(j, r, r2, q) with q[0..NR-1] the
+// records of j.  Same pairs in the same order as for_neighbors.
+template <typename T, int DIM, int L, int NR, typename Fn>
+__device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
+                                                  const T xi[3], const V4<T>* const* rec,
+                                                  Fn&& fn) {
+  if (pc.nbr && !(pc.stale && *pc.stale)) {
+    const int cnt = pc.ncnt[i];
+    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      uint32_t e[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = kb + u * L;
+        e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
+      }
+      V4<T> q[kUnroll][NR];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = (int)(e[u] & kNbrIdxMask);
+#pragma unroll
+        for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (kb + u * L >= cnt) break;
+        const int j = (int)(e[u] & kNbrIdxMask);
+        const int code = (int)(e[u] >> kNbrIdxBits);
+        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+        T r[3];
+        r[0] = (xi[0] - q[u][0].a) + (-T(dx) * pc.csz);
+        r[1] = (xi[1] - q[u][0].b) + (-T(dy) * pc.csz);
+        r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-T(dz) * pc.csz) : T(0);
+        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                              : r[0] * r[0] + r[1] * r[1];
+        if (r2 < pc.rc2) fn(j, r, r2, q[u]);
+      }
+    }
+    return;
+  }
+  const int c = pc.cell[i];
+  const int cx = c % pc.nx;
+  const int cyz = c / pc.nx;
+  const int cy = cyz % pc.ny;
+  const int cz = cyz / pc.ny;
+  constexpr int zr = DIM == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz) {
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx;
+      const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
+                j3 = pc.cs[base + 2];
+      const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      for (int jb = j0 + lane; jb < j3; jb += kUnroll * L) {
+        V4<T> q[kUnroll][NR];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L;
+          const int js = j < j3 ? j : jb;
+#pragma unroll
+          for (int w = 0; w < NR; ++w) q[u][w] = rec[w][js];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = jb + u * L;
+          if (j >= j3) break;
+          const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
+          T r[3];
+          r[0] = (xi[0] - q[u][0].a) + ox;
+          r[1] = (xi[1] - q[u][0].b) + oy;
+          r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + oz : T(0);
+          const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                : r[0] * r[0] + r[1] * r[1];
+          if (r2 < pc.rc2 && j != i) fn(j, r, r2, q[u]);
+        }
+      }
+    }
+  }
+}
+
 // Output of a neighbour-list build.
 template <typename T>
 struct NbrOut {
