@@ -261,6 +261,16 @@ sph_status sph_buffer_update_ex(sph_ctx* ctx, const uint32_t* forced_by_pid,
                                 uint32_t* log_by_pid, int64_t pid_cap,
                                 sph_buffer_counts* out);
 
+/* One full advection step as the method advances the flow (Sec. 2.3 with
+ * the buffer update of Sec. 2.4 at its end): sph_build_cells,
+ * sph_correction, sph_step(ctrl) and sph_buffer_update in one call, with
+ * the same arguments, requirements and error behaviour as those calls made
+ * in that order (the first failure returns its status; the state is then
+ * the one that call leaves).  info and counts may be NULL.  Synchronises
+ * once (in the buffer update). */
+sph_status sph_advance(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* info,
+                       sph_buffer_counts* counts);
+
 /* Decision codes of sph_buffer_update for the current state without
  * applying them (device uint32 [n_total], current order; particles outside
  * every local cell list get SPH_DEC_NONE).  Requires sph_build_cells. */

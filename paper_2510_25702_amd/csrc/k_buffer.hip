@@ -90,6 +90,16 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
   return kDecNone;
 }
 
+// K14: apply tag changes (after K13 succeeded).
+__device__ __forceinline__ void apply_one(const BufArgs& a, int i) {
+  const uint32_t d = a.dec[i];
+  const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
+  if (act == kDecRelabel) a.tag[i] = kBuffer | (id << 8);
+  else if (act == kDecRevert) a.tag[i] = kFluid;
+  else if (act == kDecRevertRelabel) a.tag[i] = kBuffer | (id2 << 8);
+  else if (act == kDecDelete) a.tag[i] = kDead;
+}
+
 // Count a decision and queue an injection.
 __device__ __forceinline__ void record(const BufArgs& a, int i, uint32_t d) {
   a.dec[i] = d;
@@ -127,6 +137,7 @@ __global__ __launch_bounds__(kWave) void k_buffer_decide(BufArgs a) {
     }
     if (a.log && a.pid[i] < a.pid_cap) a.log[a.pid[i]] = d;
     record(a, i, d);
+    apply_one(a, i);   // a decision reads only its own particle's tag
   }
 }
 
@@ -140,30 +151,29 @@ __global__ __launch_bounds__(256) void k_buffer_forced(BufArgs a) {
   if (!is_real(a.tag[i])) d = kDecNone;
   if (a.log && p < a.pid_cap) a.log[p] = d;
   record(a, i, d);
+  apply_one(a, i);
 }
 
-// K14: apply tag changes (after K13 succeeded).
-__device__ __forceinline__ void apply_one(const BufArgs& a, int i) {
+// The decide kernels apply the tag changes at once; when the injection
+// then fails for capacity they are undone (every code records the tag it
+// replaced: relabel from FLUID, revert / delete from BUFFER(b)).
+__device__ __forceinline__ void undo_one(const BufArgs& a, int i) {
   const uint32_t d = a.dec[i];
-  const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
-  if (act == kDecRelabel) a.tag[i] = kBuffer | (id << 8);
-  else if (act == kDecRevert) a.tag[i] = kFluid;
-  else if (act == kDecRevertRelabel) a.tag[i] = kBuffer | (id2 << 8);
-  else if (act == kDecDelete) a.tag[i] = kDead;
+  const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu;
+  if (act == kDecRelabel) a.tag[i] = kFluid;
+  else if (act == kDecRevert || act == kDecRevertRelabel || act == kDecDelete)
+    a.tag[i] = kBuffer | (id << 8);
 }
 
-__global__ __launch_bounds__(kWave) void k_buffer_apply(BufArgs a) {
-  if (*a.flags & kFlagCapacity) return;
+__global__ __launch_bounds__(kWave) void k_buffer_undo(BufArgs a) {
   const int cell = a.cand[blockIdx.x];
   const int b = a.cstart[cell], e = a.cstart[cell + 1];
-  for (int i = b + (int)threadIdx.x; i < e; i += kWave) apply_one(a, i);
+  for (int i = b + (int)threadIdx.x; i < e; i += kWave) undo_one(a, i);
 }
 
-// K14 (replay): every slot.
-__global__ __launch_bounds__(256) void k_buffer_apply_all(BufArgs a) {
-  if (*a.flags & kFlagCapacity) return;
+__global__ __launch_bounds__(256) void k_buffer_undo_all(BufArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n) apply_one(a, i);
+  if (i < a.n) undo_one(a, i);
 }
 
 template <typename T>
@@ -391,15 +401,18 @@ hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* lo
 }
 
 hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots) {
-  hipError_t e = c->P.precision == SPH_FP64 ? inject_impl<double>(c) : inject_impl<float>(c);
-  if (e != hipSuccess) return e;
+  (void)all_slots;   // the tag changes were applied by the decide kernels
+  return c->P.precision == SPH_FP64 ? inject_impl<double>(c) : inject_impl<float>(c);
+}
+
+hipError_t launch_buffer_undo(sph_ctx* c, bool all_slots) {
   BufArgs a = make_bufargs(c, false, nullptr);
   if (all_slots) {
     if (c->n_total == 0) return hipSuccess;
-    k_buffer_apply_all<<<(int)((c->n_total + 255) / 256), 256, 0, c->stream>>>(a);
+    k_buffer_undo_all<<<(int)((c->n_total + 255) / 256), 256, 0, c->stream>>>(a);
   } else {
     if (c->S.n_cand_cells == 0) return hipSuccess;
-    k_buffer_apply<<<c->S.n_cand_cells, kWave, 0, c->stream>>>(a);
+    k_buffer_undo<<<c->S.n_cand_cells, kWave, 0, c->stream>>>(a);
   }
   return hipGetLastError();
 }

@@ -66,34 +66,103 @@ __global__ void k_get_particles(int n, double* x, double* v, double* rho, double
 }
 
 // K1: cell id of every particle (FP64, floor((x - lo) / cs), IEEE division)
-// and its rank inside the cell; particles tagged dead get key -1.
+// and a distinct slot inside its cell; particles tagged dead get key -1.
+// The particles arrive (mostly) in the previous build's cell order, so each
+// run of equal keys along a wavefront takes its slots with one atomic.
+// Block 0 also clears the buffer-update counters of this step.
+constexpr int kKeysThreads = 1024;
+
 template <int DIM>
-__global__ void k_cell_keys(int n, const double* __restrict__ x0, const double* __restrict__ x1,
-                            const double* __restrict__ x2, const uint32_t* __restrict__ tag,
-                            GridDev g, int32_t* __restrict__ key, int32_t* __restrict__ slot,
-                            int32_t* __restrict__ count, uint32_t* __restrict__ flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (tag_kind(tag[i]) == kDead) {
-    key[i] = -1;
-    return;
-  }
-  const double* xs[3] = {x0, x1, x2};
-  int c[3] = {0, 0, 0};
-  bool bad = false;
+__global__ __launch_bounds__(kKeysThreads) void k_cell_keys(
+    int n, const double* __restrict__ x0, const double* __restrict__ x1,
+    const double* __restrict__ x2, const uint32_t* __restrict__ tag, GridDev g,
+    int32_t* __restrict__ key, int32_t* __restrict__ slot, int32_t* count,
+    uint32_t* __restrict__ flags, int32_t* __restrict__ counters, int n_counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < n_counters; q += blockDim.x) counters[q] = 0;
+  int id = -1;
+  if (i < n && tag_kind(tag[i]) != kDead) {
+    const double* xs[3] = {x0, x1, x2};
+    int c[3] = {0, 0, 0};
+    bool bad = false;
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    double q = floor(__ddiv_rn(__dsub_rn(xs[k][i], g.lo[k]), g.cs));
-    if (!(q >= 1.0 && q <= (double)(g.n[k] - 2))) {
-      bad = true;
-      q = (q >= 1.0) ? (double)(g.n[k] - 2) : 1.0;   // also catches NaN
+    for (int k = 0; k < DIM; ++k) {
+      double q = floor(__ddiv_rn(__dsub_rn(xs[k][i], g.lo[k]), g.cs));
+      if (!(q >= 1.0 && q <= (double)(g.n[k] - 2))) {
+        bad = true;
+        q = (q >= 1.0) ? (double)(g.n[k] - 2) : 1.0;   // also catches NaN
+      }
+      c[k] = (int)q;
     }
-    c[k] = (int)q;
+    if (bad) atomicOr(flags, kFlagOutOfGrid);
+    id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
   }
-  if (bad) atomicOr(flags, kFlagOutOfGrid);
-  int id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
-  key[i] = id;
-  slot[i] = atomicAdd(&count[id], 1);
+  // runs of equal keys: the head lane reserves the run's slots
+  const int prev = __shfl_up(id, 1, kWave);
+  const bool head = lane == 0 || prev != id;
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const int h = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int next = after ? __ffsll((unsigned long long)after) - 1 : kWave;
+  int base = 0;
+  if (head && id >= 0) base = atomicAdd(&count[id], next - lane);
+  base = __shfl(base, h, kWave);
+  if (i < n) {
+    key[i] = id;
+    if (id >= 0) slot[i] = base + (lane - h);
+  }
+}
+
+// K2 (grids of at most kSegScan cells): the whole exclusive scan in one
+// workgroup.  Every wavefront scans one contiguous segment of the counts
+// (coalesced, all loads in flight together), then the segment totals are
+// combined; clears the counts for the next build.
+constexpr int kSegThreads = 1024;
+constexpr int kSegWaves = kSegThreads / kWave;
+constexpr int kSegPer = 16;                                // counts per lane
+constexpr int kSegScan = kSegWaves * kWave * kSegPer;      // 16384 cells
+
+__global__ __launch_bounds__(kSegThreads) void k_scan_seg(int32_t* __restrict__ count, int nc,
+                                                         int32_t* __restrict__ cell_start) {
+  __shared__ int sm[kSegWaves];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int per = (nc + kSegThreads - 1) / kSegThreads;   // <= kSegPer
+  const int seg0 = w * per * kWave;
+  int v[kSegPer];
+#pragma unroll
+  for (int q = 0; q < kSegPer; ++q) {
+    const int idx = seg0 + q * kWave + lane;
+    v[q] = (q < per && idx < nc) ? count[idx] : 0;
+  }
+  int run = 0;
+#pragma unroll
+  for (int q = 0; q < kSegPer; ++q) {
+    const int inc = wave_incl_scan(v[q]);
+    const int ex = run + inc - v[q];
+    run += __shfl(inc, kWave - 1, kWave);
+    v[q] = ex;
+  }
+  if (lane == 0) sm[w] = run;
+  __syncthreads();
+  int off = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < kSegWaves; ++q) {
+    const int t = sm[q];
+    off += q < w ? t : 0;
+    total += t;
+  }
+#pragma unroll
+  for (int q = 0; q < kSegPer; ++q) {
+    const int idx = seg0 + q * kWave + lane;
+    if (q < per && idx < nc) {
+      cell_start[idx] = off + v[q];
+      count[idx] = 0;
+    }
+  }
+  if (threadIdx.x == 0) cell_start[nc] = total;
 }
 
 // K2: exclusive scan of the per-cell counts (reduce, scan of partials, apply).
@@ -152,39 +221,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t* __restrict
     }
     off += v[q];
   }
-}
-
-// K2 (grids of at most kSmallScan cells): the whole exclusive scan in one
-// workgroup, tile by tile (kScanTile counts per tile, kScanItems contiguous
-// per thread) with a running carry; clears the counts for the next build.
-constexpr int kSmallScan = 16 * kScanTile;
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_small(int32_t* __restrict__ in, int n,
-                                                             int32_t* __restrict__ out) {
-  __shared__ int sm[kScanThreads / kWave + 1];
-  int carry = 0;
-  for (int t0 = 0; t0 < n; t0 += kScanTile) {
-    const int base = t0 + threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int s = 0;
-#pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      v[q] = (base + q < n) ? in[base + q] : 0;
-      s += v[q];
-    }
-    int total;
-    int off = block_excl_scan(s, sm, &total) + carry;
-#pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      if (base + q < n) {
-        out[base + q] = off;
-        in[base + q] = 0;
-      }
-      off += v[q];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) out[n] = carry;
 }
 
 // K3a: scatter to cell-sorted positions (arbitrary order inside a cell).
@@ -279,11 +315,13 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   const int nc = g.ncell;
   // the counts are cleared by the scan of the previous build (and at create)
   if (n_in > 0)
-    k_cell_keys<DIM><<<(int)((n_in + 255) / 256), 256, 0, st>>>(
+    k_cell_keys<DIM><<<(int)((n_in + kKeysThreads - 1) / kKeysThreads), kKeysThreads, 0, st>>>(
         (int)n_in, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.tag.live(), g, S.key, S.slot,
-        S.count, S.flags);
-  if (nc <= kSmallScan) {
-    k_scan_small<<<1, kScanThreads, 0, st>>>(S.count, nc, S.cell_start);
+        S.count, S.flags, S.counters, 1040);
+  else
+    k_fill_i32<<<(1040 + 255) / 256, 256, 0, st>>>(S.counters, 1040, 0);
+  if (nc <= kSegScan) {
+    k_scan_seg<<<1, kSegThreads, 0, st>>>(S.count, nc, S.cell_start);
   } else {
     int nb = (nc + kScanTile - 1) / kScanTile;
     k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums);

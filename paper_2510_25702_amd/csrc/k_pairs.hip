@@ -690,14 +690,15 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
                                                      const uint64_t* next_pid) {
   __shared__ double sm[2][256 / kWave];
   n = min(n + counters[1024], n_max);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double a = 0.0, b = 0.0;
-  if (i < n && is_real(tag[i])) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (!is_real(tag[i])) continue;
     const double x = v0[i], y = v1[i], z = v2[i];
-    a = (x * x + y * y) + z * z;
+    double q = (x * x + y * y) + z * z;
     const double r = rho[i];
-    if (!(a == a) || !(r == r) || isinf(a) || isinf(r)) a = INFINITY;
-    if (turb && (double)nut[i] > 0.0) b = (double)nut[i];   // never -0.0
+    if (!(q == q) || !(r == r) || isinf(q) || isinf(r)) q = INFINITY;
+    a = fmax(a, q);
+    if (turb && (double)nut[i] > b) b = (double)nut[i];   // never -0.0
   }
   a = wave_max(a);
   b = wave_max(b);
@@ -847,7 +848,10 @@ hipError_t correction_impl(sph_ctx* c) {
   const double rl = c->P.cell_size * (1.0 + 2e-6);
   nb.rl2 = (T)(rl * rl);
   const int64_t n = c->n_total;
-  const int L = team_lanes(c);
+  // the stencil scan walks ~3x the candidates of the list passes: twice the
+  // lanes per particle while the grid is small
+  const int L = c->team_override > 0 ? team_lanes(c)
+                                     : std::min(8, team_lanes(c) * (n <= 100000 ? 2 : 1));
   if (c->use_nbr) {
     SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, true><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb));
   } else {
@@ -1026,7 +1030,7 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
   const int64_t n_max = after_update ? std::min<int64_t>(c->cap, n + kMaxInject) : n;
   const int nb = nblk(n_max);
   if (after_update) {
-    k_reduce_post<T><<<nb, 256, 0, c->stream>>>(
+    k_reduce_post<T><<<std::min(nb, 64), 256, 0, c->stream>>>(
         (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
         tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
         c->S.flags, c->S.next_pid);

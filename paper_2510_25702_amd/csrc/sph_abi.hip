@@ -456,6 +456,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
     e = hipMemcpyAsync(S.cand_cells, cand.data(), cand.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.stale, 0, 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.counters, 0, 1040 * 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.count, 0, (size_t)c->grid.ncell * 4, st);
   if (e == hipSuccess)
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
@@ -656,6 +657,15 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
   return SPH_OK;
 }
 
+sph_status sph_advance(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* info,
+                       sph_buffer_counts* counts) {
+  sph_status st = sph_build_cells(c);
+  if (st == SPH_OK) st = sph_correction(c);
+  if (st == SPH_OK) st = sph_step(c, ctrl, info);
+  if (st == SPH_OK) st = sph_buffer_update(c, counts);
+  return st;
+}
+
 sph_status sph_buffer_update(sph_ctx* c, sph_buffer_counts* out) {
   return sph_buffer_update_ex(c, nullptr, nullptr, 0, out);
 }
@@ -667,8 +677,10 @@ sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint3
   if ((forced_by_pid || log_by_pid) && pid_cap < (int64_t)c->next_pid)
     return fail(c, SPH_E_ARG, "pid_cap must cover every particle id (>= next_pid)");
   profile_launch(c, SPH_K_BUFFER);
-  hipError_t e = launch_zero_i32(c, c->S.counters, 1040);
-  if (e == hipSuccess && log_by_pid) e = launch_zero_i32(c, (int32_t*)log_by_pid, pid_cap);
+  // the counters were cleared by the cell build (the call requires one since
+  // the last update; a failed update clears them itself)
+  hipError_t e = hipSuccess;
+  if (log_by_pid) e = launch_zero_i32(c, (int32_t*)log_by_pid, pid_cap);
   if (e == hipSuccess) {
     if (forced_by_pid) e = launch_buffer_forced(c, forced_by_pid, log_by_pid, pid_cap);
     else e = launch_buffer_decide(c, false, nullptr, log_by_pid, pid_cap);
@@ -685,8 +697,11 @@ sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint3
   const int32_t* cnt = (const int32_t*)hb;
   uint32_t flags = (uint32_t)cnt[1032];
   if (flags & kFlagCapacity) {
-    // nothing was applied: clear the flag so that the state stays usable
+    // nothing was injected: undo the tag changes the decisions applied,
+    // clear the flag and the counters so that the state stays usable
     uint32_t zero = 0;
+    (void)launch_buffer_undo(c, forced_by_pid != nullptr);
+    (void)launch_zero_i32(c, c->S.counters, 1040);
     (void)hipMemcpyAsync(c->S.flags, &zero, 4, hipMemcpyHostToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);
     return fail(c, SPH_E_CAPACITY, (flags & kFlagInjectOverflow)

@@ -117,6 +117,8 @@ EXPORTS = {
     "sph_correction": (C.c_int, [C.c_void_p]),
     "sph_step": (C.c_int, [C.c_void_p, C.POINTER(sph_step_ctrl), C.POINTER(sph_step_info)]),
     "sph_buffer_update": (C.c_int, [C.c_void_p, C.POINTER(sph_buffer_counts)]),
+    "sph_advance": (C.c_int, [C.c_void_p, C.POINTER(sph_step_ctrl), C.POINTER(sph_step_info),
+                              C.POINTER(sph_buffer_counts)]),
     "sph_buffer_decisions": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sph_eval_rates": (C.c_int, [C.c_void_p, C.POINTER(sph_rates)]),
     "sph_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -218,6 +220,14 @@ def sph_buffer_update(ctx):
     cnt = sph_buffer_counts()
     _check(ctx, lib().sph_buffer_update(ctx, C.byref(cnt)))
     return cnt
+
+
+def sph_advance(ctx, ctrl=None):
+    info, cnt = sph_step_info(), sph_buffer_counts()
+    st = lib().sph_advance(ctx, C.byref(ctrl) if ctrl is not None else None, C.byref(info),
+                           C.byref(cnt))
+    _check(ctx, st)
+    return info, cnt
 
 
 def sph_buffer_decisions(ctx, dec_ptr):
@@ -450,12 +460,12 @@ class Simulation:
         return sph_buffer_update(self.ctx)
 
     def advance(self, dt_adv=0.0, n_ac=0):
-        """build cells, correction, one advection step, buffer update."""
-        self.build_cells()
-        self.correction()
-        info = self.step(dt_adv, n_ac)
-        cnt = self.buffer_update()
-        return info, cnt
+        """build cells, correction, one advection step, buffer update (one
+        library call)."""
+        ctrl = None
+        if dt_adv > 0:
+            ctrl = sph_step_ctrl(float(dt_adv), int(n_ac), 0)
+        return sph_advance(self.ctx, ctrl)
 
     def decisions(self):
         torch = self.torch

@@ -81,13 +81,17 @@ CASES = {
     "jet": small_jet,
     "mixer3d": small_mixer,
     "mixer3d_coarse": lambda: cases.make_mixer(dp=0.04),
+    # about 19.5k cells: above the cell count the key kernel scans itself
+    "channel_long": lambda: cases.make_channel(L=600.0, dp=0.1),
+    # 15625 cells: the largest per-lane share of that in-kernel scan
+    "jet_full": lambda: cases.make_jet(),
 }
 
 
 # --------------------------------------------------------------------------
 # neighbour lists (FP64 predicate): bit-exact
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["channel", "jet", "mixer3d_coarse"])
+@pytest.mark.parametrize("name", ["channel", "jet", "mixer3d_coarse", "channel_long", "jet_full"])
 @pytest.mark.parametrize("jit", [0.0, 0.4])
 def test_neighbor_sets_bit_exact(sph, ora, name, jit):
     c = CASES[name]()
@@ -345,6 +349,48 @@ def test_capacity_error_leaves_state_unchanged(sph, ora):
     g2.build_cells()
     cnt = g2.buffer_update()
     assert cnt.n_inject[1] == 5
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_capacity_error_undoes_applied_tag_changes(sph, forced):
+    # relabel (FLUID in the region), delete (BUFFER behind the open plane),
+    # revert (BUFFER outside the containment) and five injections: the tag
+    # changes are applied with the decisions and must be undone when the
+    # injections do not fit, on the predicate and on the replay path
+    import torch
+    from tests.test_oracle_buffer import crafted, inlet
+    from cases import BUFFER, FLUID, make_tag
+    b = inlet(1)
+    gen = b.length + b.fringe
+    F, B1 = make_tag(FLUID), make_tag(BUFFER, 1)
+    pts = [(gen + 0.01, 0.2 + 0.1 * k) for k in range(5)] + [(0.1, 0.5), (-0.01, 0.5),
+                                                               (0.1, 1.05)]
+    c = crafted(pts, [B1] * 5 + [F, B1, B1], [b])
+    cap = 64
+    big = gpu_sim(sph, c, sph.SPH_FP64, capacity=32)
+    big.build_cells()
+    log = torch.zeros(cap, dtype=torch.int32, device=big.device)
+    cnt = big.buffer_update_ex(log=log, pid_cap=cap)
+    acts = sorted(int(d) & 0xFF for d in log.cpu().numpy()[:8])
+    assert acts == sorted([2] * 5 + [1, 3, 4])
+    g = gpu_sim(sph, c, sph.SPH_FP64, capacity=12)
+    g.build_cells()
+    before = g.state()
+    with pytest.raises(sph.SphError) as e:
+        if forced:
+            g.buffer_update_ex(forced=log, pid_cap=cap)
+        else:
+            g.buffer_update()
+    assert e.value.status == sph.SPH_E_CAPACITY
+    after = g.state()
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    # the same update succeeds after a fresh cell build with enough room
+    g2 = gpu_sim(sph, c, sph.SPH_FP64, capacity=16)
+    g2.build_cells()
+    cnt2 = g2.buffer_update()
+    assert cnt2.n_inject[1] == cnt.n_inject[1] == 5
+    assert cnt2.n_relabel[1] == 1 and cnt2.n_delete[1] == 1
 
 
 def test_empty_and_tiny_domains(sph):
