@@ -264,10 +264,15 @@ sph_status sph_buffer_update_ex(sph_ctx* ctx, const uint32_t* forced_by_pid,
 /* One full advection step as the method advances the flow (Sec. 2.3 with
  * the buffer update of Sec. 2.4 at its end): sph_build_cells,
  * sph_correction, sph_step(ctrl) and sph_buffer_update in one call, with
- * the same arguments, requirements and error behaviour as those calls made
- * in that order (the first failure returns its status; the state is then
- * the one that call leaves).  info and counts may be NULL.  Synchronises
- * once (in the buffer update). */
+ * the same results as those calls made in that order.  The cell build and
+ * correction of the updated state are enqueued before the update's one
+ * read-back (their sizes taken on the device), so on success the state is
+ * the updated one already built and corrected: particles tagged SPH_DEAD
+ * are dropped and the next sph_advance (or sph_step) starts from it.  The
+ * first failure returns its status.  On SPH_E_CAPACITY the state is the
+ * one a failed sph_buffer_update leaves; on a flag error raised by the step
+ * (SPH_E_NUMERIC) it is the updated state and a cell build is required.
+ * info and counts may be NULL.  Synchronises once. */
 sph_status sph_advance(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* info,
                        sph_buffer_counts* counts);
 

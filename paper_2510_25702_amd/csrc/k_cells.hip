@@ -77,7 +77,12 @@ __global__ __launch_bounds__(kKeysThreads) void k_cell_keys(
     int n, const double* __restrict__ x0, const double* __restrict__ x1,
     const double* __restrict__ x2, const uint32_t* __restrict__ tag, GridDev g,
     int32_t* __restrict__ key, int32_t* __restrict__ slot, int32_t* count,
-    uint32_t* __restrict__ flags, int32_t* __restrict__ counters, int n_counters) {
+    uint32_t* __restrict__ flags, int32_t* __restrict__ counters, int n_counters,
+    const int32_t* __restrict__ ns) {
+  if (ns) {
+    if (ns[2]) return;
+    n = ns[0];
+  }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   if (blockIdx.x == 0)
@@ -126,7 +131,9 @@ constexpr int kSegPer = 16;                                // counts per lane
 constexpr int kSegScan = kSegWaves * kWave * kSegPer;      // 16384 cells
 
 __global__ __launch_bounds__(kSegThreads) void k_scan_seg(int32_t* __restrict__ count, int nc,
-                                                         int32_t* __restrict__ cell_start) {
+                                                         int32_t* __restrict__ cell_start,
+                                                         const int32_t* __restrict__ ns) {
+  if (ns && ns[2]) return;
   __shared__ int sm[kSegWaves];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int per = (nc + kSegThreads - 1) / kSegThreads;   // <= kSegPer
@@ -167,7 +174,9 @@ __global__ __launch_bounds__(kSegThreads) void k_scan_seg(int32_t* __restrict__ 
 
 // K2: exclusive scan of the per-cell counts (reduce, scan of partials, apply).
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in,
-                                                              int n, int32_t* __restrict__ part) {
+                                                              int n, int32_t* __restrict__ part,
+                                                              const int32_t* __restrict__ ns) {
+  if (ns && ns[2]) return;
   __shared__ int sm[kScanThreads / kWave + 1];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int s = 0;
@@ -179,7 +188,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __r
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* __restrict__ part, int nb,
-                                                             int32_t* __restrict__ out, int n) {
+                                                             int32_t* __restrict__ out, int n,
+                                                             const int32_t* __restrict__ ns) {
+  if (ns && ns[2]) return;
   __shared__ int sm[kScanThreads / kWave + 1];
   int base = threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -201,7 +212,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* __restrict
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t* __restrict__ in, int n,
                                                              const int32_t* __restrict__ part,
-                                                             int32_t* __restrict__ out, int zero_in) {
+                                                             int32_t* __restrict__ out, int zero_in,
+                                                             const int32_t* __restrict__ ns) {
+  if (ns && ns[2]) return;
   __shared__ int sm[kScanThreads / kWave + 1];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -225,7 +238,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t* __restrict
 
 // K3a: scatter to cell-sorted positions (arbitrary order inside a cell).
 __global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t* __restrict__ slot,
-                          const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm) {
+                          const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm,
+                          const int32_t* __restrict__ ns) {
+  if (ns) {
+    if (ns[2]) return;
+    n = ns[0];
+  }
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int k = key[i];
@@ -259,6 +277,7 @@ struct GatherArgs {
   T* volo;
   int32_t* cello;
   uint32_t* flags;
+  const int32_t* ns;   // sizes on the device (prelaunched build), or NULL
 };
 
 // K3b: place every particle at its cell-ordered slot and copy its fields
@@ -268,6 +287,11 @@ struct GatherArgs {
 // the cell's (arbitrarily ordered) scatter slots.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T, DIM> a) {
+  if (a.ns) {
+    if (a.ns[2]) return;
+    n_in = a.ns[0];
+    n_out = a.ns[1];
+  }
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = a.cell_start[a.ncell];
   if (s == 0 && total != n_out) atomicOr(a.flags, kFlagCountMismatch);
@@ -306,8 +330,10 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
 template <typename T>
 T* tp(void* p) { return static_cast<T*>(p); }
 
+// n_in / n_out: particles before / after the build; with ns (device
+// {n_in, n_out, skip}) they are upper bounds that size the grids.
 template <typename T, int DIM>
-hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
+hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns) {
   hipStream_t st = c->stream;
   Fields& F = c->F;
   Scratch& S = c->S;
@@ -317,20 +343,20 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   if (n_in > 0)
     k_cell_keys<DIM><<<(int)((n_in + kKeysThreads - 1) / kKeysThreads), kKeysThreads, 0, st>>>(
         (int)n_in, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.tag.live(), g, S.key, S.slot,
-        S.count, S.flags, S.counters, 1040);
+        S.count, S.flags, S.counters, 1040, ns);
   else
     k_fill_i32<<<(1040 + 255) / 256, 256, 0, st>>>(S.counters, 1040, 0);
   if (nc <= kSegScan) {
-    k_scan_seg<<<1, kSegThreads, 0, st>>>(S.count, nc, S.cell_start);
+    k_scan_seg<<<1, kSegThreads, 0, st>>>(S.count, nc, S.cell_start, ns);
   } else {
     int nb = (nc + kScanTile - 1) / kScanTile;
-    k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums);
-    k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc);
-    k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start, 1);
+    k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, ns);
+    k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc, ns);
+    k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start, 1, ns);
   }
   if (n_in > 0)
     k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>((int)n_in, S.key, S.slot,
-                                                          S.cell_start, S.perm);
+                                                          S.cell_start, S.perm, ns);
   GatherArgs<T, DIM> a;
   a.perm = S.perm;
   a.key = S.key;
@@ -365,6 +391,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out) {
   a.volo = tp<T>(F.vol.a[0]);
   a.cello = F.cell;
   a.flags = S.flags;
+  a.ns = ns;
   k_place<T, DIM><<<(int)((n_in + 255) / 256) + (n_in == 0), 256, 0, st>>>((int)n_in, (int)n_out, a);
   for (int k = 0; k < 3; ++k) {
     F.x[k].flip();
@@ -414,10 +441,10 @@ hipError_t get_impl(sph_ctx* c, const sph_particles* d) {
 hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) {
   const int nb = (n + kScanTile - 1) / kScanTile + (n == 0);
   if (nb > kScanTile) return hipErrorInvalidValue;
-  k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums);
-  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n);
+  k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums, nullptr);
+  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n, nullptr);
   k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(const_cast<int32_t*>(in), n, c->S.block_sums,
-                                                    out, 0);
+                                                    out, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -435,12 +462,12 @@ hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst) {
   return c->P.precision == SPH_FP64 ? get_impl<double>(c, dst) : get_impl<float>(c, dst);
 }
 
-hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out) {
+hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns) {
   if (c->P.precision == SPH_FP64)
-    return c->P.dim == 2 ? build_cells_impl<double, 2>(c, n_in, n_out)
-                         : build_cells_impl<double, 3>(c, n_in, n_out);
-  return c->P.dim == 2 ? build_cells_impl<float, 2>(c, n_in, n_out)
-                       : build_cells_impl<float, 3>(c, n_in, n_out);
+    return c->P.dim == 2 ? build_cells_impl<double, 2>(c, n_in, n_out, ns)
+                         : build_cells_impl<double, 3>(c, n_in, n_out, ns);
+  return c->P.dim == 2 ? build_cells_impl<float, 2>(c, n_in, n_out, ns)
+                       : build_cells_impl<float, 3>(c, n_in, n_out, ns);
 }
 
 }  // namespace sphx

@@ -126,7 +126,11 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
 
 template <typename T, int DIM, int L, bool BUILD>
 __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
-                                                    NbrOut<T> nb) {
+                                                    NbrOut<T> nb, const int32_t* __restrict__ ns) {
+  if (ns) {   // sizes on the device: the build of this state was prelaunched
+    if (ns[2]) return;
+    n = ns[1];
+  }
   const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (BUILD && g == 0) {
     nb.stale[0] = 0;
@@ -687,8 +691,20 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
                                                      const double* rho, const T* nut,
                                                      const uint32_t* tag, int turb,
                                                      const uint32_t* flags,
-                                                     const uint64_t* next_pid) {
+                                                     const uint64_t* next_pid, int n_alive,
+                                                     int32_t* __restrict__ ns) {
   __shared__ double sm[2][256 / kWave];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // sizes of the next cell build, for a build launched before the host
+    // has read the counts: {n_in, n_out, skip (the injection failed)}
+    const bool cap = (*flags & kFlagCapacity) != 0;
+    const int inj = cap ? 0 : counters[1024];
+    int del = 0;
+    for (int b = 0; b < 256; ++b) del += counters[512 + b];
+    ns[0] = n + inj;
+    ns[1] = n_alive + inj - del;
+    ns[2] = cap ? 1 : 0;
+  }
   n = min(n + counters[1024], n_max);
   double a = 0.0, b = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -810,12 +826,25 @@ inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
 // lane per particle once the grid alone fills the machine (measured on
 // MI355X, 2D: at 57k particles L = 4 is fastest, 0.55x the step time of
 // L = 1; at 640k and 2.56M particles L = 1 is fastest).
+// Lanes per particle (measured on 2D workloads): enough wavefronts to cover
+// the load latency at small sizes, one lane per particle once the chip is
+// full.  The correction's stencil scan walks ~3x the candidates of the list
+// passes and takes twice the lanes (two at most sizes: 160 against 242 us at
+// 640k particles, 590 against 731 us at 2.56M).
 inline int team_lanes(const sph_ctx* c) {
   if (c->team_override > 0) return c->team_override;
   const int64_t n = c->n_total;
-  if (n <= 260000) return 4;
+  if (n <= 100000) return 4;
   if (n <= 450000) return 2;
   return 1;
+}
+
+inline int corr_lanes(const sph_ctx* c, int64_t n) {
+  if (c->corr_override > 0) return c->corr_override;
+  if (c->team_override > 0) return c->team_override;
+  if (n <= 100000) return 8;
+  if (n <= 260000) return 4;
+  return 2;
 }
 
 #define SPHX_TEAM_SWITCH(L, ...)                                   \
@@ -827,7 +856,7 @@ inline int team_lanes(const sph_ctx* c) {
   }
 
 template <typename T, int DIM>
-hipError_t correction_impl(sph_ctx* c) {
+hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
   Consts<T> C = make_consts<T>(c);
   c->nbr_valid = false;
   PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);   // stencil: no list yet
@@ -847,15 +876,12 @@ hipError_t correction_impl(sph_ctx* c) {
   nb.stale = c->S.stale;
   const double rl = c->P.cell_size * (1.0 + 2e-6);
   nb.rl2 = (T)(rl * rl);
-  const int64_t n = c->n_total;
-  // the stencil scan walks ~3x the candidates of the list passes: twice the
-  // lanes per particle while the grid is small
-  const int L = c->team_override > 0 ? team_lanes(c)
-                                     : std::min(8, team_lanes(c) * (n <= 100000 ? 2 : 1));
+  const int64_t n = ns ? n_grid : c->n_total;
+  const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr) {
-    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, true><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb));
+    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, true><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb, ns));
   } else {
-    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, false><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb));
+    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, false><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb, ns));
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && c->use_nbr) c->nbr_valid = true;
@@ -1033,7 +1059,7 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
     k_reduce_post<T><<<std::min(nb, 64), 256, 0, c->stream>>>(
         (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
         tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
-        c->S.flags, c->S.next_pid);
+        c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate);
     return hipGetLastError();
   }
   k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, after_update ? c->S.counters + 1024 : nullptr,
@@ -1064,7 +1090,9 @@ hipError_t export_B_impl(sph_ctx* c, double* B) {
        ? (c->P.dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)) \
        : (c->P.dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)))
 
-hipError_t launch_correction(sph_ctx* c) { return SPHX_DISPATCH(correction_impl, c); }
+hipError_t launch_correction(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
+  return SPHX_DISPATCH(correction_impl, c, ns, n_grid);
+}
 
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
                             const sph_rates* out) {

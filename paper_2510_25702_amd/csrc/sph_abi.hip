@@ -161,7 +161,7 @@ struct Plan {
       off_nut[2], off_tag[2], off_pid[2], off_p[2], off_vol[2], off_B[6], off_anu[3], off_cell,
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
-      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2];
+      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_nstate;
   int n_cand;
 };
 
@@ -211,6 +211,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_counters = L.take(1040 * 4);
   pl->off_flags = L.take(4);
   pl->off_stale = L.take(8);
+  pl->off_nstate = L.take(16);
   pl->off_red = L.take((C / 256 + 8) * 2 * 8 + 64);
   pl->off_pairs = L.take(sizeof(long long) * kPairShards * kPairShardStride);
   pl->off_npid = L.take(8);
@@ -320,6 +321,120 @@ void profile_launch(sph_ctx* c, int kernel) {
   prof_begin(c, kernel, n * kernel_bytes_per_particle(c, kernel), n);
 }
 
+// The buffer update: decisions (predicates, or a replayed log) applied with
+// their tag changes, injection, the post-update reduction and one read-back.
+// With prelaunch the cell build and correction of the updated state are
+// enqueued before the host waits for the read-back, their sizes read on the
+// device (written by the reduction), so the GPU has work while the host
+// takes the counts and returns; a failed injection turns them into no-ops.
+sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* log_by_pid,
+                         int64_t pid_cap, sph_buffer_counts* out, bool prelaunch) {
+  if (!c) return SPH_E_ARG;
+  if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_buffer_update needs sph_build_cells first");
+  if ((forced_by_pid || log_by_pid) && pid_cap < (int64_t)c->next_pid)
+    return fail(c, SPH_E_ARG, "pid_cap must cover every particle id (>= next_pid)");
+  profile_launch(c, SPH_K_BUFFER);
+  // the counters were cleared by the cell build (the call requires one since
+  // the last update; a failed update clears them itself)
+  hipError_t e = hipSuccess;
+  if (log_by_pid) e = launch_zero_i32(c, (int32_t*)log_by_pid, pid_cap);
+  if (e == hipSuccess) {
+    if (forced_by_pid) e = launch_buffer_forced(c, forced_by_pid, log_by_pid, pid_cap);
+    else e = launch_buffer_decide(c, false, nullptr, log_by_pid, pid_cap);
+  }
+  if (e == hipSuccess) e = launch_buffer_apply(c, forced_by_pid != nullptr);
+  prof_end(c);
+  if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
+  char* hb = (char*)c->pinned;
+  c->red_valid = false;
+  HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
+  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4, hipMemcpyDeviceToHost, c->stream), "counts");
+  HIPCHK(c, hipEventRecord(c->rb_event, c->stream), "read-back event");
+  const Fields saved = c->F;
+  const bool nbr_saved = c->nbr_valid;
+  bool pre = false;
+  if (prelaunch) {
+    const int64_t n_max = std::min<int64_t>(c->cap, c->n_total + kMaxInject);
+    profile_launch(c, SPH_K_CELLS);
+    e = launch_build_cells(c, n_max, n_max, c->S.nstate);
+    prof_end(c);
+    if (e == hipSuccess) {
+      profile_launch(c, SPH_K_CORRECTION);
+      e = launch_correction(c, c->S.nstate, n_max);
+      prof_end(c);
+    }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(c->stream);
+      c->F = saved;
+      c->cells_valid = c->B_valid = c->nbr_valid = false;
+      return hip_fail(c, e, "cell build");
+    }
+    pre = true;
+  }
+  HIPCHK(c, hipEventSynchronize(c->rb_event), "buffer sync");
+  if (c->prof.on) resolve_events(c);
+  const int32_t* cnt = (const int32_t*)hb;
+  uint32_t flags = (uint32_t)cnt[1032];
+  if (flags & kFlagCapacity) {
+    // nothing was injected (and the prelaunched kernels returned at once):
+    // undo the tag changes the decisions applied, clear the flag and the
+    // counters so that the state stays usable
+    uint32_t zero = 0;
+    if (pre) {
+      (void)hipStreamSynchronize(c->stream);
+      c->F = saved;
+      c->nbr_valid = nbr_saved;
+    }
+    (void)launch_buffer_undo(c, forced_by_pid != nullptr);
+    (void)launch_zero_i32(c, c->S.counters, 1040);
+    (void)hipMemcpyAsync(c->S.flags, &zero, 4, hipMemcpyHostToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    return fail(c, SPH_E_CAPACITY, (flags & kFlagInjectOverflow)
+                                       ? "more injections than SPH_MAX_INJECT in one update"
+                                       : "particle capacity exceeded");
+  }
+  {
+    uint64_t b0 = (uint64_t)(uint32_t)cnt[1036] | ((uint64_t)(uint32_t)cnt[1037] << 32);
+    uint64_t b1 = (uint64_t)(uint32_t)cnt[1038] | ((uint64_t)(uint32_t)cnt[1039] << 32);
+    std::memcpy(&c->red_v2, &b0, 8);
+    std::memcpy(&c->red_nut, &b1, 8);
+  }
+  int64_t n_inj = cnt[1024], n_del = 0;
+  for (int b = 0; b < 256; ++b) n_del += cnt[512 + b];
+  c->next_pid = (uint64_t)(uint32_t)cnt[1033] | ((uint64_t)(uint32_t)cnt[1034] << 32);
+  c->n_total += n_inj;
+  c->n_alive += n_inj - n_del;
+  c->n_real += n_inj - n_del;
+  c->cells_valid = false;
+  c->B_valid = false;
+  if (out) {
+    std::memcpy(out->n_relabel, cnt, 256 * 4);
+    std::memcpy(out->n_inject, cnt + 256, 256 * 4);
+    std::memcpy(out->n_delete, cnt + 512, 256 * 4);
+    std::memcpy(out->n_revert, cnt + 768, 256 * 4);
+    out->n_real = c->n_real;
+    out->n_total = c->n_alive;
+  }
+  sph_status fs = check_flags(c, flags);
+  c->red_valid = fs == SPH_OK;
+  if (pre) {
+    if (fs == SPH_OK) {
+      // the prelaunched build and correction hold the updated state (the
+      // time-step maxima are over the real particles, which it keeps)
+      c->n_total = c->n_alive;
+      c->cells_valid = true;
+      c->moved = false;
+      c->B_valid = true;
+    } else {
+      // the update's particle arrays stand; the cell arrays were rebuilt
+      (void)hipStreamSynchronize(c->stream);
+      c->F = saved;
+      c->nbr_valid = false;
+    }
+  }
+  return fs;
+}
+
 }  // namespace
 
 extern "C" {
@@ -354,6 +469,10 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (const char* tl = std::getenv("SPHX_TEAM_LANES")) {   // tuning knob: 1, 2, 4 or 8
     int v = std::atoi(tl);
     if (v == 1 || v == 2 || v == 4 || v == 8) c->team_override = v;
+  }
+  if (const char* cl = std::getenv("SPHX_CORR_LANES")) {   // tuning knob: 1, 2, 4 or 8
+    int v = std::atoi(cl);
+    if (v == 1 || v == 2 || v == 4 || v == 8) c->corr_override = v;
   }
   char* w = c->ws;
   Fields& F = c->F;
@@ -399,6 +518,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   S.counters = (int32_t*)(w + pl.off_counters);
   S.flags = (uint32_t*)(w + pl.off_flags);
   S.stale = (uint32_t*)(w + pl.off_stale);
+  S.nstate = (int32_t*)(w + pl.off_nstate);
   S.red = (double*)(w + pl.off_red);
   S.pairs = (long long*)(w + pl.off_pairs);
   S.next_pid = (uint64_t*)(w + pl.off_npid);
@@ -456,15 +576,18 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
     e = hipMemcpyAsync(S.cand_cells, cand.data(), cand.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.stale, 0, 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.nstate, 0, 16, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.counters, 0, 1040 * 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.count, 0, (size_t)c->grid.ncell * 4, st);
   if (e == hipSuccess)
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 8192, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->rb_event) (void)hipEventDestroy(c->rb_event);
     delete c;
     return SPH_E_HIP;
   }
@@ -481,6 +604,7 @@ sph_status sph_destroy(sph_ctx* c) {
   }
   for (auto e : c->prof.pool) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->rb_event) (void)hipEventDestroy(c->rb_event);
   delete c;
   return SPH_OK;
 }
@@ -659,80 +783,26 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
 
 sph_status sph_advance(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* info,
                        sph_buffer_counts* counts) {
-  sph_status st = sph_build_cells(c);
-  if (st == SPH_OK) st = sph_correction(c);
+  if (!c) return SPH_E_ARG;
+  sph_status st = SPH_OK;
+  // a state left by the previous sph_advance is already built and corrected
+  // (building a built state again is the identity)
+  if (!(c->cells_valid && c->B_valid && !c->moved)) {
+    st = sph_build_cells(c);
+    if (st == SPH_OK) st = sph_correction(c);
+  }
   if (st == SPH_OK) st = sph_step(c, ctrl, info);
-  if (st == SPH_OK) st = sph_buffer_update(c, counts);
+  if (st == SPH_OK) st = buffer_update(c, nullptr, nullptr, 0, counts, true);
   return st;
 }
 
 sph_status sph_buffer_update(sph_ctx* c, sph_buffer_counts* out) {
-  return sph_buffer_update_ex(c, nullptr, nullptr, 0, out);
+  return buffer_update(c, nullptr, nullptr, 0, out, false);
 }
 
 sph_status sph_buffer_update_ex(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* log_by_pid,
                                 int64_t pid_cap, sph_buffer_counts* out) {
-  if (!c) return SPH_E_ARG;
-  if (!c->cells_valid) return fail(c, SPH_E_STATE, "sph_buffer_update needs sph_build_cells first");
-  if ((forced_by_pid || log_by_pid) && pid_cap < (int64_t)c->next_pid)
-    return fail(c, SPH_E_ARG, "pid_cap must cover every particle id (>= next_pid)");
-  profile_launch(c, SPH_K_BUFFER);
-  // the counters were cleared by the cell build (the call requires one since
-  // the last update; a failed update clears them itself)
-  hipError_t e = hipSuccess;
-  if (log_by_pid) e = launch_zero_i32(c, (int32_t*)log_by_pid, pid_cap);
-  if (e == hipSuccess) {
-    if (forced_by_pid) e = launch_buffer_forced(c, forced_by_pid, log_by_pid, pid_cap);
-    else e = launch_buffer_decide(c, false, nullptr, log_by_pid, pid_cap);
-  }
-  if (e == hipSuccess) e = launch_buffer_apply(c, forced_by_pid != nullptr);
-  prof_end(c);
-  if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
-  char* hb = (char*)c->pinned;
-  c->red_valid = false;
-  HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
-  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4, hipMemcpyDeviceToHost, c->stream), "counts");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "buffer sync");
-  if (c->prof.on) resolve_events(c);
-  const int32_t* cnt = (const int32_t*)hb;
-  uint32_t flags = (uint32_t)cnt[1032];
-  if (flags & kFlagCapacity) {
-    // nothing was injected: undo the tag changes the decisions applied,
-    // clear the flag and the counters so that the state stays usable
-    uint32_t zero = 0;
-    (void)launch_buffer_undo(c, forced_by_pid != nullptr);
-    (void)launch_zero_i32(c, c->S.counters, 1040);
-    (void)hipMemcpyAsync(c->S.flags, &zero, 4, hipMemcpyHostToDevice, c->stream);
-    (void)hipStreamSynchronize(c->stream);
-    return fail(c, SPH_E_CAPACITY, (flags & kFlagInjectOverflow)
-                                       ? "more injections than SPH_MAX_INJECT in one update"
-                                       : "particle capacity exceeded");
-  }
-  {
-    uint64_t b0 = (uint64_t)(uint32_t)cnt[1036] | ((uint64_t)(uint32_t)cnt[1037] << 32);
-    uint64_t b1 = (uint64_t)(uint32_t)cnt[1038] | ((uint64_t)(uint32_t)cnt[1039] << 32);
-    std::memcpy(&c->red_v2, &b0, 8);
-    std::memcpy(&c->red_nut, &b1, 8);
-  }
-  int64_t n_inj = cnt[1024], n_del = 0;
-  for (int b = 0; b < 256; ++b) n_del += cnt[512 + b];
-  c->next_pid = (uint64_t)(uint32_t)cnt[1033] | ((uint64_t)(uint32_t)cnt[1034] << 32);
-  c->n_total += n_inj;
-  c->n_alive += n_inj - n_del;
-  c->n_real += n_inj - n_del;
-  c->cells_valid = false;
-  c->B_valid = false;
-  if (out) {
-    std::memcpy(out->n_relabel, cnt, 256 * 4);
-    std::memcpy(out->n_inject, cnt + 256, 256 * 4);
-    std::memcpy(out->n_delete, cnt + 512, 256 * 4);
-    std::memcpy(out->n_revert, cnt + 768, 256 * 4);
-    out->n_real = c->n_real;
-    out->n_total = c->n_alive;
-  }
-  sph_status fs = check_flags(c, flags);
-  c->red_valid = fs == SPH_OK;
-  return fs;
+  return buffer_update(c, forced_by_pid, log_by_pid, pid_cap, out, false);
 }
 
 sph_status sph_buffer_decisions(sph_ctx* c, uint32_t* dec) {

@@ -61,6 +61,7 @@ struct Scratch {
   int32_t* counters;       // [4 * 256 + 8] per-buffer counts + misc
   uint32_t* flags;         // [1] error flags
   uint32_t* stale;         // [2] neighbour list outgrown (by sub-step parity)
+  int32_t* nstate;         // [4] next build's sizes after an update: n_in, n_out, skip
   double* red;             // reduction partials
   long long* pairs;        // [1] pair counter
   uint64_t* next_pid;      // [1]
@@ -107,11 +108,13 @@ struct sph_ctx {
   int pv_half = 0;
   uint32_t* pinned = nullptr;   // host staging (pinned)
   int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
+  int corr_override = 0;        // lanes per particle of the correction pass (0: auto)
   bool use_nbr = true;          // neighbour passes read the per-step list
   bool nbr_valid = false;       // the list matches the current cell build
   int substep = 0;              // acoustic sub-step being launched
   bool red_valid = false;       // red_v2 / red_nut hold the reduction of the current state
   double red_v2 = 0.0, red_nut = 0.0;
+  hipEvent_t rb_event = nullptr;  // marks the buffer update's read-back copy
   std::string err;
   sphx::Profile prof;
 };
@@ -123,8 +126,11 @@ namespace sphx {
 hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n);
 hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src);
 hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst);
-hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out);
-hipError_t launch_correction(sph_ctx* c);
+// With ns (device {n_in, n_out, skip}, written by the post-update reduction)
+// the sizes are read on the device and n_in / n_grid are upper bounds.
+hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out,
+                              const int32_t* ns = nullptr);
+hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_grid = 0);
 // time-step reduction (max |v|^2, max nu_t, flags) into S.red[0..2], and
 // into host memory when out_host3 is given; after_update also covers the
 // particles the last buffer update appended

@@ -200,10 +200,25 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
 // candidate of a batch are loaded together (the first holds its position),
 // then the candidates are tested; fn(j, r, r2, q) with q[0..NR-1] the
 // records of j.  Same pairs in the same order as for_neighbors.
+// The record passes carry less per candidate than the position-only loop:
+// deeper batches pay off, the more so the fewer lanes share a particle
+// (measured: 3 at four lanes, 6 at one or two).
+#ifndef SPHX_REC_UNROLL_WIDE
+#define SPHX_REC_UNROLL_WIDE 3
+#endif
+#ifndef SPHX_REC_UNROLL_NARROW
+#define SPHX_REC_UNROLL_NARROW 6
+#endif
+template <int L>
+constexpr int rec_unroll() {
+  return L >= 4 ? SPHX_REC_UNROLL_WIDE : SPHX_REC_UNROLL_NARROW;
+}
+
 template <typename T, int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
                                                   const T xi[3], const V4<T>* const* rec,
                                                   Fn&& fn) {
+  constexpr int kUnroll = rec_unroll<L>();
   if (pc.nbr && !(pc.stale && *pc.stale)) {
     const int cnt = pc.ncnt[i];
     for (int kb = lane; kb < cnt; kb += kUnroll * L) {

@@ -461,7 +461,7 @@ class Simulation:
 
     def advance(self, dt_adv=0.0, n_ac=0):
         """build cells, correction, one advection step, buffer update (one
-        library call)."""
+        library call; leaves the updated state built and corrected)."""
         ctrl = None
         if dt_adv > 0:
             ctrl = sph_step_ctrl(float(dt_adv), int(n_ac), 0)

@@ -393,6 +393,80 @@ def test_capacity_error_undoes_applied_tag_changes(sph, forced):
     assert cnt2.n_relabel[1] == 1 and cnt2.n_delete[1] == 1
 
 
+ADVANCE_CASES = {
+    "channel": (lambda: cases.make_channel(L=3.0, ramp_time=0.5), 1, 30),
+    "uchannel": (lambda: cases.make_uchannel(dp=0.05, Lleg=3.0), 1, 20),
+    "jet_fp64": (small_jet, 0, 15),
+    "mixer3d": (lambda: cases.make_mixer(dp=0.04), 1, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(ADVANCE_CASES))
+def test_advance_equals_the_separate_calls(sph, ora, name):
+    # sph_advance enqueues the next step's cell build and correction before
+    # it waits for the update's read-back (sizes read on the device); every
+    # step and the final state must equal those of the four calls made one
+    # by one, also when the two forms alternate on one context
+    make, prec, steps = ADVANCE_CASES[name]
+    c = relabelled(ora, make())
+    a, b = gpu_sim(sph, c, prec), gpu_sim(sph, c, prec)
+    events = 0
+    for i in range(steps):
+        if i % 3 == 2:
+            a.build_cells()
+            a.correction()
+            ia = a.step()
+            ca = a.buffer_update()
+        else:
+            ia, ca = a.advance()
+        b.build_cells()
+        b.correction()
+        ib = b.step()
+        cb = b.buffer_update()
+        assert (ia.dt_adv, ia.n_ac, ia.step) == (ib.dt_adv, ib.n_ac, ib.step)
+        for f in ("n_relabel", "n_inject", "n_delete", "n_revert"):
+            assert list(getattr(ca, f)) == list(getattr(cb, f)), f
+        assert (ca.n_total, ca.n_real) == (cb.n_total, cb.n_real)
+        events += sum(cb.n_inject) + sum(cb.n_delete)
+    a.build_cells()   # the identity after sph_advance
+    b.build_cells()
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert np.array_equal(sa[f], sb[f]), f
+    if name == "channel":
+        assert events > 0
+
+
+def test_advance_capacity_error_matches_the_update(sph):
+    # the prelaunched build turns into no-ops when the injection fails: the
+    # state after the error equals that of a plain update that failed
+    from tests.test_oracle_buffer import crafted, inlet
+    from cases import BUFFER, make_tag
+    b = inlet(1)
+    gen = b.length + b.fringe
+    pts = [(gen + 0.01, 0.2 + 0.1 * k) for k in range(5)]
+    c = crafted(pts, [make_tag(BUFFER, 1)] * 5, [b])
+    g1 = gpu_sim(sph, c, sph.SPH_FP64, capacity=7)
+    g1.build_cells()
+    g1.correction()
+    g1.step()
+    with pytest.raises(sph.SphError) as e1:
+        g1.buffer_update()
+    g2 = gpu_sim(sph, c, sph.SPH_FP64, capacity=7)
+    with pytest.raises(sph.SphError) as e2:
+        g2.advance()
+    assert e1.value.status == e2.value.status == sph.SPH_E_CAPACITY
+    s1, s2 = g1.state(), g2.state()
+    for f in s1:
+        assert np.array_equal(s1[f], s2[f]), f
+    # both stay usable and fail the same way again
+    for g in (g1, g2):
+        g.build_cells()
+        with pytest.raises(sph.SphError) as e:
+            g.buffer_update()
+        assert e.value.status == sph.SPH_E_CAPACITY
+
+
 def test_empty_and_tiny_domains(sph):
     c = block_case(dim=2, n_side=1)
     g = sph.Simulation(c, precision=sph.SPH_FP32_MIXED)
