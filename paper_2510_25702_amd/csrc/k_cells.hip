@@ -278,6 +278,7 @@ struct GatherArgs {
   int32_t* cello;
   uint32_t* flags;
   const int32_t* ns;   // sizes on the device (prelaunched build), or NULL
+  V4<T>* arec[3];      // advection records (written)
 };
 
 // K3b: place every particle at its cell-ordered slot and copy its fields
@@ -304,13 +305,16 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
   const int d = b + rank;
   if (d >= n_out) return;
   int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
+  T xr[3], vr[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double xv = a.x[k][s];
     a.xo[k][d] = xv;
     double org = (k < DIM) ? a.g.lo[k] + (double)cc[k] * a.g.cs : 0.0;
-    a.xro[k][d] = (T)(xv - org);
-    a.vo[k][d] = a.v[k][s];
+    xr[k] = (T)(xv - org);
+    a.xro[k][d] = xr[k];
+    vr[k] = a.v[k][s];
+    a.vo[k][d] = vr[k];
   }
   double r = a.rho[s];
   a.rhoo[d] = r;
@@ -318,13 +322,20 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
   uint32_t t = a.tag[s];
   a.tago[d] = t;
   a.pido[d] = a.pid[s];
-  a.volo[d] = (T)(tag_kind(t) == kWall ? a.Vw : a.mass / r);
+  const bool wall = tag_kind(t) == kWall;
+  const T vol = (T)(wall ? a.Vw : a.mass / r);
+  a.volo[d] = vol;
   a.cello[d] = c;
+  T kt = T(0), et = T(0), nt = T(0);
   if (a.turb) {
-    a.ko[d] = a.k[s];
-    a.epso[d] = a.eps[s];
-    a.nuto[d] = a.nut[s];
+    kt = a.k[s];
+    et = a.eps[s];
+    nt = a.nut[s];
+    a.ko[d] = kt;
+    a.epso[d] = et;
+    a.nuto[d] = nt;
   }
+  write_arec<T, DIM>(a.arec, d, xr, vr, wall ? -vol : vol, nt, kt, et, a.turb != 0);
 }
 
 template <typename T>
@@ -392,6 +403,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32
   a.cello = F.cell;
   a.flags = S.flags;
   a.ns = ns;
+  for (int k = 0; k < 3; ++k) a.arec[k] = static_cast<V4<T>*>(F.arec[k]);
   k_place<T, DIM><<<(int)((n_in + 255) / 256) + (n_in == 0), 256, 0, st>>>((int)n_in, (int)n_out, a);
   for (int k = 0; k < 3; ++k) {
     F.x[k].flip();

@@ -165,6 +165,7 @@ struct AdvArgs {
   double *o_anu, *o_gradv, *o_dk, *o_deps;
   int64_t n_out;
   V4<T>* prec[3];   // pressure records of sub-step 0 (written)
+  const V4<T>* arec[3];   // advection records (cell build)
 };
 
 template <typename T, int DIM, int TURB, int L>
@@ -201,24 +202,36 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     Dk_i = (T)C.nu_l + nut_i / (T)C.sigma_k;
     De_i = (T)C.nu_l + nut_i / (T)C.sigma_eps;
   }
-  for_neighbors<T, DIM, L>(pc, i, lane, xi, [&](int j, const T r[3], T r2) {
+  constexpr int NR = (DIM == 3 && TURB) ? 3 : 2;
+  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec,
+                                   [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
     const T rr = sqrt(r2);
     const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
-    const T Vj = pc.vol[j];
-    const bool wall = tag_kind(pc.tag[j]) == kWall;
+    T vj[3], volw, nut_rj, k_j, eps_j;
+    if (DIM == 2) {
+      vj[0] = q[0].c; vj[1] = q[0].d; vj[2] = T(0);
+      volw = q[1].a; nut_rj = q[1].b; k_j = q[1].c; eps_j = q[1].d;
+    } else {
+      vj[0] = q[0].d; vj[1] = q[1].a; vj[2] = q[1].b;
+      volw = q[1].c; nut_rj = q[1].d;
+      k_j = TURB ? q[2].a : T(0);
+      eps_j = TURB ? q[2].b : T(0);
+    }
+    const bool wall = volw < T(0);
+    const T Vj = wall ? -volw : volw;
     // no-slip dummy wall: antisymmetric velocity, same viscosity as i
     T vij[3];
     if (wall) {
       vij[0] = T(2) * vi[0]; vij[1] = T(2) * vi[1]; vij[2] = T(2) * vi[2];
     } else {
-      vij[0] = vi[0] - a.v[0][j];
-      vij[1] = vi[1] - a.v[1][j];
-      vij[2] = DIM == 3 ? vi[2] - a.v[2][j] : T(0);
+      vij[0] = vi[0] - vj[0];
+      vij[1] = vi[1] - vj[1];
+      vij[2] = DIM == 3 ? vi[2] - vj[2] : T(0);
     }
     T mu_ad;
     if (TURB) {
-      const T nut_j = wall ? nut_i : a.nut[j];
+      const T nut_j = wall ? nut_i : nut_rj;
       const T mu_j = C.rho0_t * ((T)C.nu_l + nut_j);
       const T mu_h = T(2) * mu_i * mu_j / (mu_i + mu_j);
       // ARD limiter: beta = min(eta max(v_ij . e_ij, 0), c0), e_ij from i to j
@@ -244,11 +257,11 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
 #pragma unroll
         for (int q = 0; q < DIM; ++q) G[3 * p + q] -= Vj * vij[p] * BgW[q];
       if (!wall) {
-        const T nut_j = a.nut[j];
+        const T nut_j = nut_rj;
         const T Dk_j = (T)C.nu_l + nut_j / (T)C.sigma_k;
         const T De_j = (T)C.nu_l + nut_j / (T)C.sigma_eps;
-        dfk += T(2) * Dk_i * Dk_j / (Dk_i + Dk_j) * (ki - a.k[j]) * f * Vj;
-        dfe += T(2) * De_i * De_j / (De_i + De_j) * (ei - a.eps[j]) * f * Vj;
+        dfk += T(2) * Dk_i * Dk_j / (Dk_i + Dk_j) * (ki - k_j) * f * Vj;
+        dfe += T(2) * De_i * De_j / (De_i + De_j) * (ei - eps_j) * f * Vj;
       }
     }
   });
@@ -922,6 +935,7 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   a.o_deps = out ? out->deps : nullptr;
   a.n_out = c->n_total;
   for (int k = 0; k < 3; ++k) a.prec[k] = tp<V4<T>>(F.prec[k]);
+  for (int k = 0; k < 3; ++k) a.arec[k] = tp<V4<T>>(F.arec[k]);
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {

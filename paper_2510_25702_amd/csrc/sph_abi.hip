@@ -161,7 +161,7 @@ struct Plan {
       off_nut[2], off_tag[2], off_pid[2], off_p[2], off_vol[2], off_B[6], off_anu[3], off_cell,
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
-      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_nstate;
+      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate;
   int n_cand;
 };
 
@@ -196,6 +196,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   for (int k = 0; k < 3; ++k) pl->off_xrb[k] = L.take(C * sT);
   for (int k = 0; k < 3; ++k) pl->off_prec[k] = L.take((P->dim == 3 || k < 2) ? C * 4 * sT : 0);
   for (int k = 0; k < 2; ++k) pl->off_drec[k] = L.take(C * 4 * sT);
+  for (int k = 0; k < 3; ++k) pl->off_arec[k] = L.take((P->dim == 3 || k < 2) ? C * 4 * sT : 0);
   pl->off_key = L.take(C * 4);
   pl->off_slot = L.take(C * 4);
   pl->off_perm = L.take(C * 4);
@@ -501,6 +502,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   for (int k = 0; k < 3; ++k) F.xrb[k] = w + pl.off_xrb[k];
   for (int k = 0; k < 3; ++k) F.prec[k] = w + pl.off_prec[k];
   for (int k = 0; k < 2; ++k) F.drec[k] = w + pl.off_drec[k];
+  for (int k = 0; k < 3; ++k) F.arec[k] = w + pl.off_arec[k];
   F.nbr_k = params->dim == 2 ? kNbrMax2 : kNbrMax3;
   if (const char* nl = std::getenv("SPHX_NBR_LIST")) c->use_nbr = std::atoi(nl) != 0;
   Scratch& S = c->S;

@@ -44,6 +44,7 @@ struct Fields {
   // j-side records of the pressure / continuity passes (16-byte vectors of T)
   void* prec[3];           // position, p, volume (negative: wall), B
   void* drec[2];           // position, velocity, p, volume (negative: wall)
+  void* arec[3];           // position, velocity, volume (negative: wall), RANS fields
 };
 
 struct Scratch {

@@ -224,4 +224,29 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
   return v;
 }
 
+// Four pair-precision values, loaded and stored as one 16-byte (float) or
+// two 16-byte (double) vector accesses: the j-side records of the
+// neighbour passes.
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T a, b, c, d;
+};
+
+// Record of particle j for the advection pass, written by the cell build:
+// position, velocity, V (negative for a wall) and the RANS fields.
+// 2D: {x0, x1, v0, v1} {Vw, nut, k, eps};
+// 3D: {x0, x1, x2, v0} {v1, v2, Vw, nut} {k, eps, 0, 0} (the third only with RANS).
+template <typename T, int DIM>
+__device__ __forceinline__ void write_arec(V4<T>* const* ar, int i, const T x[3], const T v[3],
+                                           T volw, T nut, T k, T eps, bool turb) {
+  if (DIM == 2) {
+    ar[0][i] = V4<T>{x[0], x[1], v[0], v[1]};
+    ar[1][i] = V4<T>{volw, nut, k, eps};
+  } else {
+    ar[0][i] = V4<T>{x[0], x[1], x[2], v[0]};
+    ar[1][i] = V4<T>{v[1], v[2], volw, nut};
+    if (turb) ar[2][i] = V4<T>{k, eps, T(0), T(0)};
+  }
+}
+
 }  // namespace sphx

@@ -158,13 +158,6 @@ __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int l
   }
 }
 
-// Four pair-precision values, loaded and stored as one 16-byte (float) or
-// two 16-byte (double) vector accesses.
-template <typename T>
-struct alignas(4 * sizeof(T)) V4 {
-  T a, b, c, d;
-};
-
 // Record of particle j for the pressure pass: position, p, V (negative for
 // a wall), correction matrix.  2D: {x0, x1, p, Vw} {Bxx, Bxy, Byy, 0};
 // 3D: {x0, x1, x2, p} {Vw, Bxx, Bxy, Bxz} {Byy, Byz, Bzz, 0}.
