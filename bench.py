@@ -50,7 +50,132 @@ def parse():
                          "calibration under rocprofv3) and exit")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-checkpoint", type=int, default=10)
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
+                    help="write the Markdown table of a rocprofv3 --stats output directory "
+                         "(COMMAND: the command that produced it) and exit; no GPU needed")
+    ap.add_argument("--summarize-traffic", nargs=4,
+                    metavar=("COPY_FETCH", "COPY_WRITE", "RUN_FETCH", "RUN_WRITE"),
+                    help="fold four rocprofv3 --pmc output directories (FETCH_SIZE and "
+                         "WRITE_SIZE of the copy calibration, then of a bench run of "
+                         "--workload) into profiles/hbm_traffic.json and a Markdown table; "
+                         "no GPU needed")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 output summaries (profiles/)
+# ---------------------------------------------------------------------------
+def _kernel_label(name):
+    import re
+    n = re.sub(r"^void ", "", name)
+    n = re.sub(r"^sphx::(\(anonymous namespace\)::)?", "", n)
+    depth, out = 0, []
+    for ch in n:                       # drop the argument list, keep template args
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out)
+
+
+def _one_csv(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def summarize_stats(d, out_md, command):
+    import csv
+    rows = list(csv.DictReader(open(_one_csv(d, "kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"Command (repository root, one MI355X):", "", "```", command, "```", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{_kernel_label(r['Name'])}` | {int(r['Calls'])} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    head = open(out_md).read().split("Command (repository root")[0] if os.path.exists(out_md) else ""
+    with open(out_md, "w") as fh:
+        fh.write(head + "\n".join(lines) + "\n")
+    print(f"wrote {out_md}")
+
+
+def _counter_per_kernel(d, counter):
+    """Mean per dispatch of `counter` over the second half of each kernel's
+    dispatches (the first half includes the warm-up's ramp)."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(_one_csv(d, "counter_collection.csv"))):
+        if r["Counter_Name"] != counter:
+            continue
+        per.setdefault(_kernel_label(r["Kernel_Name"]), []).append(
+            (int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    out = {}
+    for k, v in per.items():
+        v.sort()
+        half = [x for _, x in v[len(v) // 2:]]
+        out[k] = (sum(half) / len(half), max(x for _, x in v))
+    return out
+
+
+def summarize_traffic(args, cf, cw, bf, bw):
+    copy_bytes = 256 * (1 << 20)
+    fetch_copy = max(m for _, m in _counter_per_kernel(cf, "FETCH_SIZE").values())
+    write_copy = max(m for _, m in _counter_per_kernel(cw, "WRITE_SIZE").values())
+    fs = copy_bytes / 1024 / fetch_copy
+    ws = copy_bytes / 1024 / write_copy
+    fetch = _counter_per_kernel(bf, "FETCH_SIZE")
+    write = _counter_per_kernel(bw, "WRITE_SIZE")
+    names = {"k_pressure": "pressure", "k_density": "density", "k_advection": "advection",
+             "k_correction": "correction"}
+    kernels, rows = {}, []
+    for label in sorted(fetch):
+        base = label.split("<")[0]
+        if base not in names or label not in write:
+            continue
+        f, w = fetch[label][0], write[label][0]
+        b = int(round((f * fs + w * ws) * 1024))
+        kernels[f"{args.workload}/fp32/{names[base]}"] = {
+            "kernel": label, "FETCH_SIZE_KiB": round(f, 1), "WRITE_SIZE_KiB": round(w, 1),
+            "bytes_per_launch": b}
+        rows.append(f"| `{label}` | {f:.1f} | {w:.1f} | {b:,} |")
+    run = f"python bench.py --workload {args.workload} --steps 20 --warmup 5 --no-cpu --no-fp64 --no-adjoint"
+    cmds = [f"rocprofv3 --pmc FETCH_SIZE -d {cf} -o cf --output-format csv -- python bench.py --calibrate-copy 256",
+            f"rocprofv3 --pmc WRITE_SIZE -d {cw} -o cw --output-format csv -- python bench.py --calibrate-copy 256",
+            f"rocprofv3 --pmc FETCH_SIZE -d {bf} -o bf --output-format csv -- {run}",
+            f"rocprofv3 --pmc WRITE_SIZE -d {bw} -o bw --output-format csv -- {run}"]
+    rec = {"description": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB "
+                          "per dispatch), each scaled by its reading for a device-to-device copy "
+                          "of 256 MiB; mean over the second half of each kernel's launches",
+           "source_hash": kernel_source_hash(),
+           "calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB_per_copy": fetch_copy,
+                           "WRITE_SIZE_KiB_per_copy": write_copy, "fetch_scale": round(fs, 5),
+                           "write_scale": round(ws, 5)},
+           "commands": cmds, "kernels": kernels, "hashed_sources": list(TRAFFIC_SOURCES)}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    md = os.path.join(ROOT, "profiles", f"hbm_traffic_{args.workload}_fp32.md")
+    with open(md, "w") as fh:
+        fh.write(f"# HBM traffic per launch: {args.workload} workload, FP32-mixed (rocprofv3 counters)\n\n"
+                 "FETCH_SIZE and WRITE_SIZE in separate runs, each scaled by the same counter's "
+                 "reading for a plain device-to-device copy of 256 MiB (`bench.py "
+                 f"--calibrate-copy 256`): FETCH_SIZE reads {fetch_copy:.0f} KiB per copy of "
+                 f"{copy_bytes // 1024} KiB (scale {fs:.4f}), WRITE_SIZE reads {write_copy:.0f} KiB "
+                 f"(scale {ws:.4f}).  Mean per launch over the second half of each kernel's "
+                 "launches.\n\nCommands (repository root, one MI355X), then "
+                 "`python bench.py --workload " + args.workload + " --summarize-traffic "
+                 f"{cf} {cw} {bf} {bw}`:\n\n```\n" + "\n".join(cmds) + "\n```\n\n"
+                 "| kernel | FETCH KiB | WRITE KiB | HBM bytes per launch (scaled) |\n"
+                 "|---|---:|---:|---:|\n" + "\n".join(rows) + "\n\n"
+                 f"Digest of the neighbour-pass sources (`kernel_source_hash`: "
+                 f"{', '.join(TRAFFIC_SOURCES)}): `{rec['source_hash']}`; bench.py reports the "
+                 "figure of its dominant kernel as `roofline.traffic` only while the digest "
+                 "matches.\n")
+    print(f"wrote {path} and {md}")
 
 
 def make_case(name):
@@ -204,6 +329,12 @@ def cpu_baseline(case, seconds):
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(args, *args.summarize_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"decomposition is a design note, not part of this build.", file=sys.stderr)

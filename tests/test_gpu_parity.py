@@ -171,6 +171,64 @@ def test_pair_operators(sph, ora, name, turb, mode, pname, prec, tol):
     assert max(errs.values()) < tol, errs
 
 
+# launch configurations of the neighbour passes (set at context creation):
+# the per-step list with the automatic lane counts, the plain cell stencil,
+# and fixed lane counts per particle (the correction's set apart)
+LAUNCH = {
+    "list": {},
+    "stencil": {"SPHX_NBR_LIST": "0"},
+    "teams_1": {"SPHX_TEAM_LANES": "1"},
+    "teams_2_corr_8": {"SPHX_TEAM_LANES": "2", "SPHX_CORR_LANES": "8"},
+    "teams_8_corr_1": {"SPHX_TEAM_LANES": "8", "SPHX_CORR_LANES": "1"},
+}
+
+
+@pytest.mark.parametrize("launch", list(LAUNCH))
+@pytest.mark.parametrize("name,turb,mode", [("jet", None, None), ("channel", 1, 2)])
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_pair_operators_every_launch(sph, ora, monkeypatch, launch, name, turb, mode,
+                                     pname, prec, tol):
+    for k, v in LAUNCH[launch].items():
+        monkeypatch.setenv(k, v)
+    c = relabelled(ora, perturbed(name, turb, mode))
+    ref = ora.OracleSim(c, threads=8)
+    ro = ref.rates()
+    Bo, _ = ref.correction()
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    rg = g.rates()
+    gi = pid_index(g.state()["pid"])
+    idx = np.array([gi[int(p)] for p in c.pid])
+    real = (c.tag & 3) != 2
+    fields = ["ap", "drho", "anu", "p"] + (["gradv", "dk", "deps"] if c.params["turbulence"] else [])
+    errs = {f: normwise(rg[f][idx][real], ro[f][real]) for f in fields}
+    errs["B"] = normwise(rg["B"][idx][real], Bo[real])
+    assert max(errs.values()) < tol, errs
+
+
+@pytest.mark.parametrize("launch", ["list", "stencil", "teams_1"])
+@pytest.mark.parametrize("pname,prec,tol", [("fp64", 0, 1e-10), ("fp32", 1, 2e-5)])
+def test_one_step_every_launch(sph, ora, monkeypatch, launch, pname, prec, tol):
+    for k, v in LAUNCH[launch].items():
+        monkeypatch.setenv(k, v)
+    c = developing_channel(ora)
+    ref = ora.OracleSim(c, threads=8)
+    g = gpu_sim(sph, c, prec)
+    Io = ref.step()
+    g.build_cells()
+    g.correction()
+    Ig = g.step()
+    assert Ig.n_ac == Io.n_ac
+    so, sg = ref.snapshot(), g.state()
+    gi = pid_index(sg["pid"])
+    idx = np.array([gi[int(p)] for p in so["pid"]])
+    vmax = np.abs(so["v"]).max()
+    assert np.abs(sg["v"][idx] - so["v"]).max() < tol * vmax
+    assert np.abs(sg["x"][idx] - so["x"]).max() < tol * c.params["dp"]
+    assert np.abs(sg["rho"][idx] - so["rho"]).max() < tol
+
+
 @pytest.mark.parametrize("name", ["uchannel", "jet_full"])
 @pytest.mark.parametrize("pname,prec,tol", PREC)
 def test_pair_operators_full_size(sph, ora, name, pname, prec, tol):
