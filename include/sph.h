@@ -154,10 +154,12 @@ typedef struct {
   int64_t step;
 } sph_step_info;
 
-/* Kernel timing (HIP events on the context stream) for profiling. */
+/* Kernel timing (HIP events on the context stream) for profiling.
+ * SPH_K_EVENTS times an empty pair of events, recorded once per profiled
+ * sph_step: the markers' own share of every other entry's durations. */
 enum { SPH_K_CELLS = 0, SPH_K_CORRECTION = 1, SPH_K_ADVECTION = 2,
        SPH_K_PRESSURE = 3, SPH_K_DENSITY = 4, SPH_K_BUFFER = 5,
-       SPH_K_REDUCE = 6, SPH_K_COUNT = 7 };
+       SPH_K_REDUCE = 6, SPH_K_EVENTS = 7, SPH_K_COUNT = 8 };
 typedef struct {
   double total_ms;       /* summed kernel durations */
   int64_t launches;
@@ -376,6 +378,31 @@ size_t sph_adjoint_workspace_size(const sph_ctx* ctx, int32_t max_nac);
 sph_status sph_adjoint_step(sph_ctx* ctx, const sph_particles* pre, int64_t n_pre,
                             const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
                             double* lam, double* grad, void* adj_ws, size_t adj_bytes);
+
+/* The two halves of sph_adjoint_step, for a reverse sweep that does not
+ * replay each step a second time (the checkpointed recomputation of a
+ * segment runs sph_adjoint_forward, one workspace per step, and the reverse
+ * then walks the workspaces back).
+ *
+ * sph_adjoint_forward: the recorded step (same ctl as sph_adjoint_step)
+ * from the context's current state, which must be the step's start state
+ * (its next particle id must equal ctl->next_pid: SPH_E_STATE): cell build,
+ * correction with the neighbour list, the step with every sub-step state
+ * kept in adj_ws, and the replayed buffer update.  adj_ws also keeps the
+ * step's cell build, list, correction matrices and update data, so that the
+ * reverse does not read the context's state.  *n_step receives the step's
+ * particle slots.  Leaves the context at the state after the update.
+ * Asynchronous.
+ *
+ * sph_adjoint_reverse: the reverse sweep of sph_adjoint_step from a
+ * workspace filled by sph_adjoint_forward (and n_step from that call); lam
+ * and grad as in sph_adjoint_step.  Reads no particle state of the context.
+ * Synchronises. */
+sph_status sph_adjoint_forward(sph_ctx* ctx, const sph_adjoint_ctrl* ctl, void* adj_ws,
+                               size_t adj_bytes, int64_t* n_step);
+sph_status sph_adjoint_reverse(sph_ctx* ctx, const sph_objective_desc* obj,
+                               const sph_adjoint_ctrl* ctl, int64_t n_step, double* lam,
+                               double* grad, void* adj_ws, size_t adj_bytes);
 
 #ifdef __cplusplus
 }

@@ -427,10 +427,12 @@ __global__ __launch_bounds__(256) void k_adj_post(AdjDev A, PostArgs a, int N) {
   A.lD[i] = l[7];
 }
 
-__global__ __launch_bounds__(256) void k_adj_children(AdjDev A, const int32_t* counters,
-                                                      const int32_t* inj_idx, uint64_t base_pid) {
+__global__ __launch_bounds__(256) void k_adj_children(AdjDev A, const int32_t* inj,
+                                                      uint64_t base_pid) {
+  // inj[0]: injections of the update, inj[1 + r]: parent slot of child r
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = counters[1024];
+  const int m = inj[0];
+  const int32_t* inj_idx = inj + 1;
   if (r >= m || r >= kMaxInject) return;
   const int i = inj_idx[r];
   if (i >= 0 && i < A.n) A.child[i] = (int32_t)(base_pid + (uint64_t)r);
@@ -1194,13 +1196,17 @@ struct AdjLayout {
     return o;
   }
   size_t X, XR, V, RH, P, VOL, DD, rho0, vol0, tag, cot, abar, child;
+  // the step's cell build, neighbour list, correction and buffer update,
+  // kept so that the reverse sweep does not depend on the context's state
+  size_t pid, cell, cs, nbr, ncnt, stale, B, dec, inj;
   int ncot;
 };
 
 constexpr int kCot = 3 + 3 + 1 + 1 + 1 + 1 + 1 + 6 + 3 + 3 + 3 + 3 + 6 + 1;
 
-AdjLayout adj_layout(int64_t cap, int N) {
+AdjLayout adj_layout(const sph_ctx* c, int N) {
   AdjLayout L;
+  const int64_t cap = c->cap;
   const size_t c8 = (size_t)cap * 8;
   L.X = L.take(c8 * 3 * (N + 1));
   L.XR = L.take(c8 * 3 * (N + 1));
@@ -1215,6 +1221,15 @@ AdjLayout adj_layout(int64_t cap, int N) {
   L.cot = L.take(c8 * kCot);
   L.abar = L.take(c8 * 16);
   L.child = L.take((size_t)cap * 4);
+  L.pid = L.take((size_t)cap * 4);
+  L.cell = L.take((size_t)cap * 4);
+  L.cs = L.take(((size_t)c->grid.ncell + 1) * 4);
+  L.nbr = L.take((size_t)c->F.nbr_k * cap * 4);
+  L.ncnt = L.take((size_t)cap * 4);
+  L.stale = L.take(8);
+  L.B = L.take(c8 * 6);
+  L.dec = L.take((size_t)cap * 4);
+  L.inj = L.take(((size_t)kMaxInject + 1) * 4);   // [0]: injections, then the slots
   L.ncot = kCot;
   return L;
 }
@@ -1225,15 +1240,15 @@ AdjDev make_adj(sph_ctx* c, char* ws, const AdjLayout& L, int n, int64_t pid_cap
   A.cap = c->cap;
   A.pid_cap = pid_cap;
   A.tag = (const uint32_t*)(ws + L.tag);
-  A.pid = c->F.pid.live();
-  A.cell = c->F.cell;
-  A.cs = c->S.cell_start;
+  A.pid = (const uint32_t*)(ws + L.pid);
+  A.cell = (const int32_t*)(ws + L.cell);
+  A.cs = (const int32_t*)(ws + L.cs);
   A.nx = c->grid.n[0];
   A.ny = c->grid.n[1];
   A.csz = c->P.cell_size;
-  A.nbr = c->use_nbr && c->nbr_valid ? c->F.nbr : nullptr;
-  A.ncnt = c->F.ncnt;
-  A.stale = c->S.stale;
+  A.nbr = (const uint32_t*)(ws + L.nbr);   // used unless the kept stale words say so
+  A.ncnt = (const int32_t*)(ws + L.ncnt);
+  A.stale = (const uint32_t*)(ws + L.stale);
   const double rc = 2.0 * c->P.h;
   A.rc2 = rc * rc;
   A.inv_h = 1.0 / c->P.h;
@@ -1249,7 +1264,7 @@ AdjDev make_adj(sph_ctx* c, char* ws, const AdjLayout& L, int n, int64_t pid_cap
   A.DD = (double*)(ws + L.DD);
   A.rho0 = (double*)(ws + L.rho0);
   A.vol0 = (double*)(ws + L.vol0);
-  for (int k = 0; k < 6; ++k) A.B[k] = (const double*)c->F.B[k];
+  for (int k = 0; k < 6; ++k) A.B[k] = (const double*)(ws + L.B) + (int64_t)k * c->cap;
   double* cot = (double*)(ws + L.cot);
   int o = 0;
   auto nxt = [&]() { double* p = cot + (int64_t)o * c->cap; ++o; return p; };
@@ -1319,8 +1334,8 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
 
   // children of the update
   k_fill_child<<<nb, 256, 0, st>>>(n, A.child);
-  k_adj_children<<<(kMaxInject + 255) / 256, 256, 0, st>>>(A, c->S.counters, c->S.inj_idx,
-                                                           ctl->next_pid);
+  k_adj_children<<<(kMaxInject + 255) / 256, 256, 0, st>>>(
+      A, (const int32_t*)(ws + Lw.inj), ctl->next_pid);
   // clear the cotangent accumulators
   k_zero_d<<<(int)(((int64_t)kCot * c->cap + 255) / 256), 256, 0, st>>>((int64_t)kCot * c->cap,
                                                                         A.lx[0]);
@@ -1328,7 +1343,7 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
 
   PostArgs pa;
   pa.lam = lam;
-  pa.dec = c->S.dec;
+  pa.dec = (const uint32_t*)(ws + Lw.dec);
   pa.bufs = c->S.bufs;
   pa.bidx = c->S.bidx;
   pa.control_q = control_q;
@@ -1405,7 +1420,7 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
 
 size_t adjoint_ws_bytes(const sph_ctx* c, int max_nac) {
   if (c->P.precision != SPH_FP64 || c->P.turbulence || max_nac < 1) return 0;
-  return adj_layout(c->cap, max_nac).total;
+  return adj_layout(c, max_nac).total;
 }
 
 hipError_t launch_objective(sph_ctx* c, const sph_objective_desc* obj, const uint8_t* member_in,
@@ -1459,7 +1474,7 @@ hipError_t launch_objective(sph_ctx* c, const sph_objective_desc* obj, const uin
 
 // Snapshot hooks of the replayed forward step (FP64 context).
 hipError_t adjoint_snap_start(sph_ctx* c, char* ws, int N) {
-  AdjLayout L = adj_layout(c->cap, N);
+  AdjLayout L = adj_layout(c, N);
   const int n = (int)c->n_total;
   const int64_t cap = c->cap;
   double* X = (double*)(ws + L.X);
@@ -1476,7 +1491,7 @@ hipError_t adjoint_snap_start(sph_ctx* c, char* ws, int N) {
 }
 
 hipError_t adjoint_snap_advection(sph_ctx* c, char* ws, int N) {
-  AdjLayout L = adj_layout(c->cap, N);
+  AdjLayout L = adj_layout(c, N);
   const int n = (int)c->n_total;
   Fields& F = c->F;
   snap_copy(c, n, {{F.rho.live(), (double*)(ws + L.RH)}, {F.p.live(), (double*)(ws + L.P)},
@@ -1485,7 +1500,7 @@ hipError_t adjoint_snap_advection(sph_ctx* c, char* ws, int N) {
 }
 
 hipError_t adjoint_snap_pressure(sph_ctx* c, char* ws, int N, int s) {
-  AdjLayout L = adj_layout(c->cap, N);
+  AdjLayout L = adj_layout(c, N);
   const int n = (int)c->n_total;
   const int64_t cap = c->cap;
   const int64_t o = (int64_t)(s + 1) * 3 * cap;
@@ -1500,7 +1515,7 @@ hipError_t adjoint_snap_pressure(sph_ctx* c, char* ws, int N, int s) {
 }
 
 hipError_t adjoint_snap_density(sph_ctx* c, char* ws, int N, int s) {
-  AdjLayout L = adj_layout(c->cap, N);
+  AdjLayout L = adj_layout(c, N);
   const int n = (int)c->n_total;
   const int64_t cap = c->cap;
   Fields& F = c->F;
@@ -1515,9 +1530,47 @@ hipError_t adjoint_snap_density(sph_ctx* c, char* ws, int N, int s) {
   return hipGetLastError();
 }
 
+// After the step's buffer update: the build, list, correction and update
+// data of the step into the workspace (the list only while it was built;
+// otherwise the kept stale words send the reverse passes to the stencil).
+hipError_t adjoint_keep_step(sph_ctx* c, char* ws, int N, int n_step) {
+  AdjLayout L = adj_layout(c, N);
+  hipStream_t st = c->stream;
+  const int64_t cap = c->cap;
+  const int n_after = (int)c->n_total;
+  hipError_t e = hipMemcpyAsync(ws + L.pid, c->F.pid.live(), (size_t)n_after * 4,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.cell, c->F.cell, (size_t)n_step * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.cs, c->S.cell_start, ((size_t)c->grid.ncell + 1) * 4,
+                       hipMemcpyDeviceToDevice, st);
+  const bool list = c->use_nbr && c->nbr_valid;
+  if (e == hipSuccess && list && n_step > 0)
+    e = hipMemcpy2DAsync(ws + L.nbr, (size_t)cap * 4, c->F.nbr, (size_t)cap * 4,
+                         (size_t)n_step * 4, (size_t)c->F.nbr_k, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.ncnt, c->F.ncnt, (size_t)n_step * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    if (list) e = hipMemcpyAsync(ws + L.stale, c->S.stale, 8, hipMemcpyDeviceToDevice, st);
+    else e = hipMemsetAsync(ws + L.stale, 0xFF, 8, st);
+  }
+  for (int k = 0; k < 6 && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(ws + L.B + (size_t)k * cap * 8, c->F.B[k], (size_t)n_step * 8,
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.dec, c->S.dec, (size_t)n_step * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.inj, c->S.counters + 1024, 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.inj + 4, c->S.inj_idx, (size_t)kMaxInject * 4,
+                       hipMemcpyDeviceToDevice, st);
+  return e;
+}
+
 hipError_t adjoint_reverse_launch(sph_ctx* c, char* ws, const sph_objective_desc* obj,
                                   const sph_adjoint_ctrl* ctl, int n, double* lam, double* grad) {
-  AdjLayout L = adj_layout(c->cap, ctl->n_ac);
+  AdjLayout L = adj_layout(c, ctl->n_ac);
   return c->P.dim == 2 ? adjoint_reverse<2>(c, L, ws, obj, ctl, n, lam, grad)
                        : adjoint_reverse<3>(c, L, ws, obj, ctl, n, lam, grad);
 }

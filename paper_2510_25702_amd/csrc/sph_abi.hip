@@ -707,6 +707,10 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
   if (!c->cells_valid || c->moved || !c->B_valid)
     return fail(c, SPH_E_STATE, "sph_step needs sph_build_cells and sph_correction first");
   if (ctrl && ctrl->dt_adv > 0 && ctrl->n_ac < 1) return fail(c, SPH_E_ARG, "ctrl->n_ac must be >= 1");
+  if (c->prof.on) {   // the event markers' own time, to be taken off the kernels'
+    prof_begin(c, SPH_K_EVENTS, 0.0, 0.0);
+    prof_end(c);
+  }
   double v2max, nutmax;
   hipError_t e;
   if (c->red_valid) {
@@ -913,11 +917,13 @@ size_t sph_adjoint_workspace_size(const sph_ctx* c, int32_t max_nac) {
   return adjoint_ws_bytes(c, max_nac);
 }
 
-sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
-                            const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
-                            double* lam, double* grad, void* adj_ws, size_t adj_bytes) {
-  if (!c) return SPH_E_ARG;
-  if (!pre || !obj || !ctl || !lam || !grad) return fail(c, SPH_E_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+sph_status adjoint_check(sph_ctx* c, const sph_adjoint_ctrl* ctl, const void* adj_ws,
+                         size_t adj_bytes) {
+  if (!ctl) return fail(c, SPH_E_ARG, "null argument");
   if (c->P.precision != SPH_FP64 || c->P.turbulence)
     return fail(c, SPH_E_ARG, "the adjoint needs an FP64 laminar context");
   if (ctl->n_ac < 1 || !(ctl->dt_adv > 0)) return fail(c, SPH_E_ARG, "bad dt_adv / n_ac");
@@ -926,17 +932,18 @@ sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
   const size_t need = adjoint_ws_bytes(c, ctl->n_ac);
   if (!adj_ws || adj_bytes < need || ((uintptr_t)adj_ws & 255))
     return fail(c, SPH_E_ARG, "adjoint workspace too small or not 256-byte aligned");
-  if (!(obj->slab_width > 0) || !(obj->wall_length > 0))
-    return fail(c, SPH_E_ARG, "slab_width and wall_length must be > 0");
-  char* ws = (char*)adj_ws;
+  return SPH_OK;
+}
+
+// The recorded step from the context's state, keeping its sub-step states
+// and its build, list, correction and update data in the workspace.
+sph_status adjoint_forward(sph_ctx* c, const sph_adjoint_ctrl* ctl, char* ws, int64_t* n_step) {
   const int N = ctl->n_ac;
   const double dt = ctl->dt_adv / N;
-  // replay the step from its start state, keeping the sub-step states
-  sph_status st = sph_set_particles(c, n_pre, ctl->next_pid, pre);
-  if (st != SPH_OK) return st;
   c->step = ctl->step;
   c->t = ctl->t;
-  if ((st = sph_build_cells(c)) != SPH_OK) return st;
+  sph_status st = sph_build_cells(c);
+  if (st != SPH_OK) return st;
   if ((st = sph_correction(c)) != SPH_OK) return st;
   HIPCHK(c, adjoint_snap_start(c, ws, N), "adjoint snapshot");
   HIPCHK(c, launch_advection(c, ctl->dt_adv, dt, false, nullptr), "advection");
@@ -954,17 +961,67 @@ sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
   c->t += ctl->dt_adv;
   c->moved = true;
   c->B_valid = false;
-  const int n_step = (int)c->n_total;
+  const int n = (int)c->n_total;
   if ((st = sph_buffer_update_ex(c, ctl->dec_by_pid, nullptr, ctl->pid_cap, nullptr)) != SPH_OK)
     return st;
-  // and walk it backwards
-  HIPCHK(c, adjoint_reverse_launch(c, ws, obj, ctl, n_step, lam, grad), "adjoint");
+  HIPCHK(c, adjoint_keep_step(c, ws, N, n), "adjoint snapshot");
+  *n_step = n;
+  return SPH_OK;
+}
+
+sph_status adjoint_reverse(sph_ctx* c, const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
+                           int64_t n_step, double* lam, double* grad, char* ws) {
+  HIPCHK(c, adjoint_reverse_launch(c, ws, obj, ctl, (int)n_step, lam, grad), "adjoint");
   HIPCHK(c, hipMemcpyAsync((char*)c->pinned + 64, c->S.flags, 4, hipMemcpyDeviceToHost, c->stream),
          "flags");
   HIPCHK(c, hipStreamSynchronize(c->stream), "adjoint sync");
   const uint32_t flags = *(uint32_t*)((char*)c->pinned + 64);
   if (flags & kFlagCapacity) return fail(c, SPH_E_ARG, "a particle id is not below pid_cap");
   return check_flags(c, flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_adjoint_forward(sph_ctx* c, const sph_adjoint_ctrl* ctl, void* adj_ws,
+                               size_t adj_bytes, int64_t* n_step) {
+  if (!c) return SPH_E_ARG;
+  if (!n_step) return fail(c, SPH_E_ARG, "null argument");
+  sph_status st = adjoint_check(c, ctl, adj_ws, adj_bytes);
+  if (st != SPH_OK) return st;
+  if (c->next_pid != ctl->next_pid)
+    return fail(c, SPH_E_STATE, "the context is not at the recorded step's start (next_pid)");
+  return adjoint_forward(c, ctl, (char*)adj_ws, n_step);
+}
+
+sph_status sph_adjoint_reverse(sph_ctx* c, const sph_objective_desc* obj,
+                               const sph_adjoint_ctrl* ctl, int64_t n_step, double* lam,
+                               double* grad, void* adj_ws, size_t adj_bytes) {
+  if (!c) return SPH_E_ARG;
+  if (!obj || !lam || !grad) return fail(c, SPH_E_ARG, "null argument");
+  sph_status st = adjoint_check(c, ctl, adj_ws, adj_bytes);
+  if (st != SPH_OK) return st;
+  if (n_step < 0 || n_step > c->cap) return fail(c, SPH_E_ARG, "bad n_step");
+  if (!(obj->slab_width > 0) || !(obj->wall_length > 0))
+    return fail(c, SPH_E_ARG, "slab_width and wall_length must be > 0");
+  return adjoint_reverse(c, obj, ctl, n_step, lam, grad, (char*)adj_ws);
+}
+
+sph_status sph_adjoint_step(sph_ctx* c, const sph_particles* pre, int64_t n_pre,
+                            const sph_objective_desc* obj, const sph_adjoint_ctrl* ctl,
+                            double* lam, double* grad, void* adj_ws, size_t adj_bytes) {
+  if (!c) return SPH_E_ARG;
+  if (!pre || !obj || !ctl || !lam || !grad) return fail(c, SPH_E_ARG, "null argument");
+  sph_status st = adjoint_check(c, ctl, adj_ws, adj_bytes);
+  if (st != SPH_OK) return st;
+  if (!(obj->slab_width > 0) || !(obj->wall_length > 0))
+    return fail(c, SPH_E_ARG, "slab_width and wall_length must be > 0");
+  // replay the step from its start state, then walk it backwards
+  if ((st = sph_set_particles(c, n_pre, ctl->next_pid, pre)) != SPH_OK) return st;
+  int64_t n_step = 0;
+  if ((st = adjoint_forward(c, ctl, (char*)adj_ws, &n_step)) != SPH_OK) return st;
+  return adjoint_reverse(c, obj, ctl, n_step, lam, grad, (char*)adj_ws);
 }
 
 }  // extern "C"

@@ -160,6 +160,7 @@ hipError_t adjoint_snap_start(sph_ctx* c, char* ws, int N);
 hipError_t adjoint_snap_advection(sph_ctx* c, char* ws, int N);
 hipError_t adjoint_snap_pressure(sph_ctx* c, char* ws, int N, int s);
 hipError_t adjoint_snap_density(sph_ctx* c, char* ws, int N, int s);
+hipError_t adjoint_keep_step(sph_ctx* c, char* ws, int N, int n_step);
 hipError_t adjoint_reverse_launch(sph_ctx* c, char* ws, const sph_objective_desc* obj,
                                   const sph_adjoint_ctrl* ctl, int n, double* lam, double* grad);
 

@@ -6,17 +6,18 @@ Forward: ``steps`` advection steps (cell build, correction, step, objective,
 buffer update) with the time steps, buffer decisions and slab membership of
 every step recorded by particle id, and a device checkpoint of the full state
 every ``checkpoint_every`` steps.  Backward: segment by segment in reverse,
-restore the checkpoint, recompute the segment (replaying the record) to get
-each step's start state, then call ``sph_adjoint_step`` for its steps in
-reverse, carrying the state cotangent (by particle id) and accumulating the
-gradient with respect to the control buffer's sine coefficients.
+restore the checkpoint, recompute the segment with ``sph_adjoint_forward``
+(replaying the record, one workspace per step holding its sub-step states),
+then call ``sph_adjoint_reverse`` on the workspaces in reverse, carrying the
+state cotangent (by particle id) and accumulating the gradient with respect
+to the control buffer's sine coefficients.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass
 
-from .sph import (SPH_FP64, make_objective, sph_adjoint_ctrl, sph_adjoint_step,
-                  sph_adjoint_workspace_size)
+from .sph import (SPH_FP64, make_objective, sph_adjoint_ctrl, sph_adjoint_forward,
+                  sph_adjoint_reverse, sph_adjoint_workspace_size)
 
 
 @dataclass
@@ -84,36 +85,30 @@ def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_c
     nbytes = sph_adjoint_workspace_size(sim.ctx, max_nac)
     if nbytes == 0:
         raise RuntimeError("the adjoint needs an FP64 laminar context")
-    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-    ws_ptr = (ws.data_ptr() + 255) & ~255
+    K = checkpoint_every if checkpoint_every > 0 else steps
+    stride = (nbytes + 255) & ~255
+    ws = torch.empty(stride * min(K, steps) + 256, dtype=torch.uint8, device=dev)
+    ws_base = (ws.data_ptr() + 255) & ~255
     g = gJ.detach().to("cpu", torch.float64).numpy()
     wq, wt = float(g[0]) / steps, float(g[1]) / steps
-    K = checkpoint_every if checkpoint_every > 0 else steps
     starts = list(range(0, steps, K))
     t_re = t_adj = 0.0
     for s0 in reversed(starts):
         s1 = min(s0 + K, steps)
         t0 = time.perf_counter()
         sim.restore(ckpts[s0])
-        pres = []
+        ctls, nsteps = {}, {}
         for n in range(s0, s1):
-            pres.append(sim.save())
-            if n < s1 - 1:
-                r = records[n]
-                sim.build_cells()
-                sim.correction()
-                sim.step(r.dt_adv, r.n_ac)
-                sim.buffer_update_ex(forced=r.dec, pid_cap=pid_cap)
+            r = records[n]
+            ctls[n] = sph_adjoint_ctrl(r.step, r.t, r.next_pid, r.dt_adv, r.n_ac, 0,
+                                       r.dec.data_ptr(), r.member.data_ptr(), pid_cap, wq, wt)
+            nsteps[n] = sph_adjoint_forward(sim.ctx, ctls[n], ws_base + (n - s0) * stride, nbytes)
         sim.stream.synchronize()
         t1 = time.perf_counter()
         t_re += t1 - t0
         for n in reversed(range(s0, s1)):
-            r = records[n]
-            pre = pres[n - s0]
-            ctl = sph_adjoint_ctrl(r.step, r.t, r.next_pid, r.dt_adv, r.n_ac, 0,
-                                   r.dec.data_ptr(), r.member.data_ptr(), pid_cap, wq, wt)
-            sph_adjoint_step(sim.ctx, sim.parts_of(pre), pre["n"], desc, ctl, lam.data_ptr(),
-                             grad.data_ptr(), ws_ptr, nbytes)
+            sph_adjoint_reverse(sim.ctx, desc, ctls[n], nsteps[n], lam.data_ptr(),
+                                grad.data_ptr(), ws_base + (n - s0) * stride, nbytes)
         t_adj += time.perf_counter() - t1
     if timings is not None:
         timings["recompute_s"] = t_re

@@ -19,9 +19,9 @@ SPH_OK, SPH_E_ARG, SPH_E_CAPACITY, SPH_E_HIP, SPH_E_NUMERIC, SPH_E_STATE = range
 SPH_FP64, SPH_FP32_MIXED = 0, 1
 SPH_FLUID, SPH_BUFFER, SPH_WALL, SPH_DEAD = 0, 1, 2, 3
 (SPH_K_CELLS, SPH_K_CORRECTION, SPH_K_ADVECTION, SPH_K_PRESSURE, SPH_K_DENSITY,
- SPH_K_BUFFER, SPH_K_REDUCE) = range(7)
+ SPH_K_BUFFER, SPH_K_REDUCE, SPH_K_EVENTS) = range(8)
 KERNEL_NAMES = ["cells", "correction", "advection", "pressure", "density",
-                "buffer", "reduce"]
+                "buffer", "reduce", "events"]
 STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_CAPACITY", 3: "SPH_E_HIP",
           4: "SPH_E_NUMERIC", 5: "SPH_E_STATE"}
 
@@ -137,6 +137,11 @@ EXPORTS = {
     "sph_adjoint_step": (C.c_int, [C.c_void_p, C.POINTER(sph_particles), C.c_int64,
                                    C.POINTER(sph_objective_desc), C.POINTER(sph_adjoint_ctrl),
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "sph_adjoint_forward": (C.c_int, [C.c_void_p, C.POINTER(sph_adjoint_ctrl), C.c_void_p,
+                                      C.c_size_t, C.POINTER(C.c_int64)]),
+    "sph_adjoint_reverse": (C.c_int, [C.c_void_p, C.POINTER(sph_objective_desc),
+                                      C.POINTER(sph_adjoint_ctrl), C.c_int64, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_size_t]),
 }
 
 _lib = None
@@ -294,6 +299,19 @@ def sph_adjoint_step(ctx, pre, n_pre, desc, ctrl, lam_ptr, grad_ptr, ws_ptr, ws_
     _check(ctx, lib().sph_adjoint_step(ctx, C.byref(pre), int(n_pre), C.byref(desc),
                                        C.byref(ctrl), C.c_void_p(lam_ptr), C.c_void_p(grad_ptr),
                                        C.c_void_p(ws_ptr), int(ws_bytes)))
+
+
+def sph_adjoint_forward(ctx, ctrl, ws_ptr, ws_bytes):
+    n = C.c_int64(0)
+    _check(ctx, lib().sph_adjoint_forward(ctx, C.byref(ctrl), C.c_void_p(ws_ptr), int(ws_bytes),
+                                          C.byref(n)))
+    return int(n.value)
+
+
+def sph_adjoint_reverse(ctx, desc, ctrl, n_step, lam_ptr, grad_ptr, ws_ptr, ws_bytes):
+    _check(ctx, lib().sph_adjoint_reverse(ctx, C.byref(desc), C.byref(ctrl), int(n_step),
+                                          C.c_void_p(lam_ptr), C.c_void_p(grad_ptr),
+                                          C.c_void_p(ws_ptr), int(ws_bytes)))
 
 
 def make_objective(d: dict, control_buffer: int) -> sph_objective_desc:
@@ -505,7 +523,7 @@ class Simulation:
         sph_profile_enable(self.ctx, on)
 
     def kernel_stats(self):
-        return {KERNEL_NAMES[k]: sph_profile_read(self.ctx, k) for k in range(7)}
+        return {KERNEL_NAMES[k]: sph_profile_read(self.ctx, k) for k in range(len(KERNEL_NAMES))}
 
     def pair_count(self):
         return sph_pair_count(self.ctx)

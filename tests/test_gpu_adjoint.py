@@ -302,6 +302,81 @@ def test_adjoint_argument_errors(sph, sens):
                          lam.data_ptr(), grad.data_ptr(), wp, nb)
 
 
+def test_forward_reverse_split_equals_the_replaying_step(sph, sens):
+    # sph_adjoint_forward on every step of a segment, then sph_adjoint_reverse
+    # on the kept workspaces, against sph_adjoint_step replaying each step from
+    # its saved start state: the same gradient and state cotangent, bit for bit
+    import torch
+    steps, K = 6, 3
+    c = small_case(steps)
+    sim = sph.Simulation(c, precision=sph.SPH_FP64)
+    pid_cap = int(c.next_pid) + 4096
+    start = sim.save()
+    desc = sph.make_objective(c.objective, BID)
+    _, recs = gpu_rollout(sph, sens, sim, start, desc, pid_cap, steps, None)
+    sim.restore(start)
+    J, out, ckpts = sens.rollout(sim, steps, desc, pid_cap, replay=recs, checkpoint_every=K)
+    gJ = torch.tensor([1.0, 0.5], dtype=torch.float64)
+    g1, lam1 = sens.adjoint(sim, desc, out, ckpts, pid_cap, gJ, steps, K,
+                            return_state_cotangent=True)
+    # the replaying form, step by step from saved start states
+    sim.restore(start)
+    pres = []
+    for r in out:
+        pres.append(sim.save())
+        sim.build_cells()
+        sim.correction()
+        sim.step(r.dt_adv, r.n_ac)
+        sim.buffer_update_ex(forced=r.dec, pid_cap=pid_cap)
+    nb = sph.sph_adjoint_workspace_size(sim.ctx, max(r.n_ac for r in out))
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    wp = (ws.data_ptr() + 255) & ~255
+    lam2 = torch.zeros(8, pid_cap, dtype=torch.float64, device="cuda")
+    g2 = torch.zeros(16, dtype=torch.float64, device="cuda")
+    for n in reversed(range(steps)):
+        r, pre = out[n], pres[n]
+        ctl = sph.sph_adjoint_ctrl(r.step, r.t, r.next_pid, r.dt_adv, r.n_ac, 0, r.dec.data_ptr(),
+                                   r.member.data_ptr(), pid_cap, 1.0 / steps, 0.5 / steps)
+        sph.sph_adjoint_step(sim.ctx, sim.parts_of(pre), pre["n"], desc, ctl, lam2.data_ptr(),
+                             g2.data_ptr(), wp, nb)
+    assert np.abs(g1.cpu().numpy()).max() > 0
+    assert np.array_equal(g1.cpu().numpy(), g2[:16].cpu().numpy())
+    assert torch.equal(lam1, lam2)
+
+
+def test_forward_reverse_argument_errors(sph, sens):
+    import torch
+    c = small_case(4)
+    sim = sph.Simulation(c, precision=sph.SPH_FP64)
+    nb = sph.sph_adjoint_workspace_size(sim.ctx, 4)
+    desc = sph.make_objective(c.objective, BID)
+    pid_cap = int(c.next_pid) + 64
+    dec = torch.zeros(pid_cap, dtype=torch.int32, device="cuda")
+    mem = torch.zeros(pid_cap, dtype=torch.uint8, device="cuda")
+    lam = torch.zeros(8, pid_cap, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(16, dtype=torch.float64, device="cuda")
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    wp = (ws.data_ptr() + 255) & ~255
+    step, t, npid = sim.clock()
+
+    def ctl(next_pid=npid):
+        return sph.sph_adjoint_ctrl(step, t, next_pid, 1e-3, 4, 0, dec.data_ptr(), mem.data_ptr(),
+                                    pid_cap, 1.0, 0.0)
+    with pytest.raises(sph.SphError) as e:   # not the recorded step's start state
+        sph.sph_adjoint_forward(sim.ctx, ctl(next_pid=npid + 1), wp, nb)
+    assert e.value.status == sph.SPH_E_STATE
+    with pytest.raises(sph.SphError) as e:   # workspace too small
+        sph.sph_adjoint_forward(sim.ctx, ctl(), wp, nb - 256)
+    assert e.value.status == sph.SPH_E_ARG
+    n_step = sph.sph_adjoint_forward(sim.ctx, ctl(), wp, nb)
+    assert n_step == c.n
+    with pytest.raises(sph.SphError) as e:   # slot count beyond the capacity
+        sph.sph_adjoint_reverse(sim.ctx, desc, ctl(), 1 << 40, lam.data_ptr(), grad.data_ptr(),
+                                wp, nb)
+    assert e.value.status == sph.SPH_E_ARG
+    sph.sph_adjoint_reverse(sim.ctx, desc, ctl(), n_step, lam.data_ptr(), grad.data_ptr(), wp, nb)
+
+
 def test_adjoint_full_size_against_gpu_finite_differences(sph, sens):
     # the adjoint channel at its full size (20H x H, dp = H/80, ~130k
     # particles), a shortened rollout; two sampled coefficients
