@@ -220,18 +220,14 @@ def roofline(stats):
     dom = max(("pressure", "density", "advection", "correction", "cells"),
               key=lambda k: stats[k].total_ms)
     s = stats[dom]
-    # the event pair around a launch adds the markers' own time: an empty
-    # pair timed in the same run is taken off
-    ev = stats.get("events")
-    marker_ms = ev.total_ms / ev.launches if ev is not None and ev.launches else 0.0
-    raw_ms = s.total_ms / max(1, s.launches)
-    avg_ms = max(raw_ms - marker_ms, 1e-6)
+    # the neighbour passes' events are recorded by their launches at the
+    # kernel's own start and end
+    avg_ms = s.total_ms / max(1, s.launches)
     bytes_per_launch = s.bytes / max(1, s.launches)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dom, dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                      kernel=dom, avg_launch_us=round(avg_ms * 1e3, 3),
-                     event_pair_us=round(raw_ms * 1e3, 3), empty_pair_us=round(marker_ms * 1e3, 3),
                      algorithmic_bytes_per_launch=int(bytes_per_launch),
                      launches=int(s.launches))
 

@@ -154,12 +154,13 @@ typedef struct {
   int64_t step;
 } sph_step_info;
 
-/* Kernel timing (HIP events on the context stream) for profiling.
- * SPH_K_EVENTS times an empty pair of events, recorded once per profiled
- * sph_step: the markers' own share of every other entry's durations. */
+/* Kernel timing for profiling.  The four neighbour passes (correction,
+ * advection, pressure, density: one kernel each) are timed by events that
+ * their launch records at the kernel's own start and end; the other entries
+ * by a pair of events on the context stream around their launches. */
 enum { SPH_K_CELLS = 0, SPH_K_CORRECTION = 1, SPH_K_ADVECTION = 2,
        SPH_K_PRESSURE = 3, SPH_K_DENSITY = 4, SPH_K_BUFFER = 5,
-       SPH_K_REDUCE = 6, SPH_K_EVENTS = 7, SPH_K_COUNT = 8 };
+       SPH_K_REDUCE = 6, SPH_K_COUNT = 7 };
 typedef struct {
   double total_ms;       /* summed kernel durations */
   int64_t launches;

@@ -892,9 +892,9 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr) {
-    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, true><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb, ns));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
   } else {
-    SPHX_TEAM_SWITCH(L, k_correction<T, DIM, TL, false><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a, nb, ns));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, false>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && c->use_nbr) c->nbr_valid = true;
@@ -939,9 +939,9 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
-    SPHX_TEAM_SWITCH(L, k_advection<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_advection<T, DIM, 1, TL>, nblk(n * TL), (int)n, pc, C, a));
   } else {
-    SPHX_TEAM_SWITCH(L, k_advection<T, DIM, 0, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_advection<T, DIM, 0, TL>, nblk(n * TL), (int)n, pc, C, a));
   }
   return hipGetLastError();
 }
@@ -988,10 +988,10 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   switch (c->P.obc_mode) {
-    case 1: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
-    case 2: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 2, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
-    case 3: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 3, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
-    default: SPHX_TEAM_SWITCH(L, k_pressure<T, DIM, 4, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a)); break;
+    case 1: SPHX_TEAM_SWITCH(L, launch_pass(c, &k_pressure<T, DIM, 1, TL>, nblk(n * TL), (int)n, pc, C, a)); break;
+    case 2: SPHX_TEAM_SWITCH(L, launch_pass(c, &k_pressure<T, DIM, 2, TL>, nblk(n * TL), (int)n, pc, C, a)); break;
+    case 3: SPHX_TEAM_SWITCH(L, launch_pass(c, &k_pressure<T, DIM, 3, TL>, nblk(n * TL), (int)n, pc, C, a)); break;
+    default: SPHX_TEAM_SWITCH(L, launch_pass(c, &k_pressure<T, DIM, 4, TL>, nblk(n * TL), (int)n, pc, C, a)); break;
   }
   if (!rates_only)
     for (int k = 0; k < 3; ++k) {
@@ -1027,9 +1027,9 @@ hipError_t density_impl(sph_ctx* c, double dt, bool last, bool rates_only,
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
-    SPHX_TEAM_SWITCH(L, k_density<T, DIM, 1, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_density<T, DIM, 1, TL>, nblk(n * TL), (int)n, pc, C, a));
   } else {
-    SPHX_TEAM_SWITCH(L, k_density<T, DIM, 0, TL><<<nblk(n * TL), 256, 0, c->stream>>>((int)n, pc, C, a));
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_density<T, DIM, 0, TL>, nblk(n * TL), (int)n, pc, C, a));
   }
   if (!rates_only && !last) {
     F.p.flip();

@@ -286,19 +286,39 @@ double kernel_bytes_per_particle(const sph_ctx* c, int kernel) {
   }
 }
 
+// The neighbour passes launch one kernel each: their events are recorded by
+// that launch itself, at the kernel's start and end (launch_pass), so the
+// duration holds no marker overhead.  Other sections are bracketed by a
+// pair of events on the stream.
 void prof_begin(sph_ctx* c, int kernel, double bytes, double particles) {
   g_prof_kernel = -1;
+  c->prof.ext_a = c->prof.ext_b = nullptr;
   if (!c->prof.on) return;
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return;
-  if (hipEventRecord(a, c->stream) != hipSuccess) return;
+  const bool ext = kernel == SPH_K_CORRECTION || kernel == SPH_K_ADVECTION ||
+                   kernel == SPH_K_PRESSURE || kernel == SPH_K_DENSITY;
+  if (ext) {
+    c->prof.ext_a = a;
+    c->prof.ext_b = b;
+  } else if (hipEventRecord(a, c->stream) != hipSuccess) {
+    return;
+  }
   c->prof.pending.push_back({kernel, a, b, bytes, particles});
   g_prof_kernel = kernel;
 }
 
 void prof_end(sph_ctx* c) {
   if (!c->prof.on || g_prof_kernel < 0 || c->prof.pending.empty()) return;
-  (void)hipEventRecord(c->prof.pending.back().b, c->stream);
+  const Profile::Rec& r = c->prof.pending.back();
+  if (c->prof.ext_a) {   // the section launched nothing: an empty interval
+    (void)hipEventRecord(r.a, c->stream);
+    (void)hipEventRecord(r.b, c->stream);
+  } else if (!(r.kernel == SPH_K_CORRECTION || r.kernel == SPH_K_ADVECTION ||
+               r.kernel == SPH_K_PRESSURE || r.kernel == SPH_K_DENSITY)) {
+    (void)hipEventRecord(r.b, c->stream);
+  }
+  c->prof.ext_a = c->prof.ext_b = nullptr;
   g_prof_kernel = -1;
 }
 
@@ -707,10 +727,6 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
   if (!c->cells_valid || c->moved || !c->B_valid)
     return fail(c, SPH_E_STATE, "sph_step needs sph_build_cells and sph_correction first");
   if (ctrl && ctrl->dt_adv > 0 && ctrl->n_ac < 1) return fail(c, SPH_E_ARG, "ctrl->n_ac must be >= 1");
-  if (c->prof.on) {   // the event markers' own time, to be taken off the kernels'
-    prof_begin(c, SPH_K_EVENTS, 0.0, 0.0);
-    prof_end(c);
-  }
   double v2max, nutmax;
   hipError_t e;
   if (c->red_valid) {

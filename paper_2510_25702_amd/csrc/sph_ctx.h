@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <string>
 #include <vector>
@@ -79,6 +80,7 @@ struct Profile {
   long long launches[SPH_K_COUNT] = {0};
   double bytes[SPH_K_COUNT] = {0};
   double particles[SPH_K_COUNT] = {0};
+  hipEvent_t ext_a = nullptr, ext_b = nullptr;   // for the next launch_pass to record
 };
 
 }  // namespace sphx

@@ -28,6 +28,16 @@ struct PairCtx {
   const uint32_t* stale;  // non-zero: the list no longer covers the positions
 };
 
+// Launch of a neighbour pass (256-thread workgroups on the context stream);
+// under profiling the launch records the section's events itself.
+template <typename... KArgs, typename... Args>
+inline void launch_pass(sph_ctx* c, void (*k)(KArgs...), int64_t grid, Args... args) {
+  hipEvent_t a = c->prof.ext_a, b = c->prof.ext_b;
+  c->prof.ext_a = c->prof.ext_b = nullptr;
+  if (a) hipExtLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c->stream, a, b, 0, args...);
+  else hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c->stream, args...);
+}
+
 // Sum over the L lanes of a team (butterfly: the same order in every run).
 template <int L, typename T>
 __device__ __forceinline__ T team_sum(T v) {

@@ -19,9 +19,9 @@ SPH_OK, SPH_E_ARG, SPH_E_CAPACITY, SPH_E_HIP, SPH_E_NUMERIC, SPH_E_STATE = range
 SPH_FP64, SPH_FP32_MIXED = 0, 1
 SPH_FLUID, SPH_BUFFER, SPH_WALL, SPH_DEAD = 0, 1, 2, 3
 (SPH_K_CELLS, SPH_K_CORRECTION, SPH_K_ADVECTION, SPH_K_PRESSURE, SPH_K_DENSITY,
- SPH_K_BUFFER, SPH_K_REDUCE, SPH_K_EVENTS) = range(8)
+ SPH_K_BUFFER, SPH_K_REDUCE) = range(7)
 KERNEL_NAMES = ["cells", "correction", "advection", "pressure", "density",
-                "buffer", "reduce", "events"]
+                "buffer", "reduce"]
 STATUS = {0: "SPH_OK", 1: "SPH_E_ARG", 2: "SPH_E_CAPACITY", 3: "SPH_E_HIP",
           4: "SPH_E_NUMERIC", 5: "SPH_E_STATE"}
 
