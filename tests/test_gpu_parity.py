@@ -495,6 +495,46 @@ def test_advance_equals_the_separate_calls(sph, ora, name):
         assert events > 0
 
 
+@pytest.mark.parametrize("name", ["uchannel", "jet_full"])
+@pytest.mark.parametrize("pname,prec,tol", [("fp64", 0, 1e-10), ("fp32", 1, 2e-5)])
+def test_full_size_advance_matches_oracle(sph, ora, name, pname, prec, tol):
+    # the benchmark's sizes and its launch path: one sph_advance (prelaunched
+    # build and correction of the updated state, one read-back) against the
+    # oracle's step and buffer update, compared by particle id.  The GPU's
+    # adaptive time step must match the oracle's; the oracle then takes the
+    # GPU's step so that the states compare like for like.
+    c = cases.make_uchannel() if name == "uchannel" else cases.make_jet()
+    c = relabelled(ora, cases.perturbed_state(c, seed=13))
+    g = gpu_sim(sph, c, prec)
+    info, cnt = g.advance()
+    Iad = ora.OracleSim(c, threads=16).step()
+    assert Iad.n_ac == info.n_ac
+    assert abs(Iad.dt_adv - info.dt_adv) <= (1e-14 if prec == 0 else 1e-6) * Iad.dt_adv
+    ref = ora.OracleSim(c, threads=16)
+    ref.step(info.dt_adv, info.n_ac)
+    co = ref.buffer_update()
+    so, sg = ref.snapshot(), g.state()
+    alive_o = (so["tag"] & 3) != 3
+    gi = pid_index(sg["pid"])
+    po = so["pid"][alive_o]
+    common = np.array([p for p in po if int(p) in gi])
+    if prec == 0:
+        # FP64: the same decisions, particle for particle
+        assert len(common) == len(po) == len(sg["pid"])
+        assert list(cnt.n_inject) == list(co.n_inject) and list(cnt.n_delete) == list(co.n_delete)
+    else:
+        assert len(common) >= len(po) - 8
+    oi = {int(p): i for i, p in enumerate(so["pid"])}
+    io = np.array([oi[int(p)] for p in common])
+    ig = np.array([gi[int(p)] for p in common])
+    vmax = np.abs(so["v"]).max()
+    ev = np.abs(sg["v"][ig] - so["v"][io]).max() / vmax
+    ex = np.abs(sg["x"][ig] - so["x"][io]).max() / c.params["dp"]
+    er = np.abs(sg["rho"][ig] - so["rho"][io]).max()
+    print(f"{name} {pname}: n_ac {info.n_ac}, v {ev:.2e}, x {ex:.2e}, rho {er:.2e}", flush=True)
+    assert ev < tol and ex < tol and er < tol
+
+
 def test_advance_capacity_error_matches_the_update(sph):
     # the prelaunched build turns into no-ops when the injection fails: the
     # state after the error equals that of a plain update that failed
