@@ -843,10 +843,14 @@ inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
 // the load latency at small sizes, one lane per particle once the chip is
 // full.  The correction's stencil scan walks ~3x the candidates of the list
 // passes and takes twice the lanes (two at most sizes: 160 against 242 us at
-// 640k particles, 590 against 731 us at 2.56M).
+// 640k particles, 590 against 731 us at 2.56M).  In 3D (3.75M particles) the
+// passes take 2 lanes (pressure 2.7 against 3.3 ms with one) and the
+// correction 4 (6.9 against 7.6 ms with two).
 inline int team_lanes(const sph_ctx* c) {
   if (c->team_override > 0) return c->team_override;
   const int64_t n = c->n_total;
+  if (c->P.dim == 3)   // ~170 list entries per particle: more lanes at every size
+    return n <= 1000000 ? 4 : 2;
   if (n <= 100000) return 4;
   if (n <= 450000) return 2;
   return 1;
@@ -855,6 +859,7 @@ inline int team_lanes(const sph_ctx* c) {
 inline int corr_lanes(const sph_ctx* c, int64_t n) {
   if (c->corr_override > 0) return c->corr_override;
   if (c->team_override > 0) return c->team_override;
+  if (c->P.dim == 3) return n <= 100000 ? 8 : 4;   // ~1000 stencil candidates
   if (n <= 100000) return 8;
   if (n <= 260000) return 4;
   return 2;
