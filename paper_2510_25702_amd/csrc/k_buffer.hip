@@ -3,14 +3,17 @@
 // cell-linked-list box, widened by one cell for the drift since the cell
 // build) are examined, one wavefront per cell:
 //   K12 decide: every decision from one snapshot, FP64 predicates without
-//       contraction; injections are appended to a short list (integer atomic
-//       on a counter, order fixed afterwards by sorting);
+//       contraction (a decision reads only its own particle, so its tag
+//       change -- relabel, revert, dead for a deletion, which the next cell
+//       build drops: the counting sort is the compaction -- is applied at
+//       once); injections are appended to a short list (integer atomic on a
+//       counter, order fixed afterwards by sorting);
 //   K13 inject (one workgroup): bitonic sort of the list by (buffer id,
 //       parent id) in LDS, capacity check, append the new fluid particles at
 //       the end of the arrays, recycle the parents by -L_b n_b (Eq.
 //       (eq-pos-new-added)) with the buffer's boundary values;
-//   K14 apply: relabel / revert tags, tag deleted particles dead (the next
-//       cell build drops them: the counting sort is the compaction).
+//   undo: when the injections do not fit, the tag changes are reverted from
+//       the recorded decision codes and the update fails as a whole.
 #include "sph_ctx.h"
 
 namespace sphx {
@@ -90,7 +93,8 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
   return kDecNone;
 }
 
-// K14: apply tag changes (after K13 succeeded).
+// Tag change of a decision, applied by the decide kernels with the decision
+// (undone by undo_one when the injections fail).
 __device__ __forceinline__ void apply_one(const BufArgs& a, int i) {
   const uint32_t d = a.dec[i];
   const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
@@ -366,29 +370,6 @@ hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_
   return hipGetLastError();
 }
 
-// Error flags and the next particle id copied beside the counters
-// (counters[1032], [1033..1034]) so that one read-back returns all three.
-// and the time-step reduction of the updated state (counters[1036..1039]).
-__global__ void k_stage_status(int32_t* counters, const uint32_t* flags, const uint64_t* next_pid,
-                               const double* red) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    counters[1032] = (int32_t)*flags;
-    const uint64_t np = *next_pid;
-    counters[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
-    counters[1034] = (int32_t)(uint32_t)(np >> 32);
-    for (int k = 0; k < 2; ++k) {
-      const uint64_t b = __double_as_longlong(red[k]);
-      counters[1036 + 2 * k] = (int32_t)(uint32_t)(b & 0xFFFFFFFFull);
-      counters[1037 + 2 * k] = (int32_t)(uint32_t)(b >> 32);
-    }
-  }
-}
-
-hipError_t launch_stage_status(sph_ctx* c) {
-  k_stage_status<<<1, 64, 0, c->stream>>>(c->S.counters, c->S.flags, c->S.next_pid, c->S.red);
-  return hipGetLastError();
-}
-
 hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log,
                                 int64_t pid_cap) {
   if (c->n_total == 0) return hipSuccess;
@@ -400,8 +381,8 @@ hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* lo
   return hipGetLastError();
 }
 
-hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots) {
-  (void)all_slots;   // the tag changes were applied by the decide kernels
+// The injections of the decisions (the tag changes were applied with them).
+hipError_t launch_buffer_inject(sph_ctx* c) {
   return c->P.precision == SPH_FP64 ? inject_impl<double>(c) : inject_impl<float>(c);
 }
 

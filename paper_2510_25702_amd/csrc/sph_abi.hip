@@ -363,7 +363,7 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
     if (forced_by_pid) e = launch_buffer_forced(c, forced_by_pid, log_by_pid, pid_cap);
     else e = launch_buffer_decide(c, false, nullptr, log_by_pid, pid_cap);
   }
-  if (e == hipSuccess) e = launch_buffer_apply(c, forced_by_pid != nullptr);
+  if (e == hipSuccess) e = launch_buffer_inject(c);
   prof_end(c);
   if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
   char* hb = (char*)c->pinned;

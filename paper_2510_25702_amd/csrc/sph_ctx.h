@@ -147,8 +147,7 @@ hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out);
 hipError_t launch_buffer_decide(sph_ctx* c, bool dry, uint32_t* dec_out, uint32_t* log = nullptr,
                                 int64_t pid_cap = 0);
 hipError_t launch_buffer_forced(sph_ctx* c, const uint32_t* forced, uint32_t* log, int64_t pid_cap);
-hipError_t launch_buffer_apply(sph_ctx* c, bool all_slots = false);
-hipError_t launch_stage_status(sph_ctx* c);
+hipError_t launch_buffer_inject(sph_ctx* c);
 hipError_t launch_buffer_undo(sph_ctx* c, bool all_slots);
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs);
