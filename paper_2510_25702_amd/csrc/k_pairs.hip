@@ -1075,7 +1075,7 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
   const int64_t n_max = after_update ? std::min<int64_t>(c->cap, n + kMaxInject) : n;
   const int nb = nblk(n_max);
   if (after_update) {
-    k_reduce_post<T><<<std::min(nb, 64), 256, 0, c->stream>>>(
+    k_reduce_post<T><<<std::min(nb, 1024), 256, 0, c->stream>>>(
         (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
         tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
         c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate);

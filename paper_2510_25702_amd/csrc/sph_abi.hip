@@ -254,7 +254,6 @@ void resolve_events(sph_ctx* c) {
   c->prof.pending.swap(keep);
 }
 
-int g_prof_kernel = -1;
 
 }  // namespace
 
@@ -291,7 +290,7 @@ double kernel_bytes_per_particle(const sph_ctx* c, int kernel) {
 // duration holds no marker overhead.  Other sections are bracketed by a
 // pair of events on the stream.
 void prof_begin(sph_ctx* c, int kernel, double bytes, double particles) {
-  g_prof_kernel = -1;
+  c->prof.open = -1;
   c->prof.ext_a = c->prof.ext_b = nullptr;
   if (!c->prof.on) return;
   hipEvent_t a = take_event(c), b = take_event(c);
@@ -305,11 +304,11 @@ void prof_begin(sph_ctx* c, int kernel, double bytes, double particles) {
     return;
   }
   c->prof.pending.push_back({kernel, a, b, bytes, particles});
-  g_prof_kernel = kernel;
+  c->prof.open = kernel;
 }
 
 void prof_end(sph_ctx* c) {
-  if (!c->prof.on || g_prof_kernel < 0 || c->prof.pending.empty()) return;
+  if (!c->prof.on || c->prof.open < 0 || c->prof.pending.empty()) return;
   const Profile::Rec& r = c->prof.pending.back();
   if (c->prof.ext_a) {   // the section launched nothing: an empty interval
     (void)hipEventRecord(r.a, c->stream);
@@ -319,7 +318,7 @@ void prof_end(sph_ctx* c) {
     (void)hipEventRecord(r.b, c->stream);
   }
   c->prof.ext_a = c->prof.ext_b = nullptr;
-  g_prof_kernel = -1;
+  c->prof.open = -1;
 }
 
 }  // namespace sphx

@@ -81,6 +81,7 @@ struct Profile {
   double bytes[SPH_K_COUNT] = {0};
   double particles[SPH_K_COUNT] = {0};
   hipEvent_t ext_a = nullptr, ext_b = nullptr;   // for the next launch_pass to record
+  int open = -1;                                   // section being timed (-1: none)
 };
 
 }  // namespace sphx
