@@ -199,6 +199,27 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
   }
 }
 
+#ifndef SPHX_PIN_RECORDS
+#define SPHX_PIN_RECORDS 1
+#endif
+// Every vector of a batch's records is needed by then: left alone, the
+// compiler sinks the parts a candidate's distance test does not read into
+// the test's branch, where they cost a second memory round trip.  An empty
+// asm statement that takes each register keeps all the loads in front of the
+// tests (it emits no instruction).  Measured with FP32 records in 2D:
+// pressure -4 to -6 % from 160k to 2.56M particles.  In 3D and with FP64
+// records the registers it holds cost more than the round trip (3D
+// continuity +24 % on the mixer, the FP64 U-channel step +4 %): left out.
+template <typename T, int DIM, int U, int NR>
+__device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
+  if (!SPHX_PIN_RECORDS || DIM == 3 || sizeof(T) != 4) return;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int w = 0; w < NR; ++w)
+      asm volatile("" : "+v"(q[u][w].a), "+v"(q[u][w].b), "+v"(q[u][w].c), "+v"(q[u][w].d));
+}
+
 // for_neighbors over j-side records: the NR record vectors of every
 // candidate of a batch are loaded together (the first holds its position),
 // then the candidates are tested; fn(j, r, r2, q) with q[0..NR-1] the
@@ -238,6 +259,7 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
 #pragma unroll
         for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
       }
+      pin_records<T, DIM, kUnroll, NR>(q);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         if (kb + u * L >= cnt) break;
@@ -276,6 +298,7 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
 #pragma unroll
           for (int w = 0; w < NR; ++w) q[u][w] = rec[w][js];
         }
+        pin_records<T, DIM, kUnroll, NR>(q);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int j = jb + u * L;
