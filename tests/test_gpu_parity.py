@@ -249,6 +249,53 @@ def test_pair_operators_full_size(sph, ora, name, pname, prec, tol):
     assert max(errs.values()) < tol, errs
 
 
+def far_from_buffers(c, margin):
+    """Mask of the particles at least `margin` outside every buffer box."""
+    ok = np.ones(c.n, bool)
+    for b in c.buffers:
+        R = np.array(b.frame, float).reshape(3, 3)
+        y = (c.x - np.array(b.origin, float)) @ R.T
+        hw = list(b.half_width) + [0.0]
+        inside = (y[:, 0] > -margin) & (y[:, 0] < b.length + b.fringe + margin)
+        for k in range(1, c.params["dim"]):
+            inside &= np.abs(y[:, k]) < hw[k - 1] + margin
+        ok &= ~inside
+    return ok
+
+
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_pair_operators_mixer_full_size_sampled(sph, ora, pname, prec, tol):
+    # the 3D micro-mixer at its full size (3.75M particles), on the GPU in
+    # the benchmark's launch configuration; the oracle evaluates a sample of
+    # 96 particles one neighbourhood at a time: each sampled particle with
+    # everything within 4h + 2 dp of it (its neighbours and theirs, which its
+    # rates and the neighbours' B depend on), away from the buffers so that no
+    # mirror image reaches the sample
+    from scipy.spatial import cKDTree
+    c = relabelled(ora, cases.perturbed_state(cases.make_mixer(), seed=17))
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    rg = g.rates()
+    gi = pid_index(g.state()["pid"])
+    h, dp = c.params["h"], c.params["dp"]
+    rng = np.random.default_rng(5)
+    cand = np.nonzero(((c.tag & 3) == cases.FLUID) & far_from_buffers(c, 10 * h))[0]
+    picks = rng.choice(cand, 96, replace=False)
+    tree = cKDTree(c.x)
+    near = np.unique(np.concatenate(tree.query_ball_point(c.x[picks], 4 * h + 2 * dp)))
+    sub = dataclasses.replace(c, x=c.x[near].copy(), v=c.v[near].copy(), rho=c.rho[near].copy(),
+                              k=c.k[near].copy(), eps=c.eps[near].copy(), tag=c.tag[near].copy(),
+                              pid=c.pid[near].copy(), drho=c.drho[near].copy())
+    ro = ora.OracleSim(sub, threads=8).rates()
+    si = {int(p): i for i, p in enumerate(sub.pid)}
+    io = np.array([si[int(c.pid[p])] for p in picks])
+    ig = np.array([gi[int(c.pid[p])] for p in picks])
+    errs = {f: normwise(rg[f][ig], ro[f][io]) for f in ("ap", "drho", "anu", "B", "p")}
+    assert len(near) < 200000
+    assert max(errs.values()) < tol, errs
+
+
 # --------------------------------------------------------------------------
 # buffer decisions and update: bit-exact by particle id
 # --------------------------------------------------------------------------
