@@ -232,15 +232,9 @@ def roofline(stats):
                      launches=int(s.launches))
 
 
-def adjoint_leg(steps, K, torch):
-    """Inlet-profile sensitivity on the adjoint channel (FP64): the recorded
-    forward rollout, the checkpointed reverse sweep, and a plain forward
-    rollout of the same steps for the cost ratio."""
-    import numpy as np
-    import cases
+def _adjoint_run(case, precision, steps, K, torch):
     from paper_2510_25702_amd import sph, sensitivity as sens
-    case = cases.make_adjoint_channel(steps=steps)
-    sim = sph.Simulation(case, precision=sph.SPH_FP64)
+    sim = sph.Simulation(case, precision=precision)
     start = sim.save()
     desc = sph.make_objective(case.objective, 1)
     pid_cap = sens.default_pid_cap(sim, steps)
@@ -263,18 +257,39 @@ def adjoint_leg(steps, K, torch):
                      steps, K, timings=tim)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
-    g = g.cpu().numpy()
-    J = (J / steps).cpu().numpy()
+    return dict(g=g.cpu().numpy(), J=(J / steps).cpu().numpy(), t_plain=t_plain, t_fwd=t_fwd,
+                t_bwd=t_bwd, tim=tim)
+
+
+def adjoint_leg(steps, K, torch):
+    """Inlet-profile sensitivity on the adjoint channel: FP32-mixed forward
+    with the FP64 reverse sweep (the configured run) -- the recorded forward
+    rollout, the checkpointed reverse sweep, and a plain forward rollout of
+    the same steps for the cost ratio -- and the same with an FP64 forward,
+    whose gradient the FP32-forward one is compared with."""
+    import numpy as np
+    import cases
+    from paper_2510_25702_amd import sph
+    case = cases.make_adjoint_channel(steps=steps)
+    r = _adjoint_run(case, sph.SPH_FP32_MIXED, steps, K, torch)
+    r64 = _adjoint_run(case, sph.SPH_FP64, steps, K, torch)
+    g, g64 = r["g"], r64["g"]
     ms = lambda t: round(1e3 * t / steps, 4)
+    tim = r["tim"]
     return {"workload": "adjoint_channel", "particles_total": int(case.n), "steps": steps,
-            "checkpoint_every": K, "precision": "fp64",
+            "checkpoint_every": K, "precision": "fp32-mixed forward, fp64 reverse",
             "objective": "mean over steps of J_Q (outlet slab mass flux) + J_tau (wall shear)",
-            "J": [float(J[0]), float(J[1])], "grad_norm": float(np.linalg.norm(g)),
-            "forward_ms_per_step": ms(t_plain), "recorded_forward_ms_per_step": ms(t_fwd),
-            "backward_ms_per_step": ms(t_bwd),
+            "J": [float(r["J"][0]), float(r["J"][1])], "grad_norm": float(np.linalg.norm(g)),
+            "grad_rel_diff_vs_fp64_forward": float(np.abs(g - g64).max() / np.abs(g64).max()),
+            "forward_ms_per_step": ms(r["t_plain"]), "recorded_forward_ms_per_step": ms(r["t_fwd"]),
+            "backward_ms_per_step": ms(r["t_bwd"]),
             "adjoint_step_ms": ms(tim["adjoint_s"]), "recompute_ms_per_step": ms(tim["recompute_s"]),
-            "adjoint_step_over_forward": round(tim["adjoint_s"] / t_plain, 3),
-            "backward_over_forward": round(t_bwd / t_plain, 3)}
+            "adjoint_step_over_forward": round(tim["adjoint_s"] / r["t_plain"], 3),
+            "backward_over_forward": round(r["t_bwd"] / r["t_plain"], 3),
+            "fp64": {"forward_ms_per_step": ms(r64["t_plain"]),
+                     "adjoint_step_ms": ms(r64["tim"]["adjoint_s"]),
+                     "adjoint_step_over_forward": round(r64["tim"]["adjoint_s"] / r64["t_plain"], 3),
+                     "backward_over_forward": round(r64["t_bwd"] / r64["t_plain"], 3)}}
 
 
 TRAFFIC_SOURCES = ("k_pairs.hip", "sph_pairs.h", "sph_device.h", "sph_ctx.h")

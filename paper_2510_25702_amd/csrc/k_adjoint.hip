@@ -348,16 +348,21 @@ __global__ void k_fill_u8(int64_t n, uint8_t* p) {
 // ---------------------------------------------------------------------------
 // Snapshots: up to 8 FP64 arrays copied in one launch.
 // ---------------------------------------------------------------------------
+// Snapshot copies into FP64; a source in the pair precision of an
+// FP32-mixed forward (f32 set) is widened on the way.
 struct CopyList {
-  const double* src[10];
+  const void* src[10];
   double* dst[10];
+  int f32[10];
   int k;
 };
 
 __global__ __launch_bounds__(256) void k_copy(int n, CopyList c) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int q = 0; q < c.k; ++q) c.dst[q][i] = c.src[q][i];
+  for (int q = 0; q < c.k; ++q)
+    c.dst[q][i] = c.f32[q] ? (double)static_cast<const float*>(c.src[q])[i]
+                           : static_cast<const double*>(c.src[q])[i];
 }
 
 __global__ void k_copy_u32(int n, const uint32_t* s, uint32_t* d) {
@@ -1305,12 +1310,22 @@ int adj_team(const sph_ctx* c) {
   return 1;
 }
 
-void snap_copy(sph_ctx* c, int n, std::initializer_list<std::pair<const void*, double*>> lst) {
+// One snapshot entry: a source array, its FP64 destination, and whether the
+// source is in the pair precision (float in an FP32-mixed context).
+struct Snap {
+  const void* src;
+  double* dst;
+  bool pair;
+};
+
+void snap_copy(sph_ctx* c, int n, std::initializer_list<Snap> lst) {
   CopyList cl;
   cl.k = 0;
-  for (auto& pr : lst) {
-    cl.src[cl.k] = (const double*)pr.first;
-    cl.dst[cl.k] = pr.second;
+  const bool f32 = c->P.precision != SPH_FP64;
+  for (const Snap& e : lst) {
+    cl.src[cl.k] = e.src;
+    cl.dst[cl.k] = e.dst;
+    cl.f32[cl.k] = e.pair && f32 ? 1 : 0;
     ++cl.k;
   }
   k_copy<<<nblk_a(n), 256, 0, c->stream>>>(n, cl);
@@ -1419,7 +1434,7 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
 }  // namespace
 
 size_t adjoint_ws_bytes(const sph_ctx* c, int max_nac) {
-  if (c->P.precision != SPH_FP64 || c->P.turbulence || max_nac < 1) return 0;
+  if (c->P.turbulence || max_nac < 1) return 0;
   return adj_layout(c, max_nac).total;
 }
 
@@ -1481,11 +1496,12 @@ hipError_t adjoint_snap_start(sph_ctx* c, char* ws, int N) {
   double* XR = (double*)(ws + L.XR);
   double* V = (double*)(ws + L.V);
   Fields& F = c->F;
-  snap_copy(c, n, {{F.x[0].live(), X}, {F.x[1].live(), X + cap}, {F.x[2].live(), X + 2 * cap},
-                   {F.xr[0].live(), XR}, {F.xr[1].live(), XR + cap}, {F.xr[2].live(), XR + 2 * cap},
-                   {F.v[0].live(), V}, {F.v[1].live(), V + cap}, {F.v[2].live(), V + 2 * cap},
-                   {F.rho.live(), (double*)(ws + L.rho0)}});
-  snap_copy(c, n, {{F.vol.live(), (double*)(ws + L.vol0)}});
+  snap_copy(c, n, {{F.x[0].live(), X, false}, {F.x[1].live(), X + cap, false},
+                   {F.x[2].live(), X + 2 * cap, false}, {F.xr[0].live(), XR, true},
+                   {F.xr[1].live(), XR + cap, true}, {F.xr[2].live(), XR + 2 * cap, true},
+                   {F.v[0].live(), V, true}, {F.v[1].live(), V + cap, true},
+                   {F.v[2].live(), V + 2 * cap, true}, {F.rho.live(), (double*)(ws + L.rho0), false}});
+  snap_copy(c, n, {{F.vol.live(), (double*)(ws + L.vol0), true}});
   k_copy_u32<<<nblk_a(n), 256, 0, c->stream>>>(n, F.tag.live(), (uint32_t*)(ws + L.tag));
   return hipGetLastError();
 }
@@ -1494,8 +1510,9 @@ hipError_t adjoint_snap_advection(sph_ctx* c, char* ws, int N) {
   AdjLayout L = adj_layout(c, N);
   const int n = (int)c->n_total;
   Fields& F = c->F;
-  snap_copy(c, n, {{F.rho.live(), (double*)(ws + L.RH)}, {F.p.live(), (double*)(ws + L.P)},
-                   {F.vol.live(), (double*)(ws + L.VOL)}});
+  snap_copy(c, n, {{F.rho.live(), (double*)(ws + L.RH), false},
+                   {F.p.live(), (double*)(ws + L.P), true},
+                   {F.vol.live(), (double*)(ws + L.VOL), true}});
   return hipGetLastError();
 }
 
@@ -1508,9 +1525,11 @@ hipError_t adjoint_snap_pressure(sph_ctx* c, char* ws, int N, int s) {
   double* XR = (double*)(ws + L.XR) + o;
   double* V = (double*)(ws + L.V) + o;
   Fields& F = c->F;
-  snap_copy(c, n, {{F.x[0].live(), X}, {F.x[1].live(), X + cap}, {F.x[2].live(), X + 2 * cap},
-                   {F.xr[0].live(), XR}, {F.xr[1].live(), XR + cap}, {F.xr[2].live(), XR + 2 * cap},
-                   {F.v[0].live(), V}, {F.v[1].live(), V + cap}, {F.v[2].live(), V + 2 * cap}});
+  snap_copy(c, n, {{F.x[0].live(), X, false}, {F.x[1].live(), X + cap, false},
+                   {F.x[2].live(), X + 2 * cap, false}, {F.xr[0].live(), XR, true},
+                   {F.xr[1].live(), XR + cap, true}, {F.xr[2].live(), XR + 2 * cap, true},
+                   {F.v[0].live(), V, true}, {F.v[1].live(), V + cap, true},
+                   {F.v[2].live(), V + 2 * cap, true}});
   return hipGetLastError();
 }
 
@@ -1522,11 +1541,11 @@ hipError_t adjoint_snap_density(sph_ctx* c, char* ws, int N, int s) {
   double* DD = (double*)(ws + L.DD) + (int64_t)s * cap;
   double* RH = (double*)(ws + L.RH) + (int64_t)(s + 1) * cap;
   if (s < N - 1)
-    snap_copy(c, n, {{F.drho.live(), DD}, {F.rho.live(), RH},
-                     {F.p.live(), (double*)(ws + L.P) + (int64_t)(s + 1) * cap},
-                     {F.vol.live(), (double*)(ws + L.VOL) + (int64_t)(s + 1) * cap}});
+    snap_copy(c, n, {{F.drho.live(), DD, true}, {F.rho.live(), RH, false},
+                     {F.p.live(), (double*)(ws + L.P) + (int64_t)(s + 1) * cap, true},
+                     {F.vol.live(), (double*)(ws + L.VOL) + (int64_t)(s + 1) * cap, true}});
   else
-    snap_copy(c, n, {{F.drho.live(), DD}, {F.rho.live(), RH}});
+    snap_copy(c, n, {{F.drho.live(), DD, true}, {F.rho.live(), RH, false}});
   return hipGetLastError();
 }
 
@@ -1555,9 +1574,13 @@ hipError_t adjoint_keep_step(sph_ctx* c, char* ws, int N, int n_step) {
     if (list) e = hipMemcpyAsync(ws + L.stale, c->S.stale, 8, hipMemcpyDeviceToDevice, st);
     else e = hipMemsetAsync(ws + L.stale, 0xFF, 8, st);
   }
-  for (int k = 0; k < 6 && e == hipSuccess; ++k)
-    e = hipMemcpyAsync(ws + L.B + (size_t)k * cap * 8, c->F.B[k], (size_t)n_step * 8,
-                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && n_step > 0) {
+    double* B = (double*)(ws + L.B);
+    snap_copy(c, n_step, {{c->F.B[0], B, true}, {c->F.B[1], B + cap, true},
+                          {c->F.B[2], B + 2 * cap, true}, {c->F.B[3], B + 3 * cap, true},
+                          {c->F.B[4], B + 4 * cap, true}, {c->F.B[5], B + 5 * cap, true}});
+    e = hipGetLastError();
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.dec, c->S.dec, (size_t)n_step * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess)

@@ -939,8 +939,7 @@ namespace {
 sph_status adjoint_check(sph_ctx* c, const sph_adjoint_ctrl* ctl, const void* adj_ws,
                          size_t adj_bytes) {
   if (!ctl) return fail(c, SPH_E_ARG, "null argument");
-  if (c->P.precision != SPH_FP64 || c->P.turbulence)
-    return fail(c, SPH_E_ARG, "the adjoint needs an FP64 laminar context");
+  if (c->P.turbulence) return fail(c, SPH_E_ARG, "the adjoint needs a laminar context");
   if (ctl->n_ac < 1 || !(ctl->dt_adv > 0)) return fail(c, SPH_E_ARG, "bad dt_adv / n_ac");
   if (!ctl->dec_by_pid || ctl->pid_cap < (int64_t)ctl->next_pid)
     return fail(c, SPH_E_ARG, "dec_by_pid with pid_cap >= next_pid is required");

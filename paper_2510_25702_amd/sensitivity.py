@@ -16,7 +16,7 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-from .sph import (SPH_FP64, make_objective, sph_adjoint_ctrl, sph_adjoint_forward,
+from .sph import (make_objective, sph_adjoint_ctrl, sph_adjoint_forward,
                   sph_adjoint_reverse, sph_adjoint_workspace_size)
 
 
@@ -84,7 +84,7 @@ def adjoint(sim, desc, records, ckpts, pid_cap, gJ, steps, checkpoint_every, n_c
     max_nac = max(r.n_ac for r in records)
     nbytes = sph_adjoint_workspace_size(sim.ctx, max_nac)
     if nbytes == 0:
-        raise RuntimeError("the adjoint needs an FP64 laminar context")
+        raise RuntimeError("the adjoint needs a laminar context")
     K = checkpoint_every if checkpoint_every > 0 else steps
     stride = (nbytes + 255) & ~255
     ws = torch.empty(stride * min(K, steps) + 256, dtype=torch.uint8, device=dev)
@@ -124,7 +124,7 @@ class InletSensitivity:
     apply(coef, sim, objective_dict, buffer_id, steps, checkpoint_every)
     runs the forward rollout from the simulation's current state with the
     control buffer's coefficients set to `coef` and returns the step-averaged
-    [J_Q, J_tau]; backward runs the adjoint.  The simulation must be an FP64
+    [J_Q, J_tau]; backward runs the adjoint.  The simulation must be a
     laminar context; it is left at the end of the rollout after forward and
     at an earlier state after backward.
     """
@@ -136,8 +136,8 @@ class InletSensitivity:
         class _F(torch.autograd.Function):
             @staticmethod
             def forward(ctx, coef, sim, objective, buffer_id, steps, checkpoint_every=10):
-                if sim.precision != SPH_FP64:
-                    raise RuntimeError("the adjoint needs an FP64 context")
+                if sim.turbulence:
+                    raise RuntimeError("the adjoint needs a laminar context")
                 sim.set_profile_coef(buffer_id, coef.detach().cpu().numpy())
                 desc = make_objective(objective, buffer_id)
                 pid_cap = default_pid_cap(sim, steps)

@@ -383,6 +383,7 @@ class Simulation:
         self.bufs = list(case.buffers if buffers is None else buffers)
         self.capacity = case.capacity() if capacity is None else int(capacity)
         self.precision = precision
+        self.turbulence = bool(self.pdict.get("turbulence", 0))
         self.P = make_params(self.pdict, precision, self.capacity)
         self.B = make_buffers(self.bufs)
         self.nbuf = len(self.bufs)
