@@ -308,7 +308,10 @@ sph_status sph_profile_read(sph_ctx* ctx, int32_t kernel, sph_kernel_stats* out)
 sph_status sph_pair_count(sph_ctx* ctx, int64_t* pairs);
 
 /* ---------------------------------------------------------------------
- * Inlet-profile sensitivity (laminar, FP64 contexts).
+ * Inlet-profile sensitivity (laminar contexts).  The forward replays run in
+ * the context's precision; their sub-step states are kept in FP64 and the
+ * reverse sweep is FP64 (with an FP32-mixed context: the FP64 scheme's
+ * gradient at the FP32 trajectory).
  *
  * Objectives at the state after sph_step (before the buffer update):
  *   J_Q   = sum over real i with 0 <= n.(x_i - o) < w of m (v_i . n) / w,
@@ -359,9 +362,10 @@ typedef struct {
   double w_flux, w_shear;  /* dL/dJ_Q and dL/dJ_tau of this step's objectives */
 } sph_adjoint_ctrl;
 
-/* Device workspace of sph_adjoint_step for steps of up to max_nac acoustic
- * sub-steps; 0 when the context cannot run the adjoint (FP32-mixed or
- * turbulent). */
+/* Device workspace of sph_adjoint_step (or of one step of
+ * sph_adjoint_forward / sph_adjoint_reverse) for steps of up to max_nac
+ * acoustic sub-steps; 0 when the context cannot run the adjoint
+ * (turbulent). */
 size_t sph_adjoint_workspace_size(const sph_ctx* ctx, int32_t max_nac);
 
 /* Discrete adjoint of one advection step followed by its buffer update
