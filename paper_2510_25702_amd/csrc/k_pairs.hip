@@ -136,6 +136,10 @@ __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts
     nb.stale[0] = 0;
     nb.stale[1] = 0;
   }
+  constexpr int KS = BUILD ? list_stage<DIM, L>() : 0;
+  __shared__ uint32_t stage[KS > 0 ? (256 / L) * KS : 1];
+  nb.kstage = KS;
+  nb.stage = KS > 0 ? stage + (threadIdx.x / L) * KS : nullptr;
   const int m = correction_body<T, DIM, L, BUILD>(g / L, g % L, n, pc, C, a, nb);
   count_pairs(pc.pairs, m);
 }
@@ -894,6 +898,8 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
   nb.stale = c->S.stale;
   const double rl = c->P.cell_size * (1.0 + 2e-6);
   nb.rl2 = (T)(rl * rl);
+  nb.stage = nullptr;
+  nb.kstage = 0;
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr) {
