@@ -9,7 +9,8 @@
 //       once); injections are appended to a short list (integer atomic on a
 //       counter, order fixed afterwards by sorting);
 //   K13 inject (one workgroup): bitonic sort of the list by (buffer id,
-//       parent id) in LDS, capacity check, append the new fluid particles at
+//       parent id), in the registers of one wavefront for up to 64 entries
+//       and in LDS beyond, capacity check, append the new fluid particles at
 //       the end of the arrays, recycle the parents by -L_b n_b (Eq.
 //       (eq-pos-new-added)) with the buffer's boundary values;
 //   undo: when the injections do not fit, the tag changes are reverted from
@@ -95,8 +96,7 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
 
 // Tag change of a decision, applied by the decide kernels with the decision
 // (undone by undo_one when the injections fail).
-__device__ __forceinline__ void apply_one(const BufArgs& a, int i) {
-  const uint32_t d = a.dec[i];
+__device__ __forceinline__ void apply_one(const BufArgs& a, int i, uint32_t d) {
   const uint32_t act = d & 0xFFu, id = (d >> 8) & 0xFFu, id2 = (d >> 16) & 0xFFu;
   if (act == kDecRelabel) a.tag[i] = kBuffer | (id << 8);
   else if (act == kDecRevert) a.tag[i] = kFluid;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kWave) void k_buffer_decide(BufArgs a) {
     }
     if (a.log && a.pid[i] < a.pid_cap) a.log[a.pid[i]] = d;
     record(a, i, d);
-    apply_one(a, i);   // a decision reads only its own particle's tag
+    apply_one(a, i, d);   // a decision reads only its own particle's tag
   }
 }
 
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_buffer_forced(BufArgs a) {
   if (!is_real(a.tag[i])) d = kDecNone;
   if (a.log && p < a.pid_cap) a.log[p] = d;
   record(a, i, d);
-  apply_one(a, i);
+  apply_one(a, i, d);
 }
 
 // The decide kernels apply the tag changes at once; when the injection
@@ -205,30 +205,123 @@ struct InjArgs {
 };
 
 constexpr int kInjThreads = 1024;
+static_assert(kInjThreads <= kMaxInject, "the first keys are loaded one per thread");
 
-// K13: one workgroup.
+// Child r of the update (rank r in the sorted list) of parent i: an exact
+// copy of i appended at slot n + r with particle id base_pid + r; the parent
+// is then recycled by -L_b n_b with the buffer's boundary values.  One
+// thread per child, so each parent's fields are read once.
+template <typename T>
+__device__ __forceinline__ void inject_one(const InjArgs<T>& a, const BufDev& b, int r, int i,
+                                           uint64_t base_pid) {
+  const int64_t c = a.n + r;
+  double x[3];
+  T v[3];
+  for (int k = 0; k < 3; ++k) {
+    x[k] = a.x[k][i];
+    v[k] = a.v[k][i];
+  }
+  const double rho = a.rho[i];
+  const T drho = a.drho[i];
+  const uint32_t pid = a.pid[i];
+  T kt = T(0), et = T(0), nt = T(0);
+  if (a.turb) {
+    kt = a.k[i];
+    et = a.eps[i];
+    nt = a.nut[i];
+  }
+  for (int k = 0; k < 3; ++k) {
+    a.x[k][c] = x[k];
+    a.v[k][c] = v[k];
+  }
+  a.rho[c] = rho;
+  a.drho[c] = drho;
+  if (a.turb) {
+    a.k[c] = kt;
+    a.eps[c] = et;
+    a.nut[c] = nt;
+  }
+  a.tag[c] = kFluid;
+  a.pid[c] = (uint32_t)(base_pid + (uint64_t)r);
+  double xn[3];
+  for (int k = 0; k < 3; ++k) {
+    const double tt = __dmul_rn(b.length, b.frame[k]);
+    xn[k] = __dsub_rn(x[k], tt);
+    a.x[k][i] = xn[k];
+  }
+  if (b.vel_mode == kVelPrescribed) {
+    double y[3];
+    to_local(b, xn[0], xn[1], xn[2], y);
+    const double u = profile_speed(a.dim, b, y, a.seed, pid, a.step, a.t);
+    for (int k = 0; k < 3; ++k) a.v[k][i] = (T)(u * b.frame[k]);
+  }
+  if (b.p_mode == kPPrescribed)
+    a.rho[i] = rho_of_p(a.rho0, a.c0, __dmul_rn(b.p_ob, buffer_ramp(b, a.t)));
+  if (a.turb && b.turb_mode == kTurbFreestream) {
+    a.k[i] = (T)b.k_bc;
+    a.eps[i] = (T)b.eps_bc;
+    a.nut[i] = (T)(a.Cmu * b.k_bc * b.k_bc / b.eps_bc);
+  }
+}
+
+// K13: one workgroup.  The count, the first keys, the next particle id and
+// the buffer index table are loaded together; up to one wavefront of
+// injections (the usual case) is sorted in registers by that wavefront,
+// more in LDS by the whole workgroup.  The sorted order is kept in inj_idx:
+// child r of this update is the copy of slot inj_idx[r].
 template <typename T>
 __global__ __launch_bounds__(kInjThreads) void k_buffer_inject(InjArgs<T> a) {
   __shared__ uint64_t skey[kMaxInject];
   __shared__ int32_t sidx[kMaxInject];
+  __shared__ int32_t sbidx[256];
+  const int t = threadIdx.x;
   const int m = a.counters[1024];
+  const uint64_t base_pid = *a.next_pid;
+  const uint64_t key0 = a.inj_key[t];
+  const int32_t idx0 = a.inj_idx[t];
+  if (t < 256) sbidx[t] = a.bidx[t];
   if (m > kMaxInject || a.n + m > a.cap) {
-    if (threadIdx.x == 0) {
-      atomicOr(a.flags, kFlagCapacity | (m > kMaxInject ? kFlagInjectOverflow : 0u));
-    }
+    if (t == 0) atomicOr(a.flags, kFlagCapacity | (m > kMaxInject ? kFlagInjectOverflow : 0u));
     return;
   }
   if (m == 0) return;
+  __syncthreads();
+  if (m <= kWave) {
+    if (t >= kWave) return;
+    // bitonic network over the 64 lanes, padded with the largest key
+    uint64_t key = t < m ? key0 : ~0ull;
+    int idx = t < m ? idx0 : -1;
+#pragma unroll
+    for (int kk = 2; kk <= kWave; kk <<= 1) {
+#pragma unroll
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+        const uint64_t ok = __shfl_xor(key, jj, kWave);
+        const int oi = __shfl_xor(idx, jj, kWave);
+        const bool up = (t & kk) == 0, low = (t & jj) == 0;
+        if (low == up ? ok < key : ok > key) {
+          key = ok;
+          idx = oi;
+        }
+      }
+    }
+    if (t < m) {
+      a.inj_idx[t] = idx;
+      inject_one(a, a.bufs[sbidx[(int)(key >> 32)]], t, idx, base_pid);
+    }
+    if (t == 0) *a.next_pid = base_pid + (uint64_t)m;
+    return;
+  }
   int np2 = 1;
   while (np2 < m) np2 <<= 1;
-  for (int r = threadIdx.x; r < np2; r += blockDim.x) {
-    skey[r] = r < m ? a.inj_key[r] : ~0ull;
-    sidx[r] = r < m ? a.inj_idx[r] : -1;
+  for (int r = t; r < np2; r += kInjThreads) {
+    const bool own = r == t;
+    skey[r] = r < m ? (own ? key0 : a.inj_key[r]) : ~0ull;
+    sidx[r] = r < m ? (own ? idx0 : a.inj_idx[r]) : -1;
   }
   __syncthreads();
   for (int kk = 2; kk <= np2; kk <<= 1) {
     for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (int r = threadIdx.x; r < np2; r += blockDim.x) {
+      for (int r = t; r < np2; r += kInjThreads) {
         const int p = r ^ jj;
         if (p > r) {
           const bool up = (r & kk) == 0;
@@ -236,64 +329,21 @@ __global__ __launch_bounds__(kInjThreads) void k_buffer_inject(InjArgs<T> a) {
           if ((kr > kp) == up) {
             skey[r] = kp;
             skey[p] = kr;
-            const int t = sidx[r];
+            const int s = sidx[r];
             sidx[r] = sidx[p];
-            sidx[p] = t;
+            sidx[p] = s;
           }
         }
       }
       __syncthreads();
     }
   }
-  // the sorted order is kept: child r of this update is the copy of slot
-  // inj_idx[r] and has particle id base_pid + r
-  for (int r = threadIdx.x; r < m; r += blockDim.x) a.inj_idx[r] = sidx[r];
-  const uint64_t base_pid = *a.next_pid;
-  // new fluid particles: exact copies of the parents, appended in order
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+  for (int r = t; r < m; r += kInjThreads) {
     const int i = sidx[r];
-    const int64_t c = a.n + r;
-    for (int k = 0; k < 3; ++k) {
-      a.x[k][c] = a.x[k][i];
-      a.v[k][c] = a.v[k][i];
-    }
-    a.rho[c] = a.rho[i];
-    a.drho[c] = a.drho[i];
-    if (a.turb) {
-      a.k[c] = a.k[i];
-      a.eps[c] = a.eps[i];
-      a.nut[c] = a.nut[i];
-    }
-    a.tag[c] = kFluid;
-    a.pid[c] = (uint32_t)(base_pid + (uint64_t)r);
+    a.inj_idx[r] = i;
+    inject_one(a, a.bufs[sbidx[(int)(skey[r] >> 32)]], r, i, base_pid);
   }
-  __syncthreads();
-  // recycle the parents with the buffer's boundary values
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
-    const int i = sidx[r];
-    const int q = a.bidx[(int)(skey[r] >> 32)];
-    const BufDev& b = a.bufs[q];
-    double xn[3];
-    for (int k = 0; k < 3; ++k) {
-      const double tt = __dmul_rn(b.length, b.frame[k]);
-      xn[k] = __dsub_rn(a.x[k][i], tt);
-      a.x[k][i] = xn[k];
-    }
-    if (b.vel_mode == kVelPrescribed) {
-      double y[3];
-      to_local(b, xn[0], xn[1], xn[2], y);
-      const double u = profile_speed(a.dim, b, y, a.seed, a.pid[i], a.step, a.t);
-      for (int k = 0; k < 3; ++k) a.v[k][i] = (T)(u * b.frame[k]);
-    }
-    if (b.p_mode == kPPrescribed)
-      a.rho[i] = rho_of_p(a.rho0, a.c0, __dmul_rn(b.p_ob, buffer_ramp(b, a.t)));
-    if (a.turb && b.turb_mode == kTurbFreestream) {
-      a.k[i] = (T)b.k_bc;
-      a.eps[i] = (T)b.eps_bc;
-      a.nut[i] = (T)(a.Cmu * b.k_bc * b.k_bc / b.eps_bc);
-    }
-  }
-  if (threadIdx.x == 0) *a.next_pid = base_pid + (uint64_t)m;
+  if (t == 0) *a.next_pid = base_pid + (uint64_t)m;
 }
 
 BufArgs make_bufargs(sph_ctx* c, bool dry, uint32_t* dec_out) {

@@ -698,10 +698,11 @@ __global__ __launch_bounds__(256) void k_reduce_part(int n, const int32_t* n_ext
 }
 
 // K11 after a buffer update, in one launch: max |v|^2 and max nu_t of the
-// updated state (non-negative doubles: their bit patterns order like the
-// values, so integer atomic maxima give the exact, order-independent result),
-// the error flags and the next particle id, all staged beside the counters
-// (counters[1032..1039]) for the update's single read-back.
+// updated state, one pair per workgroup (the host takes the maxima of the
+// pairs: exact and order-independent), the error flags and the next
+// particle id, all staged beside the counters (flags and id in
+// counters[1032..1034], the pairs after counters[1039]) for the update's
+// single read-back.  Plain stores: no two workgroups write one word.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* counters,
                                                      const T* v0, const T* v1, const T* v2,
@@ -711,16 +712,19 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
                                                      const uint64_t* next_pid, int n_alive,
                                                      int32_t* __restrict__ ns) {
   __shared__ double sm[2][256 / kWave];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x < kWave) {
     // sizes of the next cell build, for a build launched before the host
     // has read the counts: {n_in, n_out, skip (the injection failed)}
-    const bool cap = (*flags & kFlagCapacity) != 0;
-    const int inj = cap ? 0 : counters[1024];
-    int del = 0;
-    for (int b = 0; b < 256; ++b) del += counters[512 + b];
-    ns[0] = n + inj;
-    ns[1] = n_alive + inj - del;
-    ns[2] = cap ? 1 : 0;
+    long long del = 0;
+    for (int b = threadIdx.x; b < 256; b += kWave) del += counters[512 + b];
+    del = wave_sum_ll(del);
+    if (threadIdx.x == 0) {
+      const bool cap = (*flags & kFlagCapacity) != 0;
+      const int inj = cap ? 0 : counters[1024];
+      ns[0] = n + inj;
+      ns[1] = n_alive + inj - (int)del;
+      ns[2] = cap ? 1 : 0;
+    }
   }
   n = min(n + counters[1024], n_max);
   double a = 0.0, b = 0.0;
@@ -743,11 +747,11 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
       a = fmax(a, sm[0][w]);
       b = fmax(b, sm[1][w]);
     }
-    unsigned long long* m = reinterpret_cast<unsigned long long*>(counters + 1036);
-    atomicMax(m, (unsigned long long)__double_as_longlong(a));
-    atomicMax(m + 1, (unsigned long long)__double_as_longlong(b));
-    atomicOr(reinterpret_cast<unsigned int*>(counters + 1032), *flags);
+    double* part = reinterpret_cast<double*>(counters + 1040) + 2 * blockIdx.x;
+    part[0] = a;
+    part[1] = b;
     if (blockIdx.x == 0) {
+      counters[1032] = (int32_t)*flags;
       const uint64_t np = *next_pid;
       counters[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
       counters[1034] = (int32_t)(uint32_t)(np >> 32);
@@ -1081,7 +1085,8 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
   const int64_t n_max = after_update ? std::min<int64_t>(c->cap, n + kMaxInject) : n;
   const int nb = nblk(n_max);
   if (after_update) {
-    k_reduce_post<T><<<std::min(nb, 1024), 256, 0, c->stream>>>(
+    c->post_blocks = std::min(nb, kPostBlocks);
+    k_reduce_post<T><<<c->post_blocks, 256, 0, c->stream>>>(
         (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
         tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
         c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate);

@@ -209,7 +209,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_cand = L.take(cand.size() * 4);
   pl->off_injk = L.take((size_t)kMaxInject * 8);
   pl->off_inji = L.take((size_t)kMaxInject * 4);
-  pl->off_counters = L.take(1040 * 4);
+  pl->off_counters = L.take(1040 * 4 + (size_t)kPostBlocks * 16);
   pl->off_flags = L.take(4);
   pl->off_stale = L.take(8);
   pl->off_nstate = L.take(16);
@@ -368,7 +368,8 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   char* hb = (char*)c->pinned;
   c->red_valid = false;
   HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
-  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4, hipMemcpyDeviceToHost, c->stream), "counts");
+  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4 + (size_t)c->post_blocks * 16,
+                           hipMemcpyDeviceToHost, c->stream), "counts");
   HIPCHK(c, hipEventRecord(c->rb_event, c->stream), "read-back event");
   const Fields saved = c->F;
   const bool nbr_saved = c->nbr_valid;
@@ -414,8 +415,15 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
                                        : "particle capacity exceeded");
   }
   {
-    uint64_t b0 = (uint64_t)(uint32_t)cnt[1036] | ((uint64_t)(uint32_t)cnt[1037] << 32);
-    uint64_t b1 = (uint64_t)(uint32_t)cnt[1038] | ((uint64_t)(uint32_t)cnt[1039] << 32);
+    // maxima of the per-workgroup pairs (non-negative doubles or +inf: their
+    // bit patterns order like the values)
+    uint64_t b0 = 0, b1 = 0;
+    for (int k = 0; k < c->post_blocks; ++k) {
+      uint64_t u[2];
+      std::memcpy(u, hb + 1040 * 4 + 16 * k, 16);
+      b0 = std::max(b0, u[0]);
+      b1 = std::max(b1, u[1]);
+    }
     std::memcpy(&c->red_v2, &b0, 8);
     std::memcpy(&c->red_nut, &b1, 8);
   }
@@ -603,7 +611,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (e == hipSuccess)
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 8192, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 1040 * 4 + kPostBlocks * 16, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {

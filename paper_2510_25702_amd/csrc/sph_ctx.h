@@ -13,6 +13,10 @@
 
 namespace sphx {
 
+// Most workgroups of the post-update reduction (each leaves its maxima
+// beside the buffer-update counters for the host to combine).
+constexpr int kPostBlocks = 1024;
+
 // Two-slot ("ping-pong") device array: cur() is the live copy.
 template <typename P>
 struct Slot2 {
@@ -60,7 +64,8 @@ struct Scratch {
   int32_t n_cand_cells;
   uint64_t* inj_key;       // [kMaxInject]
   int32_t* inj_idx;        // [kMaxInject]
-  int32_t* counters;       // [4 * 256 + 8] per-buffer counts + misc
+  int32_t* counters;       // [4 * 256 + 16] per-buffer counts + misc, then
+                           // [kPostBlocks][2] doubles: per-block maxima
   uint32_t* flags;         // [1] error flags
   uint32_t* stale;         // [2] neighbour list outgrown (by sub-step parity)
   int32_t* nstate;         // [4] next build's sizes after an update: n_in, n_out, skip
@@ -118,6 +123,7 @@ struct sph_ctx {
   int substep = 0;              // acoustic sub-step being launched
   bool red_valid = false;       // red_v2 / red_nut hold the reduction of the current state
   double red_v2 = 0.0, red_nut = 0.0;
+  int post_blocks = 0;            // workgroups of the last post-update reduction
   hipEvent_t rb_event = nullptr;  // marks the buffer update's read-back copy
   std::string err;
   sphx::Profile prof;
