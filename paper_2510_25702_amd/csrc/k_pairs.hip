@@ -177,20 +177,21 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
                                               const Consts<T>& C, const AdvArgs<T>& a) {
   if (i >= n) return 0;
   int m_pairs = 0;
+  // the tag, the position and the head of the list load together
   const uint32_t ti = pc.tag[i];
+  const auto h = list_head<T, L>(pc, i, lane);
+  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   if (!is_real(ti)) {
     if (!a.rates_only && lane == 0) {
       for (int k = 0; k < 3; ++k) a.anu[k][i] = T(0);
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
       if (TURB) { a.ko[i] = T(0); a.epso[i] = T(0); a.nuto[i] = T(0); }
-      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
       const T Iw[6] = {T(1), T(0), T(0), T(1), T(0), T(1)};
-      write_prec<T, DIM>(a.prec, i, xw, T(0), -(T)C.Vw, Iw);
+      write_prec<T, DIM>(a.prec, i, xi, T(0), -(T)C.Vw, Iw);
     }
     return m_pairs;
   }
-  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
   const double rho_i = a.rho[i];
   const T nut_i = TURB ? a.nut[i] : T(0);
@@ -199,15 +200,20 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   T G[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T Bi[6];
   T ki = T(0), ei = T(0), Dk_i = T(0), De_i = T(0), dfk = T(0), dfe = T(0);
+  // B (the pressure record of the update; and the velocity gradient's
+  // correction with the turbulence model), the continuity rate and the
+  // buffer index after the sum: in flight during the walk
+  if (TURB || !a.rates_only) load_B<T, DIM>(a.B, i, Bi);
   if (TURB) {
-    load_B<T, DIM>(a.B, i, Bi);
     ki = a.k[i];
     ei = a.eps[i];
     Dk_i = (T)C.nu_l + nut_i / (T)C.sigma_k;
     De_i = (T)C.nu_l + nut_i / (T)C.sigma_eps;
   }
+  const T drho_i = a.rates_only ? T(0) : a.drho[i];
+  const int qb = (TURB && tag_kind(ti) == kBuffer) ? a.bidx[tag_bid(ti)] : -1;
   constexpr int NR = (DIM == 3 && TURB) ? 3 : 2;
-  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec,
+  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
     const T rr = sqrt(r2);
@@ -302,12 +308,9 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     } else {
       k_new = fmax(kd + a.dt_adv * dk, C.k_floor);
       e_new = fmax(ed + a.dt_adv * de, C.eps_floor);
-      if (tag_kind(ti) == kBuffer) {
-        const int q = a.bidx[tag_bid(ti)];
-        if (q >= 0 && a.bufs[q].turb_mode == kTurbFreestream) {
-          k_new = a.bufs[q].k_bc;
-          e_new = a.bufs[q].eps_bc;
-        }
+      if (qb >= 0 && a.bufs[qb].turb_mode == kTurbFreestream) {
+        k_new = a.bufs[qb].k_bc;
+        e_new = a.bufs[qb].eps_bc;
       }
       nut_new = C.Cmu * k_new * k_new / e_new;
     }
@@ -324,15 +327,13 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     a.nuto[i] = (T)nut_new;
   }
   // first half density update of the first acoustic sub-step
-  const double rho_h = rho_i + a.half_dt * (double)a.drho[i];
+  const double rho_h = rho_i + a.half_dt * (double)drho_i;
   a.rho[i] = rho_h;
   const T p_h = (T)eos(rho_h, k_new, C.rho0, C.c0, TURB);
   const T v_h = (T)(C.mass / rho_h);
   a.p_out[i] = p_h;
   a.vol_out[i] = v_h;
-  T Bw[6];
-  load_B<T, DIM>(a.B, i, Bw);
-  write_prec<T, DIM>(a.prec, i, xi, p_h, v_h, Bw);
+  write_prec<T, DIM>(a.prec, i, xi, p_h, v_h, Bi);
   return m_pairs;
 }
 
@@ -380,26 +381,44 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
                                              const Consts<T>& C, const PressArgs<T>& a) {
   if (i >= n) return 0;
   int m_pairs = 0;
+  // the particle's own operands and the head of its list load with its tag
+  // (every slot below n holds valid data): none of them waits for the test
   const uint32_t ti = pc.tag[i];
-  if (!is_real(ti)) {
-    if (!a.rates_only && lane == 0) {
-      for (int k = 0; k < 3; ++k) {
-        a.xo[k][i] = a.x[k][i];
-        a.xro[k][i] = pc.xr[k][i];
-      }
-      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
-      const T vw[3] = {T(0), T(0), T(0)};
-      write_drec<T, DIM>(a.drec, i, xw, vw, T(0), -pc.vol[i]);
-    }
-    return m_pairs;
-  }
-  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+  const auto h = list_head<T, L>(pc, i, lane);
+  const T xr_i[3] = {pc.xr[0][i], pc.xr[1][i], pc.xr[2][i]};
+  const T xi[3] = {xr_i[0], xr_i[1], DIM == 3 ? xr_i[2] : T(0)};
   const T pi = a.p[i];
   T Bi[6];
   if (MODE >= 2) load_B<T, DIM>(a.B, i, Bi);
+  const T vol_i = pc.vol[i];
+  const double xd[3] = {a.x[0][i], a.x[1][i], a.x[2][i]};
+  if (!is_real(ti)) {
+    if (!a.rates_only && lane == 0) {
+      for (int k = 0; k < 3; ++k) {
+        a.xo[k][i] = xd[k];
+        a.xro[k][i] = xr_i[k];
+      }
+      const T vw[3] = {T(0), T(0), T(0)};
+      write_drec<T, DIM>(a.drec, i, xi, vw, T(0), -vol_i);
+    }
+    return m_pairs;
+  }
+  // operands of the update after the sum: in flight during the walk
+  const double rho_i = a.rho[i];
+  const int qb = tag_kind(ti) == kBuffer ? a.bidx[tag_bid(ti)] : -1;
+  T v_i[3] = {T(0), T(0), T(0)}, anu_i[3] = {T(0), T(0), T(0)}, xrb_i[3] = {T(0), T(0), T(0)};
+  int c_i = 0;
+  if (!a.rates_only) {
+    for (int k = 0; k < DIM; ++k) {
+      v_i[k] = a.v[k][i];
+      anu_i[k] = a.anu[k][i];
+      if (a.xrb[0]) xrb_i[k] = a.xrb[k][i];
+    }
+    c_i = pc.cell[i];
+  }
   T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
   constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);
-  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec,
+  for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
     const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
@@ -450,11 +469,9 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
     s[k] = team_sum<L>(s[k]);
   }
   if (lane != 0) return m_pairs;
-  int q = -1;
-  if (tag_kind(ti) == kBuffer) q = a.bidx[tag_bid(ti)];
-  if (q >= 0 && a.bufs[q].p_mode != kPNone) {
-    const T pob = a.bufs[q].p_mode == kPPrescribed
-                      ? (T)(a.bufs[q].p_ob * buffer_ramp(a.bufs[q], a.t)) : pi;
+  if (qb >= 0 && a.bufs[qb].p_mode != kPNone) {
+    const T pob = a.bufs[qb].p_mode == kPPrescribed
+                      ? (T)(a.bufs[qb].p_ob * buffer_ramp(a.bufs[qb], a.t)) : pi;
     T cc[3];
     if (MODE == 4) symv<T, DIM>(Bi, s, cc);
     else { cc[0] = s[0]; cc[1] = s[1]; cc[2] = s[2]; }
@@ -462,25 +479,24 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
     acc[1] -= T(2) * pob * cc[1];
     acc[2] -= T(2) * pob * cc[2];
   }
-  const double inv_rho = 1.0 / a.rho[i];
+  const double inv_rho = 1.0 / rho_i;
   const double ap[3] = {-(double)acc[0] * inv_rho, -(double)acc[1] * inv_rho,
                         -(double)acc[2] * inv_rho};
   if (a.rates_only) {
     for (int k = 0; k < 3; ++k) a.o_ap[(int64_t)k * a.n_out + i] = ap[k];
     return m_pairs;
   }
-  const double xd[3] = {a.x[0][i], a.x[1][i], a.x[2][i]};
   double vn[3];
   for (int k = 0; k < 3; ++k)
-    vn[k] = (k < DIM) ? (double)a.v[k][i] + a.dt * (ap[k] + (double)a.anu[k][i] + C.g[k]) : 0.0;
-  if (q >= 0 && a.bufs[q].vel_mode == kVelPrescribed) {
-    const BufDev& b = a.bufs[q];
+    vn[k] = (k < DIM) ? (double)v_i[k] + a.dt * (ap[k] + (double)anu_i[k] + C.g[k]) : 0.0;
+  if (qb >= 0 && a.bufs[qb].vel_mode == kVelPrescribed) {
+    const BufDev& b = a.bufs[qb];
     double y[3];
     to_local(b, xd[0], xd[1], xd[2], y);
     const double u = profile_speed(DIM, b, y, C.seed, a.pid[i], a.step, a.t);
     for (int k = 0; k < DIM; ++k) vn[k] = u * b.frame[k];
   }
-  const int c = pc.cell[i];
+  const int c = c_i;
   const int cc3[3] = {c % pc.nx, (c / pc.nx) % pc.ny, c / (pc.nx * pc.ny)};
   bool bad = false;
   T xnew[3], vnew[3] = {T(0), T(0), T(0)};
@@ -494,7 +510,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       const double rel = xn - (C.grid.lo[k] + (double)cc3[k] * C.grid.cs);
       if (!(rel >= -C.skin && rel <= C.grid.cs + C.skin)) bad = true;
       if (a.xrb[0]) {
-        const double dd = rel - (double)a.xrb[k][i];
+        const double dd = rel - (double)xrb_i[k];
         d2 += dd * dd;
       }
       a.xro[k][i] = (T)rel;
@@ -502,11 +518,11 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       vnew[k] = vt;
     } else {
       a.xo[k][i] = xd[k];
-      a.xro[k][i] = pc.xr[k][i];
-      xnew[k] = pc.xr[k][i];
+      a.xro[k][i] = xr_i[k];
+      xnew[k] = xr_i[k];
     }
   }
-  write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, pc.vol[i]);
+  write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, vol_i);
   if (a.xrb[0] && !(d2 <= C.skin * C.skin)) atomicOr(a.stale_w, 1u);
   if (bad) atomicOr(a.flags, kFlagSkin);
   return m_pairs;
@@ -553,14 +569,22 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
   const int i = g / L, lane = g % L;
   long long cnt = 0;
   if (i < n) {
+    // the tag, the position and the head of the list load together
     const uint32_t ti = pc.tag[i];
+    const auto h = list_head<T, L>(pc, i, lane);
+    const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
     if (is_real(ti)) {
-      const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
       const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
       const T pi = a.p[i];
+      // operands of the update after the sum: in flight during the walk
+      const double rho_i = a.rho[i];
+      const bool next = !a.rates_only && !a.last;
+      T Bw[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      if (next) load_B<T, DIM>(a.B, i, Bw);
+      const double k_i = (TURB && next) ? (double)a.k[i] : 0.0;
       T sum = T(0);
       int m = 0;
-      for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec,
+      for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec, h,
                                       [&](int j, const T r[3], T r2, const V4<T>* q) {
         const T rr = sqrt(r2);
         const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
@@ -586,7 +610,6 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       cnt = m;
       sum = team_sum<L>(sum);
       if (lane == 0) {
-        const double rho_i = a.rho[i];
         const double drho = 2.0 * rho_i * (double)sum;
         if (a.rates_only) {
           a.o_drho[i] = drho;
@@ -595,12 +618,10 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
           double rho_n = rho_i + a.half_dt * drho;
           if (!a.last) {
             rho_n = rho_n + a.half_dt * drho;
-            const T p_n = (T)eos(rho_n, TURB ? (double)a.k[i] : 0.0, C.rho0, C.c0, TURB);
+            const T p_n = (T)eos(rho_n, k_i, C.rho0, C.c0, TURB);
             const T v_n = (T)(C.mass / rho_n);
             a.p_out[i] = p_n;
             a.vol_out[i] = v_n;
-            T Bw[6];
-            load_B<T, DIM>(a.B, i, Bw);
             write_prec<T, DIM>(a.prec, i, xi, p_n, v_n, Bw);
           }
           a.rho[i] = rho_n;
@@ -609,9 +630,8 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
     } else if (!a.rates_only && !a.last && lane == 0) {
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
-      const T xw[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
       const T Iw[6] = {T(1), T(0), T(0), T(1), T(0), T(1)};
-      write_prec<T, DIM>(a.prec, i, xw, T(0), -(T)C.Vw, Iw);
+      write_prec<T, DIM>(a.prec, i, xi, T(0), -(T)C.Vw, Iw);
     }
   }
   count_pairs(pc.pairs, cnt);
@@ -699,10 +719,12 @@ __global__ __launch_bounds__(256) void k_reduce_part(int n, const int32_t* n_ext
 
 // K11 after a buffer update, in one launch: max |v|^2 and max nu_t of the
 // updated state, one pair per workgroup (the host takes the maxima of the
-// pairs: exact and order-independent), the error flags and the next
-// particle id, all staged beside the counters (flags and id in
-// counters[1032..1034], the pairs after counters[1039]) for the update's
-// single read-back.  Plain stores: no two workgroups write one word.
+// pairs: exact and order-independent), the per-buffer counts, the error
+// flags and the next particle id, all written straight into the pinned host
+// buffer `rb` (its device address) in the counters' layout -- counts in
+// [0, 1032), flags and id in [1032, 1035), the pairs after word 1040 -- so
+// that the update needs no copy.  Plain stores: no two workgroups write one
+// word.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* counters,
                                                      const T* v0, const T* v1, const T* v2,
@@ -710,8 +732,11 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
                                                      const uint32_t* tag, int turb,
                                                      const uint32_t* flags,
                                                      const uint64_t* next_pid, int n_alive,
-                                                     int32_t* __restrict__ ns) {
+                                                     int32_t* __restrict__ ns,
+                                                     int32_t* __restrict__ rb) {
   __shared__ double sm[2][256 / kWave];
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < 1032; k += blockDim.x) rb[k] = counters[k];
   if (blockIdx.x == 0 && threadIdx.x < kWave) {
     // sizes of the next cell build, for a build launched before the host
     // has read the counts: {n_in, n_out, skip (the injection failed)}
@@ -747,14 +772,14 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
       a = fmax(a, sm[0][w]);
       b = fmax(b, sm[1][w]);
     }
-    double* part = reinterpret_cast<double*>(counters + 1040) + 2 * blockIdx.x;
+    double* part = reinterpret_cast<double*>(rb + 1040) + 2 * blockIdx.x;
     part[0] = a;
     part[1] = b;
     if (blockIdx.x == 0) {
-      counters[1032] = (int32_t)*flags;
+      rb[1032] = (int32_t)*flags;
       const uint64_t np = *next_pid;
-      counters[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
-      counters[1034] = (int32_t)(uint32_t)(np >> 32);
+      rb[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
+      rb[1034] = (int32_t)(uint32_t)(np >> 32);
     }
   }
 }
@@ -1089,7 +1114,7 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
     k_reduce_post<T><<<c->post_blocks, 256, 0, c->stream>>>(
         (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
         tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
-        c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate);
+        c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate, c->pinned_dev);
     return hipGetLastError();
   }
   k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, after_update ? c->S.counters + 1024 : nullptr,

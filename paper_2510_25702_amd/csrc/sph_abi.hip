@@ -209,7 +209,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_cand = L.take(cand.size() * 4);
   pl->off_injk = L.take((size_t)kMaxInject * 8);
   pl->off_inji = L.take((size_t)kMaxInject * 4);
-  pl->off_counters = L.take(1040 * 4 + (size_t)kPostBlocks * 16);
+  pl->off_counters = L.take(1040 * 4);
   pl->off_flags = L.take(4);
   pl->off_stale = L.take(8);
   pl->off_nstate = L.take(16);
@@ -367,9 +367,9 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   if (e != hipSuccess) return hip_fail(c, e, "buffer_update");
   char* hb = (char*)c->pinned;
   c->red_valid = false;
+  // the reduction writes the counts, flags, next id and maxima into the
+  // pinned buffer itself: the event after it is the read-back
   HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
-  HIPCHK(c, hipMemcpyAsync(hb, c->S.counters, 1040 * 4 + (size_t)c->post_blocks * 16,
-                           hipMemcpyDeviceToHost, c->stream), "counts");
   HIPCHK(c, hipEventRecord(c->rb_event, c->stream), "read-back event");
   const Fields saved = c->F;
   const bool nbr_saved = c->nbr_valid;
@@ -612,6 +612,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 1040 * 4 + kPostBlocks * 16, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {

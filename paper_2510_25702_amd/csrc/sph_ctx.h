@@ -13,8 +13,8 @@
 
 namespace sphx {
 
-// Most workgroups of the post-update reduction (each leaves its maxima
-// beside the buffer-update counters for the host to combine).
+// Most workgroups of the post-update reduction (each leaves its maxima in
+// the pinned read-back buffer for the host to combine).
 constexpr int kPostBlocks = 1024;
 
 // Two-slot ("ping-pong") device array: cur() is the live copy.
@@ -64,8 +64,7 @@ struct Scratch {
   int32_t n_cand_cells;
   uint64_t* inj_key;       // [kMaxInject]
   int32_t* inj_idx;        // [kMaxInject]
-  int32_t* counters;       // [4 * 256 + 16] per-buffer counts + misc, then
-                           // [kPostBlocks][2] doubles: per-block maxima
+  int32_t* counters;       // [4 * 256 + 16] per-buffer counts + misc
   uint32_t* flags;         // [1] error flags
   uint32_t* stale;         // [2] neighbour list outgrown (by sub-step parity)
   int32_t* nstate;         // [4] next build's sizes after an update: n_in, n_out, skip
@@ -116,6 +115,7 @@ struct sph_ctx {
   bool need_pv0 = false;
   int pv_half = 0;
   uint32_t* pinned = nullptr;   // host staging (pinned)
+  int32_t* pinned_dev = nullptr;  // its device address (the post-update reduction writes there)
   int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
   int corr_override = 0;        // lanes per particle of the correction pass (0: auto)
   bool use_nbr = true;          // neighbour passes read the per-step list

@@ -25,6 +25,7 @@ struct PairCtx {
   const uint32_t* nbr;  // per-step neighbour list (NULL: scan the cell stencil)
   const int32_t* ncnt;
   int64_t nstride;
+  int nk;               // rows of the list (every one allocated)
   const uint32_t* stale;  // non-zero: the list no longer covers the positions
 };
 
@@ -238,26 +239,66 @@ constexpr int rec_unroll() {
   return L >= 4 ? SPHX_REC_UNROLL_WIDE : SPHX_REC_UNROLL_NARROW;
 }
 
+// The start of a particle's walk of its list: the count, the stale word and
+// the first batch of entries, loaded before the particle's tag is tested so
+// that none of them waits for it.  Every one of the list's rows is
+// allocated, so the first batch needs no count (entries past it are read
+// and never used).
+template <int U>
+struct ListHead {
+  int cnt;
+  bool stale;
+  uint32_t e[U];
+};
+
+template <typename T, int L>
+__device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>& pc, int i,
+                                                               int lane) {
+  constexpr int U = rec_unroll<L>();
+  ListHead<U> h;
+  h.cnt = 0;
+  h.stale = true;
+#pragma unroll
+  for (int u = 0; u < U; ++u) h.e[u] = 0u;
+  if (pc.nbr) {
+    h.cnt = pc.ncnt[i];
+    h.stale = pc.stale && *pc.stale;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = lane + u * L;
+      h.e[u] = pc.nbr[(int64_t)(k < pc.nk ? k : pc.nk - 1) * pc.nstride + i];
+    }
+  }
+  return h;
+}
+
+// The list walk proper: each batch's records are gathered while the next
+// batch's entries load; a slot past the count gathers particle i's own
+// records (in bounds, never used).
 template <typename T, int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
                                                   const T xi[3], const V4<T>* const* rec,
+                                                  const ListHead<rec_unroll<L>()>& h,
                                                   Fn&& fn) {
   constexpr int kUnroll = rec_unroll<L>();
-  if (pc.nbr && !(pc.stale && *pc.stale)) {
-    const int cnt = pc.ncnt[i];
-    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
-      uint32_t e[kUnroll];
+  if (pc.nbr && !h.stale) {
+    const int cnt = h.cnt;
+    uint32_t e[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int k = kb + u * L;
-        e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
-      }
+    for (int u = 0; u < kUnroll; ++u) e[u] = h.e[u];
+    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
       V4<T> q[kUnroll][NR];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int j = (int)(e[u] & kNbrIdxMask);
+        const int j = kb + u * L < cnt ? (int)(e[u] & kNbrIdxMask) : i;
 #pragma unroll
         for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
+      }
+      uint32_t en[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = kb + (kUnroll + u) * L;
+        en[u] = k < cnt ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
       }
       pin_records<T, DIM, kUnroll, NR>(q);
 #pragma unroll
@@ -274,6 +315,8 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
                               : r[0] * r[0] + r[1] * r[1];
         if (r2 < pc.rc2) fn(j, r, r2, q[u]);
       }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) e[u] = en[u];
     }
     return;
   }
@@ -587,6 +630,7 @@ inline PairCtx<T> make_pc(const sph_ctx* c, const sphx::Slot2<void>* xr, int xsl
   pc.nbr = list ? c->F.nbr : nullptr;
   pc.ncnt = list ? c->F.ncnt : nullptr;
   pc.nstride = c->cap;
+  pc.nk = c->F.nbr_k;
   pc.stale = nullptr;
   return pc;
 }
