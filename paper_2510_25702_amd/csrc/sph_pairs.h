@@ -530,17 +530,15 @@ __device__ __forceinline__ double eos(double rho, double k, double rho0, double 
 template <int DIM>
 __device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
   constexpr double theta = 0.25;
-  double inv[6], det, tr, d;
+  // every branch leaves its values in registers and B is written once (an
+  // early return with its own stores made the compiler keep B in scratch)
+  double inv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double det, tr, d;
   if (DIM == 2) {
     tr = A[0] + A[3];
     det = A[0] * A[3] - A[1] * A[1];
     d = tr > 0.0 ? det / ((0.5 * tr) * (0.5 * tr)) : 0.0;
-    if (!(tr > 0.0) || !(d > 0.0)) {
-      B[0] = 1.0; B[1] = 0.0; B[3] = 1.0; B[2] = B[4] = B[5] = 0.0;
-      return;
-    }
     inv[0] = A[3] / det; inv[1] = -A[1] / det; inv[3] = A[0] / det;
-    inv[2] = inv[4] = inv[5] = 0.0;
   } else {
     const double c00 = A[3] * A[5] - A[4] * A[4];
     const double c01 = A[4] * A[2] - A[1] * A[5];
@@ -549,10 +547,6 @@ __device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
     tr = A[0] + A[3] + A[5];
     const double t3 = tr / 3.0;
     d = tr > 0.0 ? det / (t3 * t3 * t3) : 0.0;
-    if (!(tr > 0.0) || !(d > 0.0)) {
-      B[0] = 1.0; B[1] = 0.0; B[2] = 0.0; B[3] = 1.0; B[4] = 0.0; B[5] = 1.0;
-      return;
-    }
     inv[0] = c00 / det;
     inv[1] = c01 / det;
     inv[2] = c02 / det;
@@ -560,9 +554,12 @@ __device__ __forceinline__ void invert_sym(const double A[6], double B[6]) {
     inv[4] = (A[2] * A[1] - A[0] * A[4]) / det;
     inv[5] = (A[0] * A[3] - A[1] * A[1]) / det;
   }
+  // guard: no positive trace or determinant -> B = I
+  const bool ok = tr > 0.0 && d > 0.0;
   const double w = d >= theta ? 1.0 : (d / theta) * (d / theta);
   const double id[6] = {1.0, 0.0, 0.0, 1.0, 0.0, DIM == 3 ? 1.0 : 0.0};
-  for (int k = 0; k < 6; ++k) B[k] = w * inv[k] + (1.0 - w) * id[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) B[k] = ok ? w * inv[k] + (1.0 - w) * id[k] : id[k];
 }
 
 
