@@ -611,9 +611,15 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (e == hipSuccess)
     e = hipMemsetAsync(S.pairs, 0, sizeof(long long) * kPairShards * kPairShardStride, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.next_pid, 0, 8, st);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 1040 * 4 + kPostBlocks * 16, hipHostMallocDefault);
+  // coherent host memory: the post-update reduction writes its read-back
+  // here from the device, and the host reads it after the event
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->pinned, 1040 * 4 + kPostBlocks * 16, hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
+  // a system-scope release when recorded: the device's writes to host
+  // memory are visible once the event has completed
+  if (e == hipSuccess)
+    e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming | hipEventReleaseToSystem);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     if (c->pinned) (void)hipHostFree(c->pinned);

@@ -582,6 +582,30 @@ def test_full_size_advance_matches_oracle(sph, ora, name, pname, prec, tol):
     assert ev < tol and ex < tol and er < tol
 
 
+@pytest.mark.parametrize("pname,prec", [("fp64", 0), ("fp32", 1)])
+def test_time_step_speed_is_the_state_speed(sph, ora, pname, prec):
+    # every step's time step comes from the maximum speed over the real
+    # particles of the state that the previous step's buffer update left,
+    # taken on the device and read back with that update's counts: step
+    # after step it must be the maximum of that state as read here (the
+    # turbulent jet's speeds change from step to step, so a value of an
+    # earlier update would not match)
+    c = relabelled(ora, cases.make_jet())
+    g = gpu_sim(sph, c, prec)
+    g.advance()
+    seen = set()
+    for s in range(10):
+        st = g.state()
+        real = (st["tag"] & 3) <= 1
+        v = st["v"][real]
+        v2 = ((v[:, 0] * v[:, 0] + v[:, 1] * v[:, 1]) + v[:, 2] * v[:, 2]).max()
+        info, _ = g.advance()
+        print(f"{pname} step {s}: vmax {info.vmax:.17g} state {np.sqrt(v2):.17g}", flush=True)
+        assert abs(info.vmax - np.sqrt(v2)) <= 1e-14 * np.sqrt(v2), s
+        seen.add(info.vmax)
+    assert len(seen) > 5
+
+
 def test_advance_capacity_error_matches_the_update(sph):
     # the prelaunched build turns into no-ops when the injection fails: the
     # state after the error equals that of a plain update that failed
