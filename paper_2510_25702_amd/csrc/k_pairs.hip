@@ -200,18 +200,25 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   T G[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T Bi[6];
   T ki = T(0), ei = T(0), Dk_i = T(0), De_i = T(0), dfk = T(0), dfe = T(0);
-  // B (the pressure record of the update; and the velocity gradient's
-  // correction with the turbulence model), the continuity rate and the
-  // buffer index after the sum: in flight during the walk
-  if (TURB || !a.rates_only) load_B<T, DIM>(a.B, i, Bi);
   if (TURB) {
+    load_B<T, DIM>(a.B, i, Bi);   // the velocity gradient's correction
     ki = a.k[i];
     ei = a.eps[i];
     Dk_i = (T)C.nu_l + nut_i / (T)C.sigma_k;
     De_i = (T)C.nu_l + nut_i / (T)C.sigma_eps;
   }
-  const T drho_i = a.rates_only ? T(0) : a.drho[i];
-  const int qb = (TURB && tag_kind(ti) == kBuffer) ? a.bidx[tag_bid(ti)] : -1;
+  // B for the pressure record (laminar), the continuity rate and the buffer
+  // index, needed after the sum: issued before the walk by wide teams,
+  // after the sum by narrow ones
+  T drho_i = T(0);
+  int qb = -1;
+  auto load_update = [&]() {
+    if (!TURB && !a.rates_only) load_B<T, DIM>(a.B, i, Bi);
+    if (!a.rates_only) drho_i = a.drho[i];
+    if (TURB && tag_kind(ti) == kBuffer) qb = a.bidx[tag_bid(ti)];
+  };
+  constexpr bool early = hoist_epilogue<L>();
+  if (early) load_update();
   constexpr int NR = (DIM == 3 && TURB) ? 3 : 2;
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
@@ -284,6 +291,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     dfe = team_sum<L>(dfe);
   }
   if (lane != 0) return m_pairs;
+  if (!early) load_update();
   const double two_over_rho = 2.0 / rho_i;
   double anu_d[3] = {two_over_rho * (double)av[0], two_over_rho * (double)av[1],
                      two_over_rho * (double)av[2]};
@@ -390,32 +398,39 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   const T pi = a.p[i];
   T Bi[6];
   if (MODE >= 2) load_B<T, DIM>(a.B, i, Bi);
-  const T vol_i = pc.vol[i];
-  const double xd[3] = {a.x[0][i], a.x[1][i], a.x[2][i]};
   if (!is_real(ti)) {
     if (!a.rates_only && lane == 0) {
       for (int k = 0; k < 3; ++k) {
-        a.xo[k][i] = xd[k];
+        a.xo[k][i] = a.x[k][i];
         a.xro[k][i] = xr_i[k];
       }
       const T vw[3] = {T(0), T(0), T(0)};
-      write_drec<T, DIM>(a.drec, i, xi, vw, T(0), -vol_i);
+      write_drec<T, DIM>(a.drec, i, xi, vw, T(0), -pc.vol[i]);
     }
     return m_pairs;
   }
-  // operands of the update after the sum: in flight during the walk
-  const double rho_i = a.rho[i];
-  const int qb = tag_kind(ti) == kBuffer ? a.bidx[tag_bid(ti)] : -1;
+  // operands of the update after the sum: issued before the walk by wide
+  // teams (in flight during it), after the sum by narrow ones
+  double rho_i = 0.0, xd[3] = {0.0, 0.0, 0.0};
+  int qb = -1, c_i = 0;
   T v_i[3] = {T(0), T(0), T(0)}, anu_i[3] = {T(0), T(0), T(0)}, xrb_i[3] = {T(0), T(0), T(0)};
-  int c_i = 0;
-  if (!a.rates_only) {
-    for (int k = 0; k < DIM; ++k) {
-      v_i[k] = a.v[k][i];
-      anu_i[k] = a.anu[k][i];
-      if (a.xrb[0]) xrb_i[k] = a.xrb[k][i];
+  T vol_i = T(0);
+  auto load_update = [&]() {
+    rho_i = a.rho[i];
+    qb = tag_kind(ti) == kBuffer ? a.bidx[tag_bid(ti)] : -1;
+    if (!a.rates_only) {
+      for (int k = 0; k < 3; ++k) xd[k] = a.x[k][i];
+      for (int k = 0; k < DIM; ++k) {
+        v_i[k] = a.v[k][i];
+        anu_i[k] = a.anu[k][i];
+        if (a.xrb[0]) xrb_i[k] = a.xrb[k][i];
+      }
+      c_i = pc.cell[i];
+      vol_i = pc.vol[i];
     }
-    c_i = pc.cell[i];
-  }
+  };
+  constexpr bool early = hoist_epilogue<L>();
+  if (early) load_update();
   T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
   constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec, h,
@@ -469,6 +484,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
     s[k] = team_sum<L>(s[k]);
   }
   if (lane != 0) return m_pairs;
+  if (!early) load_update();
   if (qb >= 0 && a.bufs[qb].p_mode != kPNone) {
     const T pob = a.bufs[qb].p_mode == kPPrescribed
                       ? (T)(a.bufs[qb].p_ob * buffer_ramp(a.bufs[qb], a.t)) : pi;
@@ -576,12 +592,18 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
     if (is_real(ti)) {
       const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
       const T pi = a.p[i];
-      // operands of the update after the sum: in flight during the walk
-      const double rho_i = a.rho[i];
+      // operands of the update after the sum: issued before the walk by
+      // wide teams, after the sum by narrow ones
       const bool next = !a.rates_only && !a.last;
+      double rho_i = 0.0, k_i = 0.0;
       T Bw[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-      if (next) load_B<T, DIM>(a.B, i, Bw);
-      const double k_i = (TURB && next) ? (double)a.k[i] : 0.0;
+      auto load_update = [&]() {
+        rho_i = a.rho[i];
+        if (next) load_B<T, DIM>(a.B, i, Bw);
+        if (TURB && next) k_i = (double)a.k[i];
+      };
+      constexpr bool early = hoist_epilogue<L>();
+      if (early) load_update();
       T sum = T(0);
       int m = 0;
       for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec, h,
@@ -610,6 +632,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       cnt = m;
       sum = team_sum<L>(sum);
       if (lane == 0) {
+        if (!early) load_update();
         const double drho = 2.0 * rho_i * (double)sum;
         if (a.rates_only) {
           a.o_drho[i] = drho;

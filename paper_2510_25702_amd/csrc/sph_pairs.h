@@ -226,10 +226,11 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 // then the candidates are tested; fn(j, r, r2, q) with q[0..NR-1] the
 // records of j.  Same pairs in the same order as for_neighbors.
 // The record passes carry less per candidate than the position-only loop:
-// deeper batches pay off, the more so the fewer lanes share a particle
-// (measured: 3 at four lanes, 6 at one or two).
+// deeper batches pay off when few lanes share a particle (measured: 6 at one
+// or two lanes); at four, with the next batch's entries loading under the
+// current records, two candidates per lane and batch are best.
 #ifndef SPHX_REC_UNROLL_WIDE
-#define SPHX_REC_UNROLL_WIDE 3
+#define SPHX_REC_UNROLL_WIDE 2
 #endif
 #ifndef SPHX_REC_UNROLL_NARROW
 #define SPHX_REC_UNROLL_NARROW 6
@@ -251,6 +252,16 @@ struct ListHead {
   uint32_t e[U];
 };
 
+// Teams of at least this many lanes load the head of the list with the tag;
+// narrower ones load it in the walk.
+#ifndef SPHX_HEAD_MIN_LANES
+#define SPHX_HEAD_MIN_LANES 4
+#endif
+template <int L>
+constexpr bool head_early() {
+  return L >= SPHX_HEAD_MIN_LANES;
+}
+
 template <typename T, int L>
 __device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>& pc, int i,
                                                                int lane) {
@@ -260,7 +271,7 @@ __device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>&
   h.stale = true;
 #pragma unroll
   for (int u = 0; u < U; ++u) h.e[u] = 0u;
-  if (pc.nbr) {
+  if (head_early<L>() && pc.nbr) {
     h.cnt = pc.ncnt[i];
     h.stale = pc.stale && *pc.stale;
 #pragma unroll
@@ -272,21 +283,91 @@ __device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>&
   return h;
 }
 
-// The list walk proper: each batch's records are gathered while the next
-// batch's entries load; a slot past the count gathers particle i's own
-// records (in bounds, never used).
+// Teams of at least SPHX_HOIST_MIN_LANES lanes issue the loads of the update
+// after the sum before the walk.  Narrower teams walk more batches per lane,
+// so the latency saved is smaller and the registers held through the walk
+// cost occupancy (measured: 3D two-lane and 2D FP64 one-lane pressure passes
+// fell below four and three wavefronts per SIMD).  Where the head of the list
+// was loaded with the tag, SPHX_AHEAD_MIN_LANES bounds the teams that also
+// load the next batch's entries under the current batch's records.
+#ifndef SPHX_AHEAD_MIN_LANES
+#define SPHX_AHEAD_MIN_LANES 1
+#endif
+#ifndef SPHX_HOIST_MIN_LANES
+#define SPHX_HOIST_MIN_LANES 4
+#endif
+template <int L>
+constexpr bool hoist_epilogue() {
+  return L >= SPHX_HOIST_MIN_LANES;
+}
+
+// The list walk proper.  Wide teams start from the head loaded with the tag
+// and gather each batch's records while the next batch's entries load (a
+// slot past the count gathers particle i's own records: in bounds, never
+// used).  Narrow teams, whose lists span several batches per lane, load the
+// count and each batch's entries in turn (measured: the early head made the
+// 3D two-lane passes 11-18 % slower).
 template <typename T, int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
                                                   const T xi[3], const V4<T>* const* rec,
                                                   const ListHead<rec_unroll<L>()>& h,
                                                   Fn&& fn) {
   constexpr int kUnroll = rec_unroll<L>();
-  if (pc.nbr && !h.stale) {
+  constexpr bool kAhead = L >= SPHX_AHEAD_MIN_LANES;
+  // the candidates of one batch: entries e, records q
+  auto test = [&](int kb, int cnt, const uint32_t (&e)[kUnroll], const V4<T> (&q)[kUnroll][NR]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (kb + u * L >= cnt) break;
+      const int j = (int)(e[u] & kNbrIdxMask);
+      const int code = (int)(e[u] >> kNbrIdxBits);
+      const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+      T r[3];
+      r[0] = (xi[0] - q[u][0].a) + (-T(dx) * pc.csz);
+      r[1] = (xi[1] - q[u][0].b) + (-T(dy) * pc.csz);
+      r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-T(dz) * pc.csz) : T(0);
+      const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                            : r[0] * r[0] + r[1] * r[1];
+      if (r2 < pc.rc2) fn(j, r, r2, q[u]);
+    }
+  };
+  if (!head_early<L>()) {
+    // the count and each batch's entries after the tag test; a slot past
+    // the count repeats the batch's first entry
+    if (pc.nbr && !(pc.stale && *pc.stale)) {
+      const int cnt = pc.ncnt[i];
+      for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+        uint32_t e[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int k = kb + u * L;
+          e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
+        }
+        V4<T> q[kUnroll][NR];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = (int)(e[u] & kNbrIdxMask);
+#pragma unroll
+          for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
+        }
+        pin_records<T, DIM, kUnroll, NR>(q);
+        test(kb, cnt, e, q);
+      }
+      return;
+    }
+  } else if (pc.nbr && !h.stale) {
     const int cnt = h.cnt;
     uint32_t e[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) e[u] = h.e[u];
     for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      if (!kAhead && kb != lane) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int k = kb + u * L;
+          e[u] = k < cnt ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
+        }
+      }
       V4<T> q[kUnroll][NR];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -298,25 +379,14 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int k = kb + (kUnroll + u) * L;
-        en[u] = k < cnt ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
+        en[u] = (kAhead && k < cnt) ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
       }
       pin_records<T, DIM, kUnroll, NR>(q);
+      test(kb, cnt, e, q);
+      if (kAhead) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        if (kb + u * L >= cnt) break;
-        const int j = (int)(e[u] & kNbrIdxMask);
-        const int code = (int)(e[u] >> kNbrIdxBits);
-        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
-        T r[3];
-        r[0] = (xi[0] - q[u][0].a) + (-T(dx) * pc.csz);
-        r[1] = (xi[1] - q[u][0].b) + (-T(dy) * pc.csz);
-        r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-T(dz) * pc.csz) : T(0);
-        const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
-                              : r[0] * r[0] + r[1] * r[1];
-        if (r2 < pc.rc2) fn(j, r, r2, q[u]);
+        for (int u = 0; u < kUnroll; ++u) e[u] = en[u];
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) e[u] = en[u];
     }
     return;
   }
