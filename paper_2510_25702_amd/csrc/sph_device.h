@@ -178,13 +178,17 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // ---------------------------------------------------------------------------
 // wave64 / block scans
 // ---------------------------------------------------------------------------
+// Inclusive scan over the 64 lanes with DPP register moves (no LDS): a
+// Hillis-Steele scan inside each row of 16 lanes (row_shr 1, 2, 4, 8; a lane
+// with no source reads 0), then lane 15 of each row added to the next row
+// (rows 1 and 3) and lane 31 added to rows 2 and 3.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int t = __shfl_up(v, o, kWave);
-    if (lane >= o) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
   return v;
 }
 
