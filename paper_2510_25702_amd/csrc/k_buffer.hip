@@ -295,8 +295,8 @@ __global__ __launch_bounds__(kInjThreads) void k_buffer_inject(InjArgs<T> a) {
     for (int kk = 2; kk <= kWave; kk <<= 1) {
 #pragma unroll
       for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-        const uint64_t ok = __shfl_xor(key, jj, kWave);
-        const int oi = __shfl_xor(idx, jj, kWave);
+        const uint64_t ok = lane_xor_by(key, jj);
+        const int oi = lane_xor_by(idx, jj);
         const bool up = (t & kk) == 0, low = (t & jj) == 0;
         if (low == up ? ok < key : ok > key) {
           key = ok;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_cell_keys(
     id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
   }
   // runs of equal keys: the head lane reserves the run's slots
-  const int prev = __shfl_up(id, 1, kWave);
+  const int prev = __builtin_amdgcn_update_dpp(0, id, 0x138, 0xF, 0xF, false);   // wave_shr:1
   const bool head = lane == 0 || prev != id;
   const uint64_t heads = __ballot(head);
   const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kSegThreads) void k_scan_seg(int32_t* __restrict__ 
   for (int q = 0; q < kSegPer; ++q) {
     const int inc = wave_incl_scan(v[q]);
     const int ex = run + inc - v[q];
-    run += __shfl(inc, kWave - 1, kWave);
+    run += __builtin_amdgcn_readlane(inc, kWave - 1);
     v[q] = ex;
   }
   if (lane == 0) sm[w] = run;

@@ -212,6 +212,49 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sm, int* total) {
   return r;
 }
 
+// Lane l's view of lane l ^ O by DPP register moves (no LDS): quad
+// permutations for O = 1, 2; for O = 4 the row shifted by 4 either way,
+// chosen by lane bit 2; for O = 8 the 16-lane row rotated by 8.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int O>
+__device__ __forceinline__ int lane_xor_i32(int v) {
+  if constexpr (O == 1) return dpp_move<0xB1>(v);            // quad_perm [1,0,3,2]
+  else if constexpr (O == 2) return dpp_move<0x4E>(v);       // quad_perm [2,3,0,1]
+  else if constexpr (O == 4) {
+    const int up = dpp_move<0x104>(v), down = dpp_move<0x114>(v);   // row_shl:4, row_shr:4
+    return (threadIdx.x & 4) ? down : up;
+  } else if constexpr (O == 8) return dpp_move<0x128>(v);     // row_ror:8
+  else return __shfl_xor(v, O, kWave);
+}
+template <int O, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, lane_xor_i32<O>(__builtin_bit_cast(int, v)));
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit values");
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)lane_xor_i32<O>((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)lane_xor_i32<O>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | (uint64_t)lo);
+  }
+}
+
+// lane_xor with the distance known after unrolling (a power of two < 64)
+template <typename T>
+__device__ __forceinline__ T lane_xor_by(T v, int o) {
+  switch (o) {
+    case 1: return lane_xor<1>(v);
+    case 2: return lane_xor<2>(v);
+    case 4: return lane_xor<4>(v);
+    case 8: return lane_xor<8>(v);
+    case 16: return lane_xor<16>(v);
+    default: return lane_xor<32>(v);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll

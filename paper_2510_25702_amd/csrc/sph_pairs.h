@@ -39,36 +39,6 @@ inline void launch_pass(sph_ctx* c, void (*k)(KArgs...), int64_t grid, Args... a
   else hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, c->stream, args...);
 }
 
-// Lane l's view of lane l ^ O by DPP register moves (no LDS): quad
-// permutations for O = 1, 2; for O = 4 the row shifted by 4 either way,
-// chosen by lane bit 2; for O = 8 the 16-lane row rotated by 8.
-template <int CTRL>
-__device__ __forceinline__ int dpp_move(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-template <int O>
-__device__ __forceinline__ int lane_xor_i32(int v) {
-  if constexpr (O == 1) return dpp_move<0xB1>(v);            // quad_perm [1,0,3,2]
-  else if constexpr (O == 2) return dpp_move<0x4E>(v);       // quad_perm [2,3,0,1]
-  else if constexpr (O == 4) {
-    const int up = dpp_move<0x104>(v), down = dpp_move<0x114>(v);   // row_shl:4, row_shr:4
-    return (threadIdx.x & 4) ? down : up;
-  } else if constexpr (O == 8) return dpp_move<0x128>(v);     // row_ror:8
-  else return __shfl_xor(v, O, kWave);
-}
-template <int O, typename T>
-__device__ __forceinline__ T lane_xor(T v) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, lane_xor_i32<O>(__builtin_bit_cast(int, v)));
-  } else {
-    static_assert(sizeof(T) == 8, "32- or 64-bit values");
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)lane_xor_i32<O>((int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)lane_xor_i32<O>((int)(uint32_t)(u >> 32));
-    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | (uint64_t)lo);
-  }
-}
-
 // Sum over the L lanes of a team (butterfly: the same order in every run).
 template <int L, typename T>
 __device__ __forceinline__ T team_sum(T v) {
