@@ -175,6 +175,7 @@ struct AdjDev {
       *ab[3], *cb[6], *lV0;
   double* abar;              // [16][cap]
   int32_t* child;            // [cap] child slot -> particle id of the copy (-1: none)
+  V4<double>* rec[5];        // [nmax][cap] packed records of the reverse pair passes
   uint32_t* flags;
 };
 
@@ -249,6 +250,104 @@ __device__ __forceinline__ void adj_neighbors(const AdjDev& A, const double* con
         const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                                    : r[0] * r[0] + r[1] * r[1];
         if (r2 < A.rc2 && j != i) fn(j, r, r2);
+      }
+    }
+}
+
+// Packed j-side records of the reverse continuity and pressure passes
+// (32-byte vectors of FP64), written per sub-step by the per-particle kernel
+// that precedes each pass, so that a pass gathers NR vectors per candidate
+// instead of a dozen scalars.  Flat value order (V negative for walls):
+//   continuity: x[DIM], V, p, v[DIM], w = 2 rho lD
+//   pressure:   x[DIM], V, p, B (2D: xx, xy, yy; 3D: xx, xy, xz, yy, yz, zz),
+//               Q[DIM], s[DIM]
+// The two sets are never live together and share storage.
+template <int DIM>
+struct AdjRec {
+  static constexpr int iV = DIM, ip = DIM + 1;
+  // continuity
+  static constexpr int iv = DIM + 2, iw = 2 * DIM + 2, nd = (2 * DIM + 3 + 3) / 4;
+  // pressure
+  static constexpr int nB = DIM == 2 ? 3 : 6, iB = DIM + 2, iQ = iB + nB, is = iQ + DIM;
+  static constexpr int np = (is + DIM + 3) / 4;
+  static constexpr int nmax = np > nd ? np : nd;
+};
+
+template <int NR>
+__device__ __forceinline__ void put_rec(V4<double>* const* rec, int i, const double (&v)[4 * NR]) {
+#pragma unroll
+  for (int w = 0; w < NR; ++w) rec[w][i] = V4<double>{v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]};
+}
+
+__device__ __forceinline__ double rv(const V4<double>* q, int k) {
+  const V4<double>& v = q[k >> 2];
+  switch (k & 3) {
+    case 0: return v.a;
+    case 1: return v.b;
+    case 2: return v.c;
+    default: return v.d;
+  }
+}
+
+// The pairs of adj_neighbors over packed records (positions in the first
+// DIM values): the NR vectors of every candidate of a batch are loaded
+// before its tests; fn(j, r, r2, q) with q the records of j.
+template <int DIM, int L, int NR, typename Fn>
+__device__ __forceinline__ void adj_neighbors_rec(const AdjDev& A, const V4<double>* const* rec,
+                                                  int i, int lane, const double xi[3], Fn&& fn) {
+  if (A.nbr && !(A.stale[0] | A.stale[1])) {
+    const int cnt = A.ncnt[i];
+    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      uint32_t e[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = kb + u * L;
+        e[u] = A.nbr[(int64_t)(k < cnt ? k : kb) * A.cap + i];
+      }
+      V4<double> q[kUnroll][NR];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = (int)(e[u] & kNbrIdxMask);
+#pragma unroll
+        for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (kb + u * L >= cnt) break;
+        const int j = (int)(e[u] & kNbrIdxMask);
+        const int code = (int)(e[u] >> kNbrIdxBits);
+        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
+        double r[3];
+        r[0] = (xi[0] - q[u][0].a) + (-(double)dx * A.csz);
+        r[1] = (xi[1] - q[u][0].b) + (-(double)dy * A.csz);
+        r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-(double)dz * A.csz) : 0.0;
+        const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                   : r[0] * r[0] + r[1] * r[1];
+        if (r2 < A.rc2) fn(j, r, r2, q[u]);
+      }
+    }
+    return;
+  }
+  int cx, cy, cz;
+  stencil_of<DIM>(A, i, cx, cy, cz);
+  constexpr int zr = DIM == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int base = ((cz + dz) * A.ny + (cy + dy)) * A.nx + cx;
+      const int j0 = A.cs[base - 1], j1 = A.cs[base], j2 = A.cs[base + 1], j3 = A.cs[base + 2];
+      const double oy = -(double)dy * A.csz, oz = -(double)dz * A.csz;
+      for (int j = j0 + lane; j < j3; j += L) {
+        V4<double> q[NR];
+#pragma unroll
+        for (int w = 0; w < NR; ++w) q[w] = rec[w][j];
+        const double ox = j < j1 ? A.csz : (j < j2 ? 0.0 : -A.csz);
+        double r[3];
+        r[0] = (xi[0] - q[0].a) + ox;
+        r[1] = (xi[1] - q[0].b) + oy;
+        r[2] = DIM == 3 ? (xi[2] - q[0].c) + oz : 0.0;
+        const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
+                                   : r[0] * r[0] + r[1] * r[1];
+        if (r2 < A.rc2 && j != i) fn(j, r, r2, q);
       }
     }
 }
@@ -500,16 +599,70 @@ __global__ __launch_bounds__(256) void k_adj_seed(AdjDev A, SeedArgs s, int N) {
 // p_s, V_s, rho_h,s):  D_i = 2 rho_i sum_j V_j f (v_ij . r / 2 + kappa p_ij |r|)
 // with walls v_j = 0, p_j = p_i; kappa = 1 / (2 rho0 c0).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_dprep(AdjDev A, int last, double half) {
+// Continuity record of particle i for the reverse pass of sub-step s
+// (positions and velocities after the sub-step, p and V at it).
+template <int DIM>
+__device__ __forceinline__ void put_drec(const AdjDev& A, int i, int s, double lD) {
+  using R = AdjRec<DIM>;
+  const int64_t cap = A.cap;
+  double v[4 * R::nd];
+#pragma unroll
+  for (int k = 0; k < 4 * R::nd; ++k) v[k] = 0.0;
+  const uint32_t t = A.tag[i];
+  const double vol = A.VOL[(int64_t)s * cap + i];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    v[k] = snap3(A.XR, cap, s + 1, k)[i];
+    v[R::iv + k] = snap3(A.V, cap, s + 1, k)[i];
+  }
+  v[R::iV] = tag_kind(t) == kWall ? -vol : vol;
+  v[R::ip] = A.P[(int64_t)s * cap + i];
+  v[R::iw] = is_real(t) ? 2.0 * A.RH[(int64_t)s * cap + i] * lD : 0.0;
+  put_rec<R::nd>(A.rec, i, v);
+}
+
+// Pressure record of particle i for the reverse pass of sub-step s, with
+// the cotangents Q and s of the kick.
+template <int DIM>
+__device__ __forceinline__ void put_prec_adj(const AdjDev& A, int i, int s, const double Q[3],
+                                             const double sv[3]) {
+  using R = AdjRec<DIM>;
+  const int64_t cap = A.cap;
+  double v[4 * R::np];
+#pragma unroll
+  for (int k = 0; k < 4 * R::np; ++k) v[k] = 0.0;
+  const double vol = A.VOL[(int64_t)s * cap + i];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    v[k] = snap3(A.XR, cap, s, k)[i];
+    v[R::iQ + k] = Q[k];
+    v[R::is + k] = sv[k];
+  }
+  v[R::iV] = tag_kind(A.tag[i]) == kWall ? -vol : vol;
+  v[R::ip] = A.P[(int64_t)s * cap + i];
+  if (DIM == 2) {
+    v[R::iB] = A.B[0][i];
+    v[R::iB + 1] = A.B[1][i];
+    v[R::iB + 2] = A.B[3][i];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[R::iB + k] = A.B[k][i];
+  }
+  put_rec<R::np>(A.rec, i, v);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_adj_dprep(AdjDev A, int last, double half, int s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  if (!is_real(A.tag[i])) {
-    A.lD[i] = 0.0;
-    return;
+  double lD = 0.0;
+  if (is_real(A.tag[i])) {
+    // last sub-step: D_{N-1} is the carried rate, rho_end = rho_h + dt/2 D;
+    // earlier: rho_h,s+1 = rho_h,s + dt D_s
+    lD = last ? A.lD[i] + half * A.lr[i] : 2.0 * half * A.lr[i];
   }
-  // last sub-step: D_{N-1} is the carried rate, rho_end = rho_h + dt/2 D;
-  // earlier: rho_h,s+1 = rho_h,s + dt D_s
-  A.lD[i] = last ? A.lD[i] + half * A.lr[i] : 2.0 * half * A.lr[i];
+  A.lD[i] = lD;
+  put_drec<DIM>(A, i, s, lD);
 }
 
 template <int DIM, int L>
@@ -519,25 +672,25 @@ __global__ __launch_bounds__(256) void k_adj_density(AdjDev A, int s, double kap
   if (i >= A.n) return;
   if (!is_real(A.tag[i])) return;
   const int64_t cap = A.cap;
-  const double* xr[3] = {snap3(A.XR, cap, s + 1, 0), snap3(A.XR, cap, s + 1, 1),
-                         snap3(A.XR, cap, s + 1, 2)};
-  const double* v[3] = {snap3(A.V, cap, s + 1, 0), snap3(A.V, cap, s + 1, 1),
-                        snap3(A.V, cap, s + 1, 2)};
-  const double* p = A.P + (int64_t)s * cap;
-  const double* vol = A.VOL + (int64_t)s * cap;
+  using R = AdjRec<DIM>;
+  const double xi[3] = {snap3(A.XR, cap, s + 1, 0)[i], snap3(A.XR, cap, s + 1, 1)[i],
+                        DIM == 3 ? snap3(A.XR, cap, s + 1, 2)[i] : 0.0};
+  const double vi[3] = {snap3(A.V, cap, s + 1, 0)[i], snap3(A.V, cap, s + 1, 1)[i],
+                        DIM == 3 ? snap3(A.V, cap, s + 1, 2)[i] : 0.0};
   const double* rh = A.RH + (int64_t)s * cap;
-  const double vi[3] = {v[0][i], v[1][i], DIM == 3 ? v[2][i] : 0.0};
-  const double pi = p[i], Vi = vol[i];
+  const double pi = A.P[(int64_t)s * cap + i], Vi = A.VOL[(int64_t)s * cap + i];
   const double wi = 2.0 * rh[i] * A.lD[i];
   // lv[3], lx[3], lp, lV
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  adj_neighbors<DIM, L>(A, xr, i, lane, [&](int j, const double r[3], double r2) {
+  adj_neighbors_rec<DIM, L, R::nd>(A, A.rec, i, lane, xi,
+                                   [&](int j, const double r[3], double r2, const V4<double>* q) {
     const double rr = sqrt(r2);
     double f, fp;
     kernel_f(rr, A.inv_h, A.kf, f, fp);
     const double rh_[3] = {r[0] / rr, r[1] / rr, r[2] / rr};
-    const double Vj = vol[j];
-    if (tag_kind(A.tag[j]) == kWall) {
+    const double Vs = rv(q, R::iV);
+    const double Vj = Vs < 0.0 ? -Vs : Vs;
+    if (Vs < 0.0) {   // wall
       const double Sij = 0.5 * dot3(vi, r);
       for (int k = 0; k < DIM; ++k) {
         acc[k] += 0.5 * f * r[k] * wi * Vj;
@@ -545,9 +698,10 @@ __global__ __launch_bounds__(256) void k_adj_density(AdjDev A, int s, double kap
       }
       return;
     }
-    const double wj = 2.0 * rh[j] * A.lD[j];
-    const double vij[3] = {vi[0] - v[0][j], vi[1] - v[1][j], DIM == 3 ? vi[2] - v[2][j] : 0.0};
-    const double pij = pi - p[j];
+    const double wj = rv(q, R::iw);
+    const double vij[3] = {vi[0] - rv(q, R::iv), vi[1] - rv(q, R::iv + 1),
+                           DIM == 3 ? vi[2] - rv(q, R::iv + 2) : 0.0};
+    const double pij = pi - rv(q, R::ip);
     const double Sij = 0.5 * dot3(vij, r) + kappa * pij * rr;
     const double Sji = 0.5 * dot3(vij, r) - kappa * pij * rr;
     for (int k = 0; k < DIM; ++k) {
@@ -589,12 +743,16 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
+  const double zero[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < 3; ++k) {
     A.qb[k][i] = 0.0;
     A.sb[k][i] = 0.0;
   }
   const uint32_t ti = A.tag[i];
-  if (!is_real(ti)) return;
+  if (!is_real(ti)) {
+    put_prec_adj<DIM>(A, i, s, zero, zero);
+    return;
+  }
   const int64_t cap = A.cap;
   double lv[3], lx[3];
   for (int k = 0; k < 3; ++k) {
@@ -614,6 +772,7 @@ __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
       A.lx[k][i] = lx[k];
       A.lv[k][i] = 0.0;
     }
+    put_prec_adj<DIM>(A, i, s, zero, zero);
     return;
   }
   const double rho = A.RH[(int64_t)s * cap + i];
@@ -625,6 +784,7 @@ __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
     A.qb[k][i] = Qb[k];
     A.lv[k][i] = lv[k];
   }
+  double sv[3] = {0.0, 0.0, 0.0};
   if (q >= 0 && a.bufs[q].p_mode != kPNone) {
     const BufDev& b = a.bufs[q];
     const double pob = b.p_mode == kPPrescribed ? b.p_ob * buffer_ramp(b, a.t)
@@ -638,8 +798,12 @@ __global__ __launch_bounds__(256) void k_adj_kick(AdjDev A, KickArgs a, int s) {
     } else {
       c[0] = Qb[0]; c[1] = Qb[1]; c[2] = Qb[2];
     }
-    for (int k = 0; k < 3; ++k) A.sb[k][i] = -2.0 * pob * c[k];
+    for (int k = 0; k < 3; ++k) {
+      sv[k] = -2.0 * pob * c[k];
+      A.sb[k][i] = sv[k];
+    }
   }
+  put_prec_adj<DIM>(A, i, s, Qb, sv);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,10 +819,10 @@ __global__ __launch_bounds__(256) void k_adj_pressure(AdjDev A, KickArgs a, int 
   const uint32_t ti = A.tag[i];
   if (!is_real(ti)) return;
   const int64_t cap = A.cap;
-  const double* xr[3] = {snap3(A.XR, cap, s, 0), snap3(A.XR, cap, s, 1), snap3(A.XR, cap, s, 2)};
-  const double* p = A.P + (int64_t)s * cap;
-  const double* vol = A.VOL + (int64_t)s * cap;
-  const double pi = p[i], Vi = vol[i];
+  using R = AdjRec<DIM>;
+  const double xi[3] = {snap3(A.XR, cap, s, 0)[i], snap3(A.XR, cap, s, 1)[i],
+                        DIM == 3 ? snap3(A.XR, cap, s, 2)[i] : 0.0};
+  const double pi = A.P[(int64_t)s * cap + i], Vi = A.VOL[(int64_t)s * cap + i];
   double Bi[6] = {1, 0, 0, 1, 0, DIM == 3 ? 1.0 : 0.0};
   if (MODE >= 2)
     for (int k = 0; k < 6; ++k) Bi[k] = DIM == 2 && (k == 2 || k == 4 || k == 5) ? 0.0 : A.B[k][i];
@@ -666,16 +830,18 @@ __global__ __launch_bounds__(256) void k_adj_pressure(AdjDev A, KickArgs a, int 
   const double si_[3] = {A.sb[0][i], A.sb[1][i], A.sb[2][i]};
   // 0-2 lx, 3 lp, 4 lV, 5-10 lB, 11-13 Q (forward sum), 14-16 s (forward sum)
   double acc[17] = {0};
-  adj_neighbors<DIM, L>(A, xr, i, lane, [&](int j, const double r[3], double r2) {
+  adj_neighbors_rec<DIM, L, R::np>(A, A.rec, i, lane, xi,
+                                   [&](int j, const double r[3], double r2, const V4<double>* q) {
     const double rr = sqrt(r2);
     double f, fp;
     kernel_f(rr, A.inv_h, A.kf, f, fp);
     const double rh_[3] = {r[0] / rr, r[1] / rr, r[2] / rr};
-    const double Vj = vol[j];
-    const bool wall = tag_kind(A.tag[j]) == kWall;
+    const double Vs = rv(q, R::iV);
+    const double Vj = Vs < 0.0 ? -Vs : Vs;
+    const bool wall = Vs < 0.0;
     // s_i = sum_j V_j f r and the i- and j-side terms of sbar
-    const double sj_[3] = {wall ? 0.0 : A.sb[0][j], wall ? 0.0 : A.sb[1][j],
-                           wall ? 0.0 : A.sb[2][j]};
+    const double sj_[3] = {wall ? 0.0 : rv(q, R::is), wall ? 0.0 : rv(q, R::is + 1),
+                           (wall || DIM == 2) ? 0.0 : rv(q, R::is + 2)};
     for (int k = 0; k < 3; ++k) acc[14 + k] += Vj * f * r[k];
     {
       const double di = dot3(si_, r), dj = dot3(sj_, r);
@@ -705,12 +871,19 @@ __global__ __launch_bounds__(256) void k_adj_pressure(AdjDev A, KickArgs a, int 
       for (int k = 0; k < 3; ++k) acc[11 + k] += Vj * f * Mr[k];
       return;
     }
-    const double pj = p[j];
-    const double Qj[3] = {A.qb[0][j], A.qb[1][j], A.qb[2][j]};
+    const double pj = rv(q, R::ip);
+    const double Qj[3] = {rv(q, R::iQ), rv(q, R::iQ + 1), DIM == 3 ? rv(q, R::iQ + 2) : 0.0};
     double Mr[3], MQi[3], MQj[3];
     if (MODE >= 2) {
       double Bj[6];
-      for (int k = 0; k < 6; ++k) Bj[k] = DIM == 2 && (k == 2 || k == 4 || k == 5) ? 0.0 : A.B[k][j];
+      if (DIM == 2) {
+        Bj[0] = rv(q, R::iB);
+        Bj[1] = rv(q, R::iB + 1);
+        Bj[3] = rv(q, R::iB + 2);
+        Bj[2] = Bj[4] = Bj[5] = 0.0;
+      } else {
+        for (int k = 0; k < 6; ++k) Bj[k] = rv(q, R::iB + k);
+      }
       double Bjr[3], Bir[3], BjQi[3], BiQi[3], BjQj[3], BiQj[3];
       symv_d<DIM>(Bj, r, Bjr);
       symv_d<DIM>(Bi, r, Bir);
@@ -786,22 +959,22 @@ __global__ __launch_bounds__(256) void k_adj_eos(AdjDev A, int s, double c02, do
 
 // k_adj_eos of sub-step s + 1 followed by k_adj_dprep of sub-step s (both
 // per particle, one launch).
+template <int DIM>
 __global__ __launch_bounds__(256) void k_adj_eos_dprep(AdjDev A, int s1, double c02, double mass,
                                                        double half) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  if (!is_real(A.tag[i])) {
-    A.lp[i] = 0.0;
-    A.lV[i] = 0.0;
-    A.lD[i] = 0.0;
-    return;
+  double lD = 0.0;
+  if (is_real(A.tag[i])) {
+    const double r = A.RH[(int64_t)s1 * A.cap + i];
+    const double lr = A.lr[i] + c02 * A.lp[i] - mass / (r * r) * A.lV[i];
+    A.lr[i] = lr;
+    lD = 2.0 * half * lr;
   }
-  const double r = A.RH[(int64_t)s1 * A.cap + i];
-  const double lr = A.lr[i] + c02 * A.lp[i] - mass / (r * r) * A.lV[i];
-  A.lr[i] = lr;
   A.lp[i] = 0.0;
   A.lV[i] = 0.0;
-  A.lD[i] = 2.0 * half * lr;
+  A.lD[i] = lD;
+  put_drec<DIM>(A, i, s1 - 1, lD);
 }
 
 // ---------------------------------------------------------------------------
@@ -1200,7 +1373,7 @@ struct AdjLayout {
     total += (b + 255) & ~size_t(255);
     return o;
   }
-  size_t X, XR, V, RH, P, VOL, DD, rho0, vol0, tag, cot, abar, child;
+  size_t X, XR, V, RH, P, VOL, DD, rho0, vol0, tag, cot, abar, child, rec;
   // the step's cell build, neighbour list, correction and buffer update,
   // kept so that the reverse sweep does not depend on the context's state
   size_t pid, cell, cs, nbr, ncnt, stale, B, dec, inj;
@@ -1226,6 +1399,8 @@ AdjLayout adj_layout(const sph_ctx* c, int N) {
   L.cot = L.take(c8 * kCot);
   L.abar = L.take(c8 * 16);
   L.child = L.take((size_t)cap * 4);
+  L.rec = L.take((size_t)cap * sizeof(V4<double>) *
+                 (c->P.dim == 2 ? AdjRec<2>::nmax : AdjRec<3>::nmax));
   L.pid = L.take((size_t)cap * 4);
   L.cell = L.take((size_t)cap * 4);
   L.cs = L.take(((size_t)c->grid.ncell + 1) * 4);
@@ -1289,6 +1464,11 @@ AdjDev make_adj(sph_ctx* c, char* ws, const AdjLayout& L, int n, int64_t pid_cap
   A.lV0 = nxt();
   A.abar = (double*)(ws + L.abar);
   A.child = (int32_t*)(ws + L.child);
+  {
+    const int nrec = c->P.dim == 2 ? AdjRec<2>::nmax : AdjRec<3>::nmax;
+    V4<double>* r0 = (V4<double>*)(ws + L.rec);
+    for (int w = 0; w < 5; ++w) A.rec[w] = w < nrec ? r0 + (int64_t)w * c->cap : nullptr;
+  }
   A.flags = c->S.flags;
   return A;
 }
@@ -1395,8 +1575,8 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
   ka.dt = dt;
   const double kappa = 1.0 / (2.0 * P.rho0 * P.c0);
   for (int s = N - 1; s >= 0; --s) {
-    if (s == N - 1) k_adj_dprep<<<nb, 256, 0, st>>>(A, 1, 0.5 * dt);
-    else k_adj_eos_dprep<<<nb, 256, 0, st>>>(A, s + 1, P.c0 * P.c0, mass, 0.5 * dt);
+    if (s == N - 1) k_adj_dprep<DIM><<<nb, 256, 0, st>>>(A, 1, 0.5 * dt, s);
+    else k_adj_eos_dprep<DIM><<<nb, 256, 0, st>>>(A, s + 1, P.c0 * P.c0, mass, 0.5 * dt);
     ADJ_TEAM(Lt, k_adj_density<DIM, TL><<<nblk_a((int64_t)n * TL), 256, 0, st>>>(A, s, kappa));
     k_adj_kick<DIM><<<nb, 256, 0, st>>>(A, ka, s);
     switch (P.obc_mode) {
