@@ -297,6 +297,24 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
   const int total = a.cell_start[a.ncell];
   if (s == 0 && total != n_out) atomicOr(a.flags, kFlagCountMismatch);
   if (s >= n_in) return;
+  // the source slot's fields load with its key, while the rank is found
+  double xv[3];
+  T vr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xv[k] = a.x[k][s];
+    vr[k] = a.v[k][s];
+  }
+  const double r = a.rho[s];
+  const T drho = a.drho[s];
+  const uint32_t t = a.tag[s];
+  const uint32_t pid = a.pid[s];
+  T kt = T(0), et = T(0), nt = T(0);
+  if (a.turb) {
+    kt = a.k[s];
+    et = a.eps[s];
+    nt = a.nut[s];
+  }
   const int c = a.key[s];
   if (c < 0) return;
   const int b = a.cell_start[c], e = a.cell_start[c + 1];
@@ -305,32 +323,24 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
   const int d = b + rank;
   if (d >= n_out) return;
   int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
-  T xr[3], vr[3];
+  T xr[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double xv = a.x[k][s];
-    a.xo[k][d] = xv;
+    a.xo[k][d] = xv[k];
     double org = (k < DIM) ? a.g.lo[k] + (double)cc[k] * a.g.cs : 0.0;
-    xr[k] = (T)(xv - org);
+    xr[k] = (T)(xv[k] - org);
     a.xro[k][d] = xr[k];
-    vr[k] = a.v[k][s];
     a.vo[k][d] = vr[k];
   }
-  double r = a.rho[s];
   a.rhoo[d] = r;
-  a.drhoo[d] = a.drho[s];
-  uint32_t t = a.tag[s];
+  a.drhoo[d] = drho;
   a.tago[d] = t;
-  a.pido[d] = a.pid[s];
+  a.pido[d] = pid;
   const bool wall = tag_kind(t) == kWall;
   const T vol = (T)(wall ? a.Vw : a.mass / r);
   a.volo[d] = vol;
   a.cello[d] = c;
-  T kt = T(0), et = T(0), nt = T(0);
   if (a.turb) {
-    kt = a.k[s];
-    et = a.eps[s];
-    nt = a.nut[s];
     a.ko[d] = kt;
     a.epso[d] = et;
     a.nuto[d] = nt;
