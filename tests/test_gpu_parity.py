@@ -387,6 +387,47 @@ def test_crafted_decisions_bit_exact(sph, ora):
     assert len({d & 0xFF for d in oo.values()}) == 6
 
 
+@pytest.mark.parametrize("pname,prec", [("fp64", 0), ("fp32", 1)])
+def test_many_injections_in_one_update(sph, ora, pname, prec):
+    # more injections in one update than one wavefront sorts in its registers
+    # (64): the workgroup sorts them in LDS; the children must still be the
+    # copies of their parents in canonical order with the next particle ids,
+    # and the recycled parents bit-identical to the oracle's, by particle id
+    from tests.test_oracle_buffer import DP, crafted, inlet
+    from cases import BUFFER, FLUID, make_tag
+    b1 = inlet(1, origin=(0.0, 0.5), hw=0.5)
+    gen = b1.length + b1.fringe
+    rng = np.random.default_rng(11)
+    n_inj = 200
+    pts = [(gen + 0.4 * DP * rng.uniform(), 0.02 + 0.96 * rng.uniform()) for _ in range(n_inj)]
+    tags = [make_tag(BUFFER, 1)] * n_inj
+    pts += [(0.5 * b1.length, 0.05 + 0.9 * k / 29) for k in range(30)]   # stay
+    tags += [make_tag(BUFFER, 1)] * 30
+    pts += [(-0.25 * DP, 0.1 + 0.8 * k / 9) for k in range(10)]          # delete
+    tags += [make_tag(BUFFER, 1)] * 10
+    pts += [(1.5, 0.5), (1.6, 0.6)]
+    tags += [make_tag(FLUID)] * 2
+    c = crafted(pts, tags, [b1])
+    ref = ora.OracleSim(c)
+    g = gpu_sim(sph, c, prec, capacity=len(pts) + 1024)
+    g.build_cells()
+    cnt_o = ref.buffer_update()
+    cnt_g = g.buffer_update()
+    assert cnt_o.n_inject[1] == n_inj and cnt_o.n_delete[1] == 10
+    for f in ("n_relabel", "n_inject", "n_delete", "n_revert"):
+        assert list(getattr(cnt_o, f)) == list(getattr(cnt_g, f)), f
+    so, sg = ref.snapshot(), g.state()
+    alive = (sg["tag"] & 3) != 3
+    gi = {int(p): i for i, p in enumerate(sg["pid"]) if alive[i]}
+    assert sorted(gi) == sorted(int(p) for p in so["pid"])
+    idx = np.array([gi[int(p)] for p in so["pid"]])
+    assert np.array_equal(sg["tag"][idx], so["tag"])
+    assert np.array_equal(sg["x"][idx], so["x"])
+    assert np.array_equal(sg["rho"][idx], so["rho"])
+    tol = 1e-14 if prec == sph.SPH_FP64 else 1e-6
+    assert np.abs(sg["v"][idx] - so["v"]).max() <= tol * max(1.0, np.abs(so["v"]).max())
+
+
 # --------------------------------------------------------------------------
 # whole advection steps
 # --------------------------------------------------------------------------
