@@ -62,7 +62,11 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
     acc(r, r2, pc.vol[j]);
     ++m_pairs;
   };
-  if (BUILD) scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair);
+  auto pair_v = [&](int, const T r[3], T r2, T vj) {   // V_j loaded with the positions
+    acc(r, r2, vj);
+    ++m_pairs;
+  };
+  if (BUILD) scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair_v);
   else for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
   if (a.mirror) {
     const double xi0 = a.x[0][i], xi1 = a.x[1][i], xi2 = a.x[2][i];

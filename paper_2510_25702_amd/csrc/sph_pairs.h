@@ -484,15 +484,24 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   const int cz = cyz / pc.ny;
   constexpr int zr = DIM == 3 ? 1 : 0;
   int cnt = 0;
-  for (int dz = -zr; dz <= zr; ++dz)
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int base = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx;
-      const int j0 = pc.cs[base - 1], j1 = pc.cs[base], j2 = pc.cs[base + 1],
-                j3 = pc.cs[base + 2];
+  for (int dz = -zr; dz <= zr; ++dz) {
+    // the cell ranges of the plane's three rows, loaded together (the list
+    // stores of a row would otherwise keep the next row's loads behind it)
+    int rows[3][4];
+#pragma unroll
+    for (int r3 = 0; r3 < 3; ++r3) {
+      const int base = ((cz + dz) * pc.ny + (cy + r3 - 1)) * pc.nx + cx;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rows[r3][k] = pc.cs[base - 1 + k];
+    }
+#pragma unroll
+    for (int r3 = 0; r3 < 3; ++r3) {
+      const int dy = r3 - 1;
+      const int j0 = rows[r3][0], j1 = rows[r3][1], j2 = rows[r3][2], j3 = rows[r3][3];
       const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
       // the same trip count for every lane of the team
       for (int jb = j0; jb < j3; jb += kUnroll * L) {
-        T q0[kUnroll], q1[kUnroll], q2[kUnroll];
+        T q0[kUnroll], q1[kUnroll], q2[kUnroll], qv[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int j = jb + u * L + lane;
@@ -500,6 +509,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           q0[u] = pc.xr[0][js];
           q1[u] = pc.xr[1][js];
           q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
+          qv[u] = pc.vol[js];   // with the positions: one round trip per batch
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -527,10 +537,11 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
             else o.nbr[(int64_t)(cnt + off) * o.stride + i] = ent;
           }
           cnt += tot;
-          if (in && r2 < pc.rc2) fn(j, r, r2);
+          if (in && r2 < pc.rc2) fn(j, r, r2, qv[u]);
         }
       }
     }
+  }
   if (lane == 0) {
     if (cnt > o.K) atomicOr(o.flags, kFlagNbrOverflow);
     o.ncnt[i] = cnt < o.K ? cnt : o.K;
