@@ -470,8 +470,8 @@ constexpr int list_stage() {
 // rounding), in stencil order.  A team of L lanes scans a row together (lane
 // l takes every L-th candidate, in the order of for_neighbors) and appends
 // the accepted candidates in candidate order with a wavefront ballot, so the
-// list order does not depend on L.  fn(j, r, r2) is called for the pairs
-// within 2h, as for_neighbors calls it.
+// list order does not depend on L.  fn(j, r, r2, V_j) is called for the
+// pairs within 2h, in for_neighbors' order.
 template <typename T, int DIM, int L, typename Fn>
 __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane, const T xi[3],
                                            const NbrOut<T>& o, Fn&& fn) {
