@@ -65,11 +65,9 @@ __global__ void k_get_particles(int n, double* x, double* v, double* rho, double
   if (pid) pid[i] = PD[i];
 }
 
-// K1: cell id of every particle (FP64, floor((x - lo) / cs), IEEE division)
-// and a distinct slot inside its cell; particles tagged dead get key -1.
-// The particles arrive (mostly) in the previous build's cell order, so each
-// run of equal keys along a wavefront takes its slots with one atomic.
-// Block 0 also clears the buffer-update counters of this step.
+// K1: cell id of every particle and a distinct slot inside its cell
+// (cell_key_slot); particles tagged dead get key -1.  Block 0 also clears
+// the buffer-update counters of this step.
 constexpr int kKeysThreads = 1024;
 
 template <int DIM>
@@ -84,41 +82,9 @@ __global__ __launch_bounds__(kKeysThreads) void k_cell_keys(
     n = ns[0];
   }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
   if (blockIdx.x == 0)
     for (int q = threadIdx.x; q < n_counters; q += blockDim.x) counters[q] = 0;
-  int id = -1;
-  if (i < n && tag_kind(tag[i]) != kDead) {
-    const double* xs[3] = {x0, x1, x2};
-    int c[3] = {0, 0, 0};
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      double q = floor(__ddiv_rn(__dsub_rn(xs[k][i], g.lo[k]), g.cs));
-      if (!(q >= 1.0 && q <= (double)(g.n[k] - 2))) {
-        bad = true;
-        q = (q >= 1.0) ? (double)(g.n[k] - 2) : 1.0;   // also catches NaN
-      }
-      c[k] = (int)q;
-    }
-    if (bad) atomicOr(flags, kFlagOutOfGrid);
-    id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
-  }
-  // runs of equal keys: the head lane reserves the run's slots
-  const int prev = __builtin_amdgcn_update_dpp(0, id, 0x138, 0xF, 0xF, false);   // wave_shr:1
-  const bool head = lane == 0 || prev != id;
-  const uint64_t heads = __ballot(head);
-  const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-  const int h = 63 - __clzll(heads & upto);
-  const uint64_t after = heads & ~upto;
-  const int next = after ? __ffsll((unsigned long long)after) - 1 : kWave;
-  int base = 0;
-  if (head && id >= 0) base = atomicAdd(&count[id], next - lane);
-  base = __shfl(base, h, kWave);
-  if (i < n) {
-    key[i] = id;
-    if (id >= 0) slot[i] = base + (lane - h);
-  }
+  cell_key_slot<DIM>(i, n, x0, x1, x2, tag, g, key, slot, count, flags);
 }
 
 // K2 (grids of at most kSegScan cells): the whole exclusive scan in one
@@ -132,8 +98,11 @@ constexpr int kSegScan = kSegWaves * kWave * kSegPer;      // 16384 cells
 
 __global__ __launch_bounds__(kSegThreads) void k_scan_seg(int32_t* __restrict__ count, int nc,
                                                          int32_t* __restrict__ cell_start,
-                                                         const int32_t* __restrict__ ns) {
+                                                         const int32_t* __restrict__ ns,
+                                                         int32_t* __restrict__ counters) {
   if (ns && ns[2]) return;
+  if (counters)   // the keys came with the post-update reduction: clear here
+    for (int q = threadIdx.x; q < 1040; q += blockDim.x) counters[q] = 0;
   __shared__ int sm[kSegWaves];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int per = (nc + kSegThreads - 1) / kSegThreads;   // <= kSegPer
@@ -189,8 +158,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __r
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t* __restrict__ part, int nb,
                                                              int32_t* __restrict__ out, int n,
-                                                             const int32_t* __restrict__ ns) {
+                                                             const int32_t* __restrict__ ns,
+                                                             int32_t* __restrict__ counters) {
   if (ns && ns[2]) return;
+  if (counters)   // the keys came with the post-update reduction: clear here
+    for (int q = threadIdx.x; q < 1040; q += blockDim.x) counters[q] = 0;
   __shared__ int sm[kScanThreads / kWave + 1];
   int base = threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -354,25 +326,30 @@ T* tp(void* p) { return static_cast<T*>(p); }
 // n_in / n_out: particles before / after the build; with ns (device
 // {n_in, n_out, skip}) they are upper bounds that size the grids.
 template <typename T, int DIM>
-hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns) {
+hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns,
+                            bool keys_done) {
   hipStream_t st = c->stream;
   Fields& F = c->F;
   Scratch& S = c->S;
   const GridDev& g = c->grid;
   const int nc = g.ncell;
   // the counts are cleared by the scan of the previous build (and at create)
-  if (n_in > 0)
+  int32_t* clear = keys_done ? S.counters : nullptr;
+  if (keys_done) {
+    // keys, slots and counts came with the post-update reduction
+  } else if (n_in > 0) {
     k_cell_keys<DIM><<<(int)((n_in + kKeysThreads - 1) / kKeysThreads), kKeysThreads, 0, st>>>(
         (int)n_in, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.tag.live(), g, S.key, S.slot,
         S.count, S.flags, S.counters, 1040, ns);
-  else
+  } else {
     k_fill_i32<<<(1040 + 255) / 256, 256, 0, st>>>(S.counters, 1040, 0);
+  }
   if (nc <= kSegScan) {
-    k_scan_seg<<<1, kSegThreads, 0, st>>>(S.count, nc, S.cell_start, ns);
+    k_scan_seg<<<1, kSegThreads, 0, st>>>(S.count, nc, S.cell_start, ns, clear);
   } else {
     int nb = (nc + kScanTile - 1) / kScanTile;
     k_scan_reduce<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, ns);
-    k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc, ns);
+    k_scan_parts<<<1, kScanThreads, 0, st>>>(S.block_sums, nb, S.cell_start, nc, ns, clear);
     k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start, 1, ns);
   }
   if (n_in > 0)
@@ -464,7 +441,7 @@ hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) 
   const int nb = (n + kScanTile - 1) / kScanTile + (n == 0);
   if (nb > kScanTile) return hipErrorInvalidValue;
   k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums, nullptr);
-  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n, nullptr);
+  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n, nullptr, nullptr);
   k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(const_cast<int32_t*>(in), n, c->S.block_sums,
                                                     out, 0, nullptr);
   return hipGetLastError();
@@ -484,12 +461,13 @@ hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst) {
   return c->P.precision == SPH_FP64 ? get_impl<double>(c, dst) : get_impl<float>(c, dst);
 }
 
-hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns) {
+hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out, const int32_t* ns,
+                              bool keys_done) {
   if (c->P.precision == SPH_FP64)
-    return c->P.dim == 2 ? build_cells_impl<double, 2>(c, n_in, n_out, ns)
-                         : build_cells_impl<double, 3>(c, n_in, n_out, ns);
-  return c->P.dim == 2 ? build_cells_impl<float, 2>(c, n_in, n_out, ns)
-                       : build_cells_impl<float, 3>(c, n_in, n_out, ns);
+    return c->P.dim == 2 ? build_cells_impl<double, 2>(c, n_in, n_out, ns, keys_done)
+                         : build_cells_impl<double, 3>(c, n_in, n_out, ns, keys_done);
+  return c->P.dim == 2 ? build_cells_impl<float, 2>(c, n_in, n_out, ns, keys_done)
+                       : build_cells_impl<float, 3>(c, n_in, n_out, ns, keys_done);
 }
 
 }  // namespace sphx

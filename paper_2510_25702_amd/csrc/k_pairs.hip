@@ -752,15 +752,23 @@ __global__ __launch_bounds__(256) void k_reduce_part(int n, const int32_t* n_ext
 // [0, 1032), flags and id in [1032, 1035), the pairs after word 1040 -- so
 // that the update needs no copy.  Plain stores: no two workgroups write one
 // word.
-template <typename T>
+// Cell keys of the updated arrays for a build launched after the
+// reduction (key == NULL: none).
+struct KeyOut {
+  const double* x[3];
+  GridDev g;
+  int32_t *key, *slot, *count;
+};
+
+template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* counters,
                                                      const T* v0, const T* v1, const T* v2,
                                                      const double* rho, const T* nut,
                                                      const uint32_t* tag, int turb,
-                                                     const uint32_t* flags,
+                                                     uint32_t* flags,
                                                      const uint64_t* next_pid, int n_alive,
                                                      int32_t* __restrict__ ns,
-                                                     int32_t* __restrict__ rb) {
+                                                     int32_t* __restrict__ rb, KeyOut ko) {
   __shared__ double sm[2][256 / kWave];
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < 1032; k += blockDim.x) rb[k] = counters[k];
@@ -779,9 +787,18 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
     }
   }
   n = min(n + counters[1024], n_max);
+  // the next build's keys, unless the injection failed (its kernels are
+  // skipped then, and the counts must stay clear)
+  const bool keys = ko.key && (*flags & kFlagCapacity) == 0;
   double a = 0.0, b = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (!is_real(tag[i])) continue;
+  // a block-uniform trip count: every lane of a wavefront takes part in the
+  // run-aggregated slot atomics of cell_key_slot
+  for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + (int)threadIdx.x;
+    if (keys)
+      cell_key_slot<DIM>(i, n, ko.x[0], ko.x[1], ko.x[2], tag, ko.g, ko.key, ko.slot, ko.count,
+                         flags);
+    if (i >= n || !is_real(tag[i])) continue;
     const double x = v0[i], y = v1[i], z = v2[i];
     double q = (x * x + y * y) + z * z;
     const double r = rho[i];
@@ -1131,17 +1148,29 @@ hipError_t prepare_pv_impl(sph_ctx* c, const sph_rates* out) {
 }
 
 template <typename T>
-hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update) {
+hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update, bool keys) {
   Fields& F = c->F;
   const int64_t n = c->n_total;
   const int64_t n_max = after_update ? std::min<int64_t>(c->cap, n + kMaxInject) : n;
   const int nb = nblk(n_max);
   if (after_update) {
     c->post_blocks = std::min(nb, kPostBlocks);
-    k_reduce_post<T><<<c->post_blocks, 256, 0, c->stream>>>(
-        (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
-        tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(), c->P.turbulence,
-        c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate, c->pinned_dev);
+    KeyOut ko;
+    for (int k = 0; k < 3; ++k) ko.x[k] = F.x[k].live();
+    ko.g = c->grid;
+    ko.key = keys ? c->S.key : nullptr;
+    ko.slot = c->S.slot;
+    ko.count = c->S.count;
+    auto go = [&](auto dimtag) {
+      constexpr int D = decltype(dimtag)::value;
+      k_reduce_post<T, D><<<c->post_blocks, 256, 0, c->stream>>>(
+          (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
+          tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(),
+          c->P.turbulence, c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate,
+          c->pinned_dev, ko);
+    };
+    if (c->P.dim == 2) go(std::integral_constant<int, 2>());
+    else go(std::integral_constant<int, 3>());
     return hipGetLastError();
   }
   k_reduce_part<T><<<nb, 256, 0, c->stream>>>((int)n, after_update ? c->S.counters + 1024 : nullptr,
@@ -1194,9 +1223,9 @@ hipError_t launch_prepare_pv(sph_ctx* c, const sph_rates* out) {
   return SPHX_DISPATCH(prepare_pv_impl, c, out);
 }
 
-hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update) {
-  return c->P.precision == SPH_FP64 ? reduce_impl<double>(c, host2, after_update)
-                                    : reduce_impl<float>(c, host2, after_update);
+hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update, bool keys) {
+  return c->P.precision == SPH_FP64 ? reduce_impl<double>(c, host2, after_update, keys)
+                                    : reduce_impl<float>(c, host2, after_update, keys);
 }
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }

@@ -369,7 +369,7 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   c->red_valid = false;
   // the reduction writes the counts, flags, next id and maxima into the
   // pinned buffer itself: the event after it is the read-back
-  HIPCHK(c, launch_reduce(c, nullptr, true), "reduce");
+  HIPCHK(c, launch_reduce(c, nullptr, true, prelaunch), "reduce");
   HIPCHK(c, hipEventRecord(c->rb_event, c->stream), "read-back event");
   const Fields saved = c->F;
   const bool nbr_saved = c->nbr_valid;
@@ -377,7 +377,7 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   if (prelaunch) {
     const int64_t n_max = std::min<int64_t>(c->cap, c->n_total + kMaxInject);
     profile_launch(c, SPH_K_CELLS);
-    e = launch_build_cells(c, n_max, n_max, c->S.nstate);
+    e = launch_build_cells(c, n_max, n_max, c->S.nstate, true);   // keys came with the reduction
     prof_end(c);
     if (e == hipSuccess) {
       profile_launch(c, SPH_K_CORRECTION);

@@ -138,13 +138,18 @@ hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src)
 hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst);
 // With ns (device {n_in, n_out, skip}, written by the post-update reduction)
 // the sizes are read on the device and n_in / n_grid are upper bounds.
+// keys_done: that reduction also computed the cell keys, slots and counts
+// (launch_reduce with keys), so the build starts at the scan.
 hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out,
-                              const int32_t* ns = nullptr);
+                              const int32_t* ns = nullptr, bool keys_done = false);
 hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_grid = 0);
 // time-step reduction (max |v|^2, max nu_t, flags) into S.red[0..2], and
 // into host memory when out_host3 is given; after_update also covers the
 // particles the last buffer update appended
-hipError_t launch_reduce(sph_ctx* c, double* out_host3, bool after_update = false);
+// keys (after_update only): also the cell keys, slots and counts of the
+// updated arrays for the next build (launch_build_cells with keys_done)
+hipError_t launch_reduce(sph_ctx* c, double* out_host3, bool after_update = false,
+                         bool keys = false);
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
                             const sph_rates* out);
 hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rates* out);

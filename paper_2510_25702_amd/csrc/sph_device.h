@@ -178,6 +178,55 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // ---------------------------------------------------------------------------
 // wave64 / block scans
 // ---------------------------------------------------------------------------
+// Cell id of slot i (FP64, floor((x - lo) / cs), IEEE division; -1 for a
+// particle tagged dead or a slot at or beyond n) and its slot inside the
+// cell.  The particles arrive (mostly) in the previous build's cell order,
+// so each run of equal ids along the wavefront takes its slots with one
+// atomic on its cell count.  Every lane of the wavefront must call this
+// with consecutive slots.
+template <int DIM>
+__device__ __forceinline__ void cell_key_slot(int i, int n, const double* __restrict__ x0,
+                                              const double* __restrict__ x1,
+                                              const double* __restrict__ x2,
+                                              const uint32_t* __restrict__ tag, const GridDev& g,
+                                              int32_t* __restrict__ key,
+                                              int32_t* __restrict__ slot, int32_t* count,
+                                              uint32_t* __restrict__ flags) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int id = -1;
+  if (i < n && tag_kind(tag[i]) != kDead) {
+    const double* xs[3] = {x0, x1, x2};
+    int c[3] = {0, 0, 0};
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      double q = floor(__ddiv_rn(__dsub_rn(xs[k][i], g.lo[k]), g.cs));
+      if (!(q >= 1.0 && q <= (double)(g.n[k] - 2))) {
+        bad = true;
+        q = (q >= 1.0) ? (double)(g.n[k] - 2) : 1.0;   // also catches NaN
+      }
+      c[k] = (int)q;
+    }
+    if (bad) atomicOr(flags, kFlagOutOfGrid);
+    id = (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
+  }
+  // runs of equal keys: the head lane reserves the run's slots
+  const int prev = __builtin_amdgcn_update_dpp(0, id, 0x138, 0xF, 0xF, false);   // wave_shr:1
+  const bool head = lane == 0 || prev != id;
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const int h = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int next = after ? __ffsll((unsigned long long)after) - 1 : kWave;
+  int base = 0;
+  if (head && id >= 0) base = atomicAdd(&count[id], next - lane);
+  base = __shfl(base, h, kWave);
+  if (i < n) {
+    key[i] = id;
+    if (id >= 0) slot[i] = base + (lane - h);
+  }
+}
+
 // Inclusive scan over the 64 lanes with DPP register moves (no LDS): a
 // Hillis-Steele scan inside each row of 16 lanes (row_shr 1, 2, 4, 8; a lane
 // with no source reads 0), then lane 15 of each row added to the next row
