@@ -1,14 +1,16 @@
 // Neighbour passes of the SPH step on gfx950 (Sec. 2.2 of the paper).
 //
 // Layout: every field is a structure-of-arrays in cell order (built by
-// k_cells.hip).  One thread owns one particle i and gathers over the
-// 3^dim cells around the cell it was sorted into; in each cell row the
-// three cells are one contiguous index range, so the j-side reads of a
-// wavefront are contiguous and shared through the vector L1 / L2.  Pair
-// arithmetic runs in T (float in FP32-mixed mode, double in FP64 mode) on
-// cell-relative positions; densities, positions and the inversion of the
-// correction matrix stay in FP64.  Every particle sums its own neighbours
-// (gather form): no floating-point atomics, results are deterministic.
+// k_cells.hip).  A team of L lanes (one to eight, by problem size) owns one
+// particle i.  The correction pass scans the 3^dim cells around i's build
+// cell (in each cell row the three cells are one contiguous index range)
+// and writes the step's neighbour list; the advection, pressure and
+// continuity passes walk that list and gather packed 16-byte records of
+// their neighbours.  Pair arithmetic runs in T (float in FP32-mixed mode,
+// double in FP64 mode) on cell-relative positions; densities, positions and
+// the inversion of the correction matrix stay in FP64.  Every particle sums
+// its own neighbours (gather form) and the team reduces in a fixed order:
+// no floating-point atomics, results are deterministic.
 #include "sph_pairs.h"
 
 namespace sphx {

@@ -1,6 +1,7 @@
 // Neighbour-pass building blocks shared by the forward passes (k_pairs.hip)
-// and their adjoints (k_adjoint.hip): the cell-stencil neighbour loop with
-// teams of lanes per particle, team reductions, the sharded pair counter,
+// and their adjoints (k_adjoint.hip): the cell-stencil neighbour loop and
+// the list walks over packed records with teams of lanes per particle, the
+// list build of the correction, team reductions, the sharded pair counter,
 // small symmetric-matrix helpers, the equation of state and the guarded
 // inverse of the correction moment.
 #pragma once
