@@ -216,6 +216,43 @@ def run_gpu(case, precision, steps, warmup, torch):
                 n_ac=n_ac, stats=stats, sim=g)
 
 
+def fp32_error(r32, case):
+    """Stated error of the FP32-mixed path: its pair operators (pressure and
+    viscous accelerations, continuity rate, B, p; with turbulence also the
+    velocity gradient and the k, epsilon rates) against the FP64 path's on
+    one state, the one the timed FP32-mixed run ended in; normwise relative
+    differences, matched by particle id.  The FP64 path matches the FP64
+    oracle to 1e-12 in the parity tests."""
+    import dataclasses
+    import numpy as np
+    from paper_2510_25702_amd import sph
+    g = r32["sim"]
+    st = g.state()
+    step, t, npid = sph.sph_get_clock(g.ctx)
+    c = dataclasses.replace(case, x=st["x"], v=st["v"], rho=st["rho"], drho=st["drho"],
+                            k=st["k"], eps=st["eps"], tag=st["tag"], pid=st["pid"],
+                            npid=int(npid), step=int(step), t=float(t))
+    fields = ("ap", "anu", "drho", "B", "p")
+    if case.params["turbulence"]:
+        fields += ("gradv", "dk", "deps")
+    res = {}
+    for prec in (sph.SPH_FP64, sph.SPH_FP32_MIXED):
+        s = sph.Simulation(c, precision=prec)
+        s.build_cells()
+        s.correction()
+        r = s.rates()
+        order = np.argsort(s.state()["pid"])
+        res[prec] = {f: np.asarray(r[f])[order] for f in fields}
+        del s
+    out = {"state": f"end of the timed FP32-mixed run (step {step})",
+           "norm": "max |FP32-mixed - FP64| / max |FP64| per operator"}
+    for f in fields:
+        a, b = res[sph.SPH_FP32_MIXED][f], res[sph.SPH_FP64][f]
+        den = float(np.abs(b).max())
+        out[f] = float(f"{np.abs(a - b).max() / den:.3g}") if den > 0 else 0.0
+    return out
+
+
 def roofline(stats):
     dom = max(("pressure", "density", "advection", "correction", "cells"),
               key=lambda k: stats[k].total_ms)
@@ -413,6 +450,7 @@ def main():
                        "pairs_per_s": round(r64["pairs"] / r64["seconds"], 1),
                        "roofline": roof64}
         out["fp32_over_fp64"] = round(value / v64, 3)
+    out["fp32_error_vs_fp64"] = fp32_error(r32, case)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_checkpoint, torch)
     if not args.no_cpu:
