@@ -229,11 +229,15 @@ def test_one_step_every_launch(sph, ora, monkeypatch, launch, pname, prec, tol):
     assert np.abs(sg["rho"][idx] - so["rho"]).max() < tol
 
 
-@pytest.mark.parametrize("name", ["uchannel", "jet_full"])
+FULL_SIZE = {"uchannel": cases.make_uchannel, "jet_full": cases.make_jet,
+             "adjoint_channel": cases.make_adjoint_channel}
+
+
+@pytest.mark.parametrize("name", list(FULL_SIZE))
 @pytest.mark.parametrize("pname,prec,tol", PREC)
 def test_pair_operators_full_size(sph, ora, name, pname, prec, tol):
     # the benchmark's workload sizes, in the launch configuration it times
-    c = cases.make_uchannel() if name == "uchannel" else cases.make_jet()
+    c = FULL_SIZE[name]()
     c = relabelled(ora, cases.perturbed_state(c, seed=9))
     ref = ora.OracleSim(c, threads=16)
     ro = ref.rates()
