@@ -292,27 +292,31 @@ __device__ __forceinline__ double rv(const V4<double>* q, int k) {
 // The pairs of adj_neighbors over packed records (positions in the first
 // DIM values): the NR vectors of every candidate of a batch are loaded
 // before its tests; fn(j, r, r2, q) with q the records of j.
+#ifndef SPHX_ADJ_UNROLL
+#define SPHX_ADJ_UNROLL 2
+#endif
 template <int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void adj_neighbors_rec(const AdjDev& A, const V4<double>* const* rec,
                                                   int i, int lane, const double xi[3], Fn&& fn) {
+  constexpr int U = SPHX_ADJ_UNROLL;
   if (A.nbr && !(A.stale[0] | A.stale[1])) {
     const int cnt = A.ncnt[i];
-    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
-      uint32_t e[kUnroll];
+    for (int kb = lane; kb < cnt; kb += U * L) {
+      uint32_t e[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int k = kb + u * L;
         e[u] = A.nbr[(int64_t)(k < cnt ? k : kb) * A.cap + i];
       }
-      V4<double> q[kUnroll][NR];
+      V4<double> q[U][NR];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int j = (int)(e[u] & kNbrIdxMask);
 #pragma unroll
         for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         if (kb + u * L >= cnt) break;
         const int j = (int)(e[u] & kNbrIdxMask);
         const int code = (int)(e[u] >> kNbrIdxBits);
