@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device 5 times (HBM counter "
                          "calibration under rocprofv3) and exit")
+    ap.add_argument("--obc-ablation", action="store_true",
+                    help="only run the open-boundary ablation of Table 2 (Cases 1-4) on the "
+                         "laminar channel and print its JSON line")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-checkpoint", type=int, default=10)
     ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
@@ -214,6 +217,71 @@ def run_gpu(case, precision, steps, warmup, torch):
     dt = t1 - t0
     return dict(seconds=dt, particle_steps=real_steps, n_real=n_real0, pairs=pairs,
                 n_ac=n_ac, stats=stats, sim=g)
+
+
+def obc_ablation(steps=3000, navg=1000, precision=0):
+    """The open-boundary ablation of Table 2 (Cases 1-4 = obc_mode 1-4) on a
+    laminar straight channel with the paper's ratios: 20 particles across,
+    Re = 50 on the bulk velocity, parabolic inlet, outlet pressure equal to
+    the channel's Poiseuille pressure drop (the paper: 0.1 and 0.1), started
+    from the developed state.  Over the last `navg` steps (every fifth) it
+    averages the centre-line pressure, fitted over the interior (slope and
+    inlet value against the Poiseuille ones) and the velocity profile of the
+    last H before the outlet buffer (normwise L2 against the parabola)."""
+    import numpy as np
+    import cases
+    from paper_2510_25702_amd import sph
+    H, L, dp, Re, Um, c0 = 1.0, 6.0, 0.05, 50.0, 1.0, 10.0
+    nu = (2.0 / 3.0) * Um * H / Re
+    grad = 8.0 * nu * Um / H ** 2            # -dp/dx of the Poiseuille flow, rho0 = 1
+    p_out = grad * L
+    out = {"setup": f"{L}Hx{H} channel, dp = H/{round(H / dp)}, Re {Re:g}, c0 = {c0:g} U_max, "
+                    f"p_out = {p_out:.3f} = the Poiseuille drop, {steps} steps, mean of the "
+                    f"last {navg}", "p_inlet_theory": p_out + grad * L, "slope_theory": -grad}
+    for mode in (1, 2, 3, 4):
+        c = cases.make_channel(H=H, L=L, dp=dp, Re=Re, Umax=Um, c0=c0, ramp_time=0.0,
+                               p_out=p_out, obc_mode=mode)
+        fl = (c.tag & 3) != cases.WALL
+        y = c.x[:, 1]
+        c.v = c.v.copy()
+        c.v[fl, 0] = 4 * Um * (y[fl] / H) * (1 - y[fl] / H)
+        c.rho = c.rho.copy()
+        c.rho[fl] = 1.0 + (p_out + grad * (L - c.x[fl, 0])) / c0 ** 2
+        g = sph.Simulation(c, precision=precision)
+        g.build_cells()
+        g.buffer_update()
+        nb, nx = int(round(H / dp)), int(round(L / (2 * dp)))
+        au, nu_, ap, np_ = np.zeros(nb), np.zeros(nb), np.zeros(nx), np.zeros(nx)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            g.advance()
+            if k < steps - navg or k % 5:
+                continue
+            st = g.state()
+            x, v = st["x"], st["v"]
+            real = (st["tag"] & 3) <= 1
+            p = c0 ** 2 * (st["rho"] - 1.0)
+            sel = real & (x[:, 0] > L - 4 * dp - H) & (x[:, 0] < L - 4 * dp - 0.5 * H)
+            b = np.clip((x[sel, 1] / dp).astype(int), 0, nb - 1)
+            np.add.at(au, b, v[sel, 0])
+            np.add.at(nu_, b, 1)
+            sel = real & (np.abs(x[:, 1] - H / 2) < 2 * dp)
+            b = np.clip((x[sel, 0] / (2 * dp)).astype(int), 0, nx - 1)
+            np.add.at(ap, b, p[sel])
+            np.add.at(np_, b, 1)
+        secs = time.perf_counter() - t0
+        u = au / np.maximum(nu_, 1)
+        yy = (np.arange(nb) + 0.5) * dp
+        ua = 4 * Um * yy * (1 - yy)
+        xc = (np.arange(nx) + 0.5) * 2 * dp
+        m = (np_ > 0) & (xc > 4 * dp + 0.5) & (xc < L - 4 * dp - 0.5)
+        slope, icpt = np.polyfit(xc[m], (ap / np.maximum(np_, 1))[m], 1)
+        out[f"case{mode}"] = {
+            "slope_rel_err": round(float(slope / -grad - 1.0), 4),
+            "p_inlet_rel_err": round(float(icpt / (p_out + grad * L) - 1.0), 4),
+            "outlet_u_L2": round(float(np.sqrt(np.mean((u - ua) ** 2) / np.mean(ua ** 2))), 4),
+            "seconds": round(secs, 2)}
+    return out
 
 
 def fp32_error(r32, case):
@@ -406,6 +474,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n, "copies": 5}), flush=True)
+        return
+    if args.obc_ablation:
+        print(json.dumps({"obc_ablation": obc_ablation(steps=6000, navg=2000)}), flush=True)
         return
     from paper_2510_25702_amd import sph
     case = make_case(args.workload)

@@ -174,7 +174,7 @@ def _frame2(nx, ny):
 # ----------------------------------------------------------------------------
 def make_channel(H=1.0, L=10.0, dp=None, Re=100.0, Umax=1.0, c0=10.0,
                  steps=200, profile=PROFILE_PARABOLIC, coef=(), obc_mode=4,
-                 name="channel", seed=0, ramp_time=10.0):
+                 name="channel", seed=0, ramp_time=10.0, p_out=0.0):
     dp = H / 20 if dp is None else dp
     nu = (2.0 / 3.0) * Umax * H / Re          # Re on the bulk velocity
     P = base_params(2, dp, c0=c0, nu_l=nu, u_ref=Umax, obc_mode=obc_mode,
@@ -190,7 +190,7 @@ def make_channel(H=1.0, L=10.0, dp=None, Re=100.0, Umax=1.0, c0=10.0,
                    ramp_time=ramp_time)
     outlet = Buffer(2, (L, H / 2, 0.0), _frame2(-1.0, 0.0), Lb, (H / 2, 0.0),
                     0.5 * dp, vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED,
-                    p_ob=0.0)
+                    p_ob=p_out)
     # the outlet frame's transverse axis is -y; the profile is symmetric
     return _assemble(name, P, [inlet, outlet], fluid, wall, steps,
                      note=f"{L}Hx{H} channel dp={dp} Re={Re}")
