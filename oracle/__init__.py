@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("cfl_adv", C.c_double), ("cfl_ac", C.c_double),
                 ("u_ref", C.c_double), ("cell_size", C.c_double),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("tvf_alpha", C.c_double)]
 
 
 class BufferDesc(C.Structure):
@@ -69,7 +69,7 @@ class StateC(C.Structure):
 
 class RatesC(C.Structure):
     _fields_ = [(nm, C.POINTER(C.c_double)) for nm in
-                ("p", "vol", "ap", "drho", "anu", "gradv", "dk", "deps")]
+                ("p", "vol", "ap", "drho", "anu", "gradv", "dk", "deps", "shift")]
 
 
 class StepInfo(C.Structure):
@@ -151,7 +151,7 @@ def make_params(p: dict) -> Params:
     for name, _ in Params._fields_:
         if name == "pad0":
             continue
-        val = p[name]
+        val = p.get(name, 0.0) if name == "tvf_alpha" else p[name]
         if name in ("g", "lo", "hi"):
             for k in range(3):
                 getattr(P, name)[k] = float(val[k])
@@ -275,9 +275,10 @@ class OracleSim:
                     Bm[:, 8] = 0.0
         out = dict(p=np.zeros(n), vol=np.zeros(n), ap=np.zeros((n, 3)),
                    drho=np.zeros(n), anu=np.zeros((n, 3)),
-                   gradv=np.zeros((n, 9)), dk=np.zeros(n), deps=np.zeros(n))
+                   gradv=np.zeros((n, 9)), dk=np.zeros(n), deps=np.zeros(n),
+                   shift=np.zeros((n, 3)))
         R = RatesC(*[_ptr(out[f]) for f in ("p", "vol", "ap", "drho", "anu",
-                                            "gradv", "dk", "deps")])
+                                            "gradv", "dk", "deps", "shift")])
         err = lib().ora_rates_eval(C.byref(self.P), self.B, self.nbuf,
                                    C.byref(self.S), _ptr(np.ascontiguousarray(Bm)),
                                    C.byref(R))

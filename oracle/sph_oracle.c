@@ -653,6 +653,43 @@ static int pass_viscous(const pass_t* T, double* anu, int64_t* npairs) {
   return err;
 }
 
+/* Transport-velocity shift (Sec. 2.3 names the transport-velocity
+ * formulation for particle regularity and cites it without a formula; this
+ * is the standard position-correction form, stated here):
+ *   dx_i = -alpha h^2 sum_j 2 V_j grad_i W_ij
+ * over every neighbour j (fluid, buffer, wall) of a FLUID particle i; zero
+ * for buffer and wall particles.  The sum vanishes on a uniform lattice and
+ * points from i towards denser neighbours, so dx_i moves particles towards
+ * emptier space.  It is evaluated on the start-of-step configuration and
+ * added to the position at the end of the advection step: over the step the
+ * particle travels with v + dx / dt_adv. */
+static int pass_shift(const pass_t* T, double* dx) {
+  const ora_params* P = T->P;
+  int dim = P->dim;
+  double h = P->h, rc2 = cutoff2(P);
+  double c = -P->tvf_alpha * h * h;
+  int err = ORA_OK;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads)
+  for (int64_t i = 0; i < T->S->n; ++i) {
+    int64_t nb[MAXNB];
+    double s3[3] = {0, 0, 0};
+    dx[3 * i] = dx[3 * i + 1] = dx[3 * i + 2] = 0.0;
+    if (KIND(T->S->tag[i]) != ORA_FLUID) continue;
+    int m = neighbors_of(T->g, T->x, i, rc2, nb);
+    if (m < 0) { err = ORA_E_NUMERIC; continue; }
+    const double* xi = T->x + 3 * i;
+    for (int a = 0; a < m; ++a) {
+      int64_t j = nb[a];
+      double r[3] = {xi[0] - T->x[3 * j], xi[1] - T->x[3 * j + 1], xi[2] - T->x[3 * j + 2]};
+      double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+      double f = kernel_dW_over_r(sqrt(r2), h, dim);   /* grad_i W_ij = f r_ij */
+      for (int k = 0; k < dim; ++k) s3[k] += 2.0 * T->vol[j] * f * r[k];
+    }
+    for (int k = 0; k < dim; ++k) dx[3 * i + k] = c * s3[k];
+  }
+  return err;
+}
+
 /* Velocity gradient, Eq. (velo-grad-equ), and the k-epsilon rates,
  * Eqs. (k-discretized-equ), (epsilon-discretized-equ) with
  * G_k = tau_t : grad v, tau_t = nu_t (grad v + grad v^T) - 2k I / 3. */
@@ -729,6 +766,7 @@ int ora_rates_eval(const ora_params* P, const ora_buffer* B, int nbuf,
   if (R->anu) err |= pass_viscous(&T, R->anu, NULL);
   if (P->turbulence && R->gradv && R->dk && R->deps)
     err |= pass_turbulence(&T, R->gradv, R->dk, R->deps);
+  if (R->shift) err |= pass_shift(&T, R->shift);
   grid_free(&g);
   return err;
 }
@@ -818,7 +856,9 @@ static double rho_of_p(const ora_params* P, double p) {
 /* One advection step of the dual-criteria scheme (Sec. 2.3; reading):       */
 /* B, viscous force and RANS at the start-of-step state, then n_ac acoustic  */
 /* kick-drift-kick sub-steps (half density update, pressure kick with the    */
-/* velocity boundary condition, drift, continuity, half density update).     */
+/* velocity boundary condition, drift, continuity, half density update);     */
+/* with tvf_alpha != 0 the transport-velocity shift of the start-of-step     */
+/* state is added to the positions at the end.                               */
 /* ------------------------------------------------------------------------ */
 int ora_advection_step(const ora_params* P, const ora_buffer* B, int nbuf,
                        ora_state* S, double dt_adv_fixed, int n_ac_fixed,
@@ -834,6 +874,7 @@ int ora_advection_step(const ora_params* P, const ora_buffer* B, int nbuf,
   double* gradv = (double*)malloc(sizeof(double) * 9 * sz);
   double* dk = (double*)malloc(sizeof(double) * sz);
   double* de = (double*)malloc(sizeof(double) * sz);
+  double* dx = P->tvf_alpha != 0.0 ? (double*)malloc(sizeof(double) * 3 * sz) : NULL;
   int err = ORA_OK;
   int64_t pairs = 0;
   grid_t g;
@@ -870,6 +911,7 @@ int ora_advection_step(const ora_params* P, const ora_buffer* B, int nbuf,
   }
   pass_t T = {P, B, nbuf, S, &g, S->rho, p, vol, Bmat, S->x, S->v, S->t};
   err |= pass_viscous(&T, anu, &pairs);
+  if (dx) err |= pass_shift(&T, dx);
   if (P->turbulence) {
     err |= pass_turbulence(&T, gradv, dk, de);
     for (int64_t i = 0; i < n; ++i) {
@@ -923,6 +965,9 @@ int ora_advection_step(const ora_params* P, const ora_buffer* B, int nbuf,
       S->rho[i] = S->rho[i] + 0.5 * dt * S->drho[i];
     }
   }
+  if (dx)   /* the transport-velocity shift of the start-of-step state */
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < dim; ++k) S->x[3 * i + k] += dx[3 * i + k];
   S->step += 1;
   S->t += info.dt_adv;
 
@@ -930,6 +975,7 @@ done:
   info.n_pairs = pairs;
   if (I) *I = info;
   free(Bmat); free(vol); free(p); free(ap); free(anu); free(gradv); free(dk); free(de);
+  free(dx);
   return err;
 }
 

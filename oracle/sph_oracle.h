@@ -43,6 +43,7 @@ typedef struct {
   double cell_size;
   double lo[3], hi[3];
   uint64_t seed;
+  double tvf_alpha;       /* transport-velocity shift coefficient; 0 = off */
 } ora_params;
 
 typedef struct {
@@ -75,6 +76,7 @@ typedef struct {
   double *anu;            /* [n][3] viscous acceleration */
   double *gradv;          /* [n][9] velocity gradient (turbulent only) */
   double *dk, *deps;      /* [n] k / epsilon rates (turbulent only) */
+  double *shift;          /* [n][3] transport-velocity shift (NULL: skipped) */
 } ora_rates;
 
 typedef struct {
