@@ -657,8 +657,10 @@ static int pass_viscous(const pass_t* T, double* anu, int64_t* npairs) {
  * formulation for particle regularity and cites it without a formula; this
  * is the standard position-correction form, stated here):
  *   dx_i = -alpha h^2 sum_j 2 V_j grad_i W_ij
- * over every neighbour j (fluid, buffer, wall) of a FLUID particle i; zero
- * for buffer and wall particles.  The sum vanishes on a uniform lattice and
+ * over every neighbour j (fluid, buffer, wall) of a particle i that moves
+ * with the flow: a FLUID particle, or a BUFFER particle of a buffer whose
+ * velocity is extrapolated from the fluid (Table 3); zero for particles of
+ * prescribed-velocity buffers and for walls.  The sum vanishes on a uniform lattice and
  * points from i towards denser neighbours, so dx_i moves particles towards
  * emptier space.  It is evaluated on the start-of-step configuration and
  * added to the position at the end of the advection step: over the step the
@@ -674,7 +676,13 @@ static int pass_shift(const pass_t* T, double* dx) {
     int64_t nb[MAXNB];
     double s3[3] = {0, 0, 0};
     dx[3 * i] = dx[3 * i + 1] = dx[3 * i + 2] = 0.0;
-    if (KIND(T->S->tag[i]) != ORA_FLUID) continue;
+    uint32_t ti = T->S->tag[i];
+    if (KIND(ti) == ORA_BUFFER) {
+      const ora_buffer* b = find_buffer(T->B, T->nbuf, BID(ti));
+      if (!b || b->vel_mode != ORA_VEL_EXTRAPOLATE) continue;
+    } else if (KIND(ti) != ORA_FLUID) {
+      continue;
+    }
     int m = neighbors_of(T->g, T->x, i, rc2, nb);
     if (m < 0) { err = ORA_E_NUMERIC; continue; }
     const double* xi = T->x + 3 * i;

@@ -2,9 +2,10 @@
 
 The paper uses the transport-velocity formulation for particle regularity
 (Sec. 2.3) and cites it without a formula; the oracle states the standard
-position-correction form dx_i = -alpha h^2 sum_j 2 V_j grad_i W_ij for fluid
-particles, evaluated on the start-of-step state and added to the positions
-at the end of the advection step.  The expected values below come from
+position-correction form dx_i = -alpha h^2 sum_j 2 V_j grad_i W_ij for the
+particles that move with the flow (fluid, and buffer particles of buffers
+that extrapolate their velocity), evaluated on the start-of-step state and
+added to the positions at the end of the advection step.  The expected values below come from
 symmetry, antisymmetry of the kernel gradient, the divergence theorem in
 the continuum limit, and the structure of the step, not from the oracle.
 """
@@ -108,10 +109,18 @@ def test_shift_at_a_lattice_edge_matches_the_divergence_theorem(ora):
     assert np.abs(got[:, 1] / expect - 1.0).max() < 0.03
 
 
-def test_step_adds_the_start_of_step_shift_to_fluid_positions_only(ora):
+def test_step_adds_the_start_of_step_shift_to_flow_particles_only(ora):
     # With the shift on, the step differs from the plain step only in the
-    # positions of fluid particles, by exactly the shift of the start state.
-    c = cases.make_channel(H=0.5, L=1.5, dp=0.05, Re=50.0, Umax=1.0)
+    # positions of fluid particles and of the outlet buffer's (extrapolated
+    # velocity), by exactly the shift of the start state; the inlet buffer's
+    # particles (prescribed velocity) and the walls do not move by it.
+    c0 = cases.make_channel(H=0.5, L=1.5, dp=0.05, Re=50.0, Umax=1.0)
+    s0 = ora.OracleSim(c0, threads=4)
+    s0.buffer_update()
+    sn = s0.snapshot()
+    c = dataclasses.replace(c0, **{f: sn[f] for f in ("x", "v", "rho", "drho", "k", "eps",
+                                                        "tag", "pid")},
+                            npid=int(s0.S.next_pid))
     plain = ora.OracleSim(c, threads=4)
     tvf = ora.OracleSim(_tvf(c), threads=4)
     dx = tvf.rates()["shift"]
@@ -119,8 +128,11 @@ def test_step_adds_the_start_of_step_shift_to_fluid_positions_only(ora):
     plain.step(I.dt_adv, I.n_ac)
     tvf.step(I.dt_adv, I.n_ac)
     a, b = plain.snapshot(), tvf.snapshot()
-    fluid = (c.tag & 3) == 0
-    assert fluid.sum() > 0 and (~fluid).sum() > 0
+    kind, bid = c.tag & 3, (c.tag >> 8) & 0xFF
+    outlet = [q.id for q in c.buffers if q.vel_mode == cases.VEL_EXTRAPOLATE]
+    fluid = (kind == 0) | ((kind == 1) & np.isin(bid, outlet))
+    assert (kind == 1).sum() > 0 and ((kind == 1) & ~fluid).sum() > 0
+    assert ((kind == 1) & fluid).sum() > 0 and (kind == 2).sum() > 0
     for f in ("v", "rho", "drho", "tag", "pid"):
         assert np.array_equal(a[f], b[f]), f
     assert np.array_equal(a["x"][~fluid], b["x"][~fluid])
