@@ -660,7 +660,11 @@ static int pass_viscous(const pass_t* T, double* anu, int64_t* npairs) {
  * over every neighbour j (fluid, buffer, wall) of a particle i that moves
  * with the flow: a FLUID particle, or a BUFFER particle of a buffer whose
  * velocity is extrapolated from the fluid (Table 3); zero for particles of
- * prescribed-velocity buffers and for walls.  The sum vanishes on a uniform lattice and
+ * prescribed-velocity buffers and for walls.  A buffer particle keeps only
+ * the component tangential to its buffer's open face (normal n_b removed):
+ * its support is cut at the face, where the sum would push it out, and its
+ * motion across the face, which decides deletion and injection, is the
+ * buffer's own.  The sum vanishes on a uniform lattice and
  * points from i towards denser neighbours, so dx_i moves particles towards
  * emptier space.  It is evaluated on the start-of-step configuration and
  * added to the position at the end of the advection step: over the step the
@@ -677,8 +681,9 @@ static int pass_shift(const pass_t* T, double* dx) {
     double s3[3] = {0, 0, 0};
     dx[3 * i] = dx[3 * i + 1] = dx[3 * i + 2] = 0.0;
     uint32_t ti = T->S->tag[i];
+    const ora_buffer* b = NULL;
     if (KIND(ti) == ORA_BUFFER) {
-      const ora_buffer* b = find_buffer(T->B, T->nbuf, BID(ti));
+      b = find_buffer(T->B, T->nbuf, BID(ti));
       if (!b || b->vel_mode != ORA_VEL_EXTRAPOLATE) continue;
     } else if (KIND(ti) != ORA_FLUID) {
       continue;
@@ -694,6 +699,11 @@ static int pass_shift(const pass_t* T, double* dx) {
       for (int k = 0; k < dim; ++k) s3[k] += 2.0 * T->vol[j] * f * r[k];
     }
     for (int k = 0; k < dim; ++k) dx[3 * i + k] = c * s3[k];
+    if (b) {   /* tangential part only: dx - (dx . n_b) n_b */
+      const double* nb_ = b->frame;
+      double dn = (dx[3 * i] * nb_[0] + dx[3 * i + 1] * nb_[1]) + dx[3 * i + 2] * nb_[2];
+      for (int k = 0; k < dim; ++k) dx[3 * i + k] -= dn * nb_[k];
+    }
   }
   return err;
 }

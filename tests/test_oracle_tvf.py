@@ -139,3 +139,11 @@ def test_step_adds_the_start_of_step_shift_to_flow_particles_only(ora):
     assert np.abs(dx[~fluid]).max() == 0.0
     assert np.abs(dx[fluid]).max() > 0
     assert np.abs((b["x"] - a["x"]) - dx)[fluid].max() < 1e-15
+    # outlet-buffer particles move only along the open face (normal removed)
+    for q in c.buffers:
+        if q.vel_mode != cases.VEL_EXTRAPOLATE:
+            continue
+        sel = (kind == 1) & (bid == q.id)
+        n = np.array(q.frame[0])
+        assert np.abs(dx[sel] @ n).max() < 1e-18
+        assert np.abs(dx[sel]).max() > 0
