@@ -664,7 +664,9 @@ static int pass_viscous(const pass_t* T, double* anu, int64_t* npairs) {
  * the component tangential to its buffer's open face (normal n_b removed):
  * its support is cut at the face, where the sum would push it out, and its
  * motion across the face, which decides deletion and injection, is the
- * buffer's own.  The sum vanishes on a uniform lattice and
+ * buffer's own; within 2h of the ends of the box's transverse extent (a
+ * corner of the domain, where the support is cut along the face too) it
+ * gets none.  The sum vanishes on a uniform lattice and
  * points from i towards denser neighbours, so dx_i moves particles towards
  * emptier space.  It is evaluated on the start-of-step configuration and
  * added to the position at the end of the advection step: over the step the
@@ -699,10 +701,14 @@ static int pass_shift(const pass_t* T, double* dx) {
       for (int k = 0; k < dim; ++k) s3[k] += 2.0 * T->vol[j] * f * r[k];
     }
     for (int k = 0; k < dim; ++k) dx[3 * i + k] = c * s3[k];
-    if (b) {   /* tangential part only: dx - (dx . n_b) n_b */
+    if (b) {   /* tangential part only: dx - (dx . n_b) n_b; none near the ends */
+      double y[3];
+      to_local(b, xi, y);
+      int end = fabs(y[1]) > b->half_width[0] - 2.0 * h ||
+                (dim == 3 && fabs(y[2]) > b->half_width[1] - 2.0 * h);
       const double* nb_ = b->frame;
       double dn = (dx[3 * i] * nb_[0] + dx[3 * i + 1] * nb_[1]) + dx[3 * i + 2] * nb_[2];
-      for (int k = 0; k < dim; ++k) dx[3 * i + k] -= dn * nb_[k];
+      for (int k = 0; k < dim; ++k) dx[3 * i + k] = end ? 0.0 : dx[3 * i + k] - dn * nb_[k];
     }
   }
   return err;

@@ -147,3 +147,7 @@ def test_step_adds_the_start_of_step_shift_to_flow_particles_only(ora):
         n = np.array(q.frame[0])
         assert np.abs(dx[sel] @ n).max() < 1e-18
         assert np.abs(dx[sel]).max() > 0
+        # none within 2h of the ends of the transverse extent
+        y1 = (c.x - np.array(q.origin)) @ np.array(q.frame[1])
+        ends = sel & (np.abs(y1) > q.half_width[0] - 2 * c.params["h"])
+        assert ends.sum() > 0 and np.abs(dx[ends]).max() == 0.0
