@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device 5 times (HBM counter "
                          "calibration under rocprofv3) and exit")
+    ap.add_argument("--laminar-jet", action="store_true",
+                    help="laminar plane jet (Re 40) against the closed-form jet; prints one JSON line")
     ap.add_argument("--obc-ablation", action="store_true",
                     help="only run the open-boundary ablation of Table 2 (Cases 1-4) on the "
                          "laminar channel and print its JSON line")
@@ -284,6 +286,88 @@ def obc_ablation(steps=3000, navg=1000, precision=0):
     return out
 
 
+def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
+    """The laminar plane jet of Sec. 4.3 (Re 40, slot D = 2, 40 D x 40 D, nf
+    particles across the slot, six buffers of Table 3, transport-velocity
+    shift on) against the closed-form plane laminar jet: centre-line speed
+    u_c = 0.4543 (K^2 / (nu x))^(1/3) and half-width b = 3.2028 (nu^2 / K)^(1/3)
+    x^(2/3) (u = u_c sech^2(0.8814 y / b)), K = U^2 D the momentum flux of the
+    slot, x from a virtual origin.  The virtual origin is not fixed, so the
+    checks are on slopes: u_c^-3 and b^(3/2) are linear in x with the stated
+    slopes, and the profiles u / u_c against y / b collapse onto sech^2.
+    Means over the last `navg` steps (every tenth), stations every D from
+    10 D to 32 D."""
+    import numpy as np
+    import cases
+    from paper_2510_25702_amd import sph
+    c = cases.make_laminar_jet(nf=nf)
+    D, U, Re = 2.0, 1.0, 40.0
+    nu, K, dp, W = U * D / Re, U * U * D, D / nf, 40.0
+    g = sph.Simulation(c, precision=precision)
+    g.build_cells()
+    g.buffer_update()
+    xs = np.arange(10, 33) * D
+    ny = int(round(2 * W / dp))
+    acc, cnt = np.zeros((len(xs), ny)), np.zeros((len(xs), ny))
+    t0 = time.perf_counter()
+    for k in range(steps):
+        g.advance()
+        if (k + 1) % 4000 == 0:
+            print(f"laminar jet: step {k + 1} of {steps}", file=sys.stderr, flush=True)
+        if k < steps - navg or k % 10:
+            continue
+        st = g.state()
+        x, v = st["x"], st["v"]
+        real = (st["tag"] & 3) <= 1
+        for q, x0 in enumerate(xs):
+            sel = real & (np.abs(x[:, 0] - x0) < dp)
+            b = np.clip(((x[sel, 1] + W) / dp).astype(int), 0, ny - 1)
+            np.add.at(acc[q], b, v[sel, 0])
+            np.add.at(cnt[q], b, 1)
+    secs = time.perf_counter() - t0
+    u = acc / np.maximum(cnt, 1)
+    yc = -W + (np.arange(ny) + 0.5) * dp
+    uc = u[:, np.abs(yc) < dp].mean(axis=1)
+    half = []
+    for q in range(len(xs)):
+        prof, up = u[q], yc > 0
+        above = np.where(up & (prof < 0.5 * uc[q]))[0]
+        j = above[0]                     # first bin above the centre line below u_c / 2
+        y0, y1, f0, f1 = yc[j - 1], yc[j], prof[j - 1], prof[j]
+        bp = y0 + (0.5 * uc[q] - f0) * (y1 - y0) / (f1 - f0)
+        below = np.where(~up & (prof < 0.5 * uc[q]))[0]
+        j = below[-1]
+        y0, y1, f0, f1 = yc[j], yc[j + 1], prof[j], prof[j + 1]
+        bm = y0 + (0.5 * uc[q] - f0) * (y1 - y0) / (f1 - f0)
+        half.append(0.5 * (bp - bm))
+    half = np.array(half)
+    s_u, i_u = np.polyfit(xs, uc ** -3, 1)
+    s_b, i_b = np.polyfit(xs, half ** 1.5, 1)
+    th_u = nu / (0.4543 ** 3 * K * K)
+    th_b = (3.2028 * (nu * nu / K) ** (1.0 / 3.0)) ** 1.5
+    eta = yc[None, :] / half[:, None]
+    m = np.abs(eta) < 2.5
+    coll = u / uc[:, None]
+    prof = 1.0 / np.cosh(0.8814 * eta) ** 2
+    l2 = float(np.sqrt(np.mean((coll - prof)[m] ** 2) / np.mean(prof[m] ** 2)))
+    mom = (u ** 2).sum(axis=1) * dp
+    return {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
+                     f"tvf_alpha {c.params['tvf_alpha']}, {steps} steps (t = "
+                     f"{sph.sph_get_clock(g.ctx)[1]:.0f}), mean of the last {navg}",
+            "uc_m3_slope_rel_err": round(float(s_u / th_u - 1.0), 4),
+            "uc_m3_corr": round(float(np.corrcoef(xs, uc ** -3)[0, 1]), 5),
+            "uc_virtual_origin": round(float(-i_u / s_u), 2),
+            "b_1p5_slope_rel_err": round(float(s_b / th_b - 1.0), 4),
+            "b_1p5_corr": round(float(np.corrcoef(xs, half ** 1.5)[0, 1]), 5),
+            "b_virtual_origin": round(float(-i_b / s_b), 2),
+            "profile_collapse_L2": round(l2, 4),
+            "momentum_flux_over_K": [round(float(mom[0] / K), 3), round(float(mom[-1] / K), 3)],
+            "uc": [round(float(a), 4) for a in uc[::4]],
+            "b": [round(float(a), 3) for a in half[::4]],
+            "x": [float(a) for a in xs[::4]],
+            "seconds": round(secs, 1)}
+
+
 def fp32_error(r32, case):
     """Stated error of the FP32-mixed path: its pair operators (pressure and
     viscous accelerations, continuity rate, B, p; with turbulence also the
@@ -474,6 +558,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n, "copies": 5}), flush=True)
+        return
+    if args.laminar_jet:
+        print(json.dumps({"laminar_jet": laminar_jet()}), flush=True)
         return
     if args.obc_ablation:
         print(json.dumps({"obc_ablation": obc_ablation(steps=6000, navg=2000)}), flush=True)

@@ -141,7 +141,7 @@ def lattice2(x0, x1, y0, y1, dp):
 
 
 def _assemble(name, params, buffers, fluid, wall, steps, *, v=None, k0=0.0,
-              eps0=0.0, note=""):
+              eps0=0.0, note="", pad_cells=3):
     nf, nw = fluid.shape[0], wall.shape[0]
     x = np.concatenate([fluid, wall]).astype(np.float64)
     n = nf + nw
@@ -157,7 +157,7 @@ def _assemble(name, params, buffers, fluid, wall, steps, *, v=None, k0=0.0,
     tag = np.zeros(n, dtype=np.uint32)
     tag[nf:] = WALL
     pid = np.arange(n, dtype=np.uint32)
-    _set_bounds(params, x)
+    _set_bounds(params, x, pad_cells)
     return Case(name, params, buffers, x, vel, rho, k, eps, tag, pid,
                 steps, note)
 
@@ -289,10 +289,18 @@ def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
 # far-field.  k-epsilon on; no walls.
 # ----------------------------------------------------------------------------
 def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
-             turb_int=0.05, mix_len=0.07, noise=0.05, seed=2, steps=5000):
+             turb_int=0.05, mix_len=0.07, noise=0.05, seed=2, steps=5000, turbulence=1,
+             tvf_alpha=0.0, corner_overhang=0.0, pad_cells=3):
+    """Plane jet with the six buffers of Table 3.  corner_overhang widens the
+    outlet buffer's transverse box past y = +-W (the corner cells it shares
+    with the far-field buffers): a slow particle there that moves out through
+    the top or bottom stays an outlet particle instead of turning into a
+    fluid particle outside every buffer.  pad_cells widens the cell grid
+    around the domain for long runs."""
     dp = D / 20 if dp is None else dp
     nu = U * D / Re
-    P = base_params(2, dp, c0=c0, nu_l=nu, u_ref=U, turbulence=1, seed=seed)
+    P = base_params(2, dp, c0=c0, nu_l=nu, u_ref=U, turbulence=turbulence, seed=seed)
+    P["tvf_alpha"] = tvf_alpha
     k_in = 1.5 * (turb_int * U) ** 2
     eps_in = P["Cmu"] ** 0.75 * k_in ** 1.5 / (mix_len * D)
     k_a, eps_a = 1e-3 * k_in, 1e-3 * eps_in
@@ -304,7 +312,7 @@ def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
                 vel_mode=VEL_PRESCRIBED, p_mode=P_EXTRAPOLATE,
                 turb_mode=TURB_FREESTREAM, k_bc=k_in, eps_bc=eps_in,
                 profile=PROFILE_UNIFORM, u0=U, noise_amp=noise)
-    b2 = Buffer(2, (L, 0.0, 0.0), _frame2(-1.0, 0.0), Lb, (W, 0.0), f,
+    b2 = Buffer(2, (L, 0.0, 0.0), _frame2(-1.0, 0.0), Lb, (W + corner_overhang, 0.0), f,
                 vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=0.0)
     hw_side = (W - D / 2) / 2
     b3 = Buffer(3, (0.0, D / 2 + hw_side, 0.0), ex, Lb, (hw_side, 0.0), f,
@@ -319,9 +327,22 @@ def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
                 vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=0.0)
     wall = np.zeros((0, 3))
     return _assemble("jet", P, [b1, b2, b3, b4, b5, b6], fluid, wall, steps,
-                     k0=k_a, eps0=eps_a,
+                     k0=k_a, eps0=eps_a, pad_cells=pad_cells,
                      note=f"plane jet D={D} {L}x{2 * W} dp={dp} Re={Re:g} "
                           f"k_in={k_in:.4g} eps_in={eps_in:.4g}")
+
+
+def make_laminar_jet(nf=10, Re=40.0, tvf_alpha=0.2, steps=20000, seed=2):
+    """Laminar plane jet of Sec. 4.3: slot width D = 2, domain 40 D long and
+    2 x 20 D wide, nf particles across the slot, uniform inlet speed 1, the
+    six buffers of Table 3, no inlet noise, with the transport-velocity
+    shift (particle regularity in the low-pressure shear layers at the slot
+    lips and in the outlet buffer's backflow).  The grid is padded for runs
+    of some 10^4 steps."""
+    D = 2.0
+    dp = D / nf
+    return make_jet(dp=dp, D=D, L=40 * D, W=20 * D, U=1.0, Re=Re, noise=0.0, seed=seed,
+                    steps=steps, turbulence=0, tvf_alpha=tvf_alpha, pad_cells=20)
 
 
 # ----------------------------------------------------------------------------

@@ -82,6 +82,14 @@ typedef struct {
                            cell inside them */
   int64_t capacity;     /* particle slots: real + wall + reserve for injection, < 2^27 */
   uint64_t seed;        /* counter-based random numbers (inlet noise) */
+  double tvf_alpha;     /* transport-velocity shift (Sec. 2.3 names the formulation
+                           and cites it without a formula; the form used is
+                           dx_i = -tvf_alpha h^2 sum_j 2 V_j grad_i W_ij for fluid
+                           particles and, along their open face only,
+                           particles of extrapolated-velocity buffers, summed
+                           on the start-of-step state and added
+                           to the positions at the end of the advection step);
+                           0 = off.  The adjoint requires 0. */
 } sph_params;
 
 /* One buffer (Secs. 2.4.1-2.4.3, 3.1, 3.2, Table 3).  The box is given in
@@ -133,6 +141,8 @@ typedef struct {
   double* deps;   /* [n] deps/dt (RANS only), Eq. (epsilon-discretized-equ) */
   double* B;      /* [9][n] correction matrix, Eq. (equ-B-matrix) */
   double* p;      /* [n] effective pressure (Table 1) */
+  double* shift;  /* [3][n] transport-velocity shift (tvf_alpha != 0; 0 for
+                     prescribed-velocity buffers and walls); NULL: not written */
 } sph_rates;
 
 typedef struct {
@@ -365,7 +375,7 @@ typedef struct {
 /* Device workspace of sph_adjoint_step (or of one step of
  * sph_adjoint_forward / sph_adjoint_reverse) for steps of up to max_nac
  * acoustic sub-steps; 0 when the context cannot run the adjoint
- * (turbulent). */
+ * (turbulent, or with the transport-velocity shift on). */
 size_t sph_adjoint_workspace_size(const sph_ctx* ctx, int32_t max_nac);
 
 /* Discrete adjoint of one advection step followed by its buffer update

@@ -1618,7 +1618,7 @@ hipError_t adjoint_reverse(sph_ctx* c, const AdjLayout& Lw, char* ws, const sph_
 }  // namespace
 
 size_t adjoint_ws_bytes(const sph_ctx* c, int max_nac) {
-  if (c->P.turbulence || max_nac < 1) return 0;
+  if (c->P.turbulence || c->P.tvf_alpha != 0.0 || max_nac < 1) return 0;
   return adj_layout(c, max_nac).total;
 }
 

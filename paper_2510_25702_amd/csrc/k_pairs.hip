@@ -176,6 +176,12 @@ struct AdvArgs {
   int64_t n_out;
   V4<T>* prec[3];   // pressure records of sub-step 0 (written)
   const V4<T>* arec[3];   // advection records (cell build)
+  int tvf;                // transport-velocity shift summed (uniform switch)
+  double tvf_c;           // -2 tvf_alpha h^2
+  double two_h;           // buffer particles within 2h of the box ends: no shift
+  const double* x[3];     // FP64 positions (buffer particles' local frame)
+  T* shift[3];            // the shift of fluid particles (written)
+  double* o_shift;        // rates output [3][n_out]
 };
 
 template <typename T, int DIM, int TURB, int L>
@@ -206,6 +212,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   T G[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T Bi[6];
   T ki = T(0), ei = T(0), Dk_i = T(0), De_i = T(0), dfk = T(0), dfe = T(0);
+  T sh[3] = {T(0), T(0), T(0)};   // sum_j V_j grad_i W_ij (transport velocity)
   if (TURB) {
     load_B<T, DIM>(a.B, i, Bi);   // the velocity gradient's correction
     ki = a.k[i];
@@ -271,6 +278,11 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     av[0] += s * vij[0];
     av[1] += s * vij[1];
     av[2] += s * vij[2];
+    if (a.tvf) {
+      const T fv = f * Vj;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) sh[k] += fv * r[k];
+    }
     if (TURB) {
       const T gW[3] = {f * r[0], f * r[1], f * r[2]};
       T BgW[3];
@@ -290,6 +302,10 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   });
 #pragma unroll
   for (int k = 0; k < 3; ++k) av[k] = team_sum<L>(av[k]);
+  if (a.tvf) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) sh[k] = team_sum<L>(sh[k]);
+  }
   if (TURB) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) G[k] = team_sum<L>(G[k]);
@@ -327,6 +343,31 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
         e_new = a.bufs[qb].eps_bc;
       }
       nut_new = C.Cmu * k_new * k_new / e_new;
+    }
+  }
+  if (a.tvf) {   // particles that move with the flow: fluid, extrapolating buffers
+    double d[3] = {0.0, 0.0, 0.0};
+    const BufDev* bq = tag_kind(ti) == kBuffer ? &a.bufs[a.bidx[tag_bid(ti)]] : nullptr;
+    if (tag_kind(ti) == kFluid || (bq && bq->vel_mode == kVelExtrapolate)) {
+      for (int k = 0; k < DIM; ++k) d[k] = a.tvf_c * (double)sh[k];
+      if (bq) {   // along the open face only (normal n_b removed), none near the ends
+        const double r0[3] = {a.x[0][i] - bq->origin[0], a.x[1][i] - bq->origin[1],
+                              DIM == 3 ? a.x[2][i] - bq->origin[2] : 0.0 - bq->origin[2]};
+        const double* fr = bq->frame;
+        const double y1 = (fr[3] * r0[0] + fr[4] * r0[1]) + fr[5] * r0[2];
+        const double y2 = (fr[6] * r0[0] + fr[7] * r0[1]) + fr[8] * r0[2];
+        const bool end = fabs(y1) > bq->hw[0] - a.two_h ||
+                         (DIM == 3 && fabs(y2) > bq->hw[1] - a.two_h);
+        const double dn = (d[0] * fr[0] + d[1] * fr[1]) + d[2] * fr[2];
+        for (int k = 0; k < DIM; ++k) d[k] = end ? 0.0 : d[k] - dn * fr[k];
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (a.rates_only) {
+        if (a.o_shift) a.o_shift[(int64_t)k * a.n_out + i] = d[k];
+      } else {
+        a.shift[k][i] = (T)d[k];
+      }
     }
   }
   if (a.rates_only) {
@@ -908,6 +949,27 @@ __global__ void k_export_B(int n, const T* B0, const T* B1, const T* B2, const T
   out[8 * N + i] = b[5];
 }
 
+// End of the advection step with the transport-velocity shift: real
+// particles advance by the shift summed on the start-of-step state (zero for
+// prescribed-velocity buffers), FP64 master position and cell-relative copy.
+// No neighbour is read, so the update is in place.
+template <typename T, int DIM>
+__global__ void k_shift_apply(int n, const uint32_t* __restrict__ tag, const T* s0, const T* s1,
+                              const T* s2, double* x0, double* x1, double* x2, T* r0, T* r1,
+                              T* r2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || tag_kind(tag[i]) > kBuffer) return;
+  const T d[3] = {s0[i], s1[i], DIM == 3 ? s2[i] : T(0)};
+  x0[i] += (double)d[0];
+  x1[i] += (double)d[1];
+  r0[i] += d[0];
+  r1[i] += d[1];
+  if (DIM == 3) {
+    x2[i] += (double)d[2];
+    r2[i] += d[2];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host-side argument assembly
 // ---------------------------------------------------------------------------
@@ -1022,6 +1084,12 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   a.n_out = c->n_total;
   for (int k = 0; k < 3; ++k) a.prec[k] = tp<V4<T>>(F.prec[k]);
   for (int k = 0; k < 3; ++k) a.arec[k] = tp<V4<T>>(F.arec[k]);
+  a.tvf = F.shift[0] && (!rates_only || (out && out->shift)) ? 1 : 0;
+  a.tvf_c = -2.0 * c->P.tvf_alpha * c->P.h * c->P.h;
+  a.two_h = 2.0 * c->P.h;
+  for (int k = 0; k < 3; ++k) a.x[k] = F.x[k].live();
+  for (int k = 0; k < 3; ++k) a.shift[k] = tp<T>(F.shift[k]);
+  a.o_shift = out ? out->shift : nullptr;
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
@@ -1187,6 +1255,17 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update, bool keys) 
 }
 
 template <typename T, int DIM>
+hipError_t shift_apply_impl(sph_ctx* c) {
+  Fields& F = c->F;
+  const int64_t n = c->n_total;
+  k_shift_apply<T, DIM><<<nblk(n), 256, 0, c->stream>>>(
+      (int)n, F.tag.live(), tp<T>(F.shift[0]), tp<T>(F.shift[1]), tp<T>(F.shift[2]),
+      F.x[0].live(), F.x[1].live(), F.x[2].live(), tp<T>(F.xr[0].live()),
+      tp<T>(F.xr[1].live()), tp<T>(F.xr[2].live()));
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
 hipError_t export_B_impl(sph_ctx* c, double* B) {
   Fields& F = c->F;
   const int64_t n = c->n_total;
@@ -1231,6 +1310,8 @@ hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update, bool keys
 }
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }
+
+hipError_t launch_shift_apply(sph_ctx* c) { return SPHX_DISPATCH(shift_apply_impl, c); }
 
 hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
 

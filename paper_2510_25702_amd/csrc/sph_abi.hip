@@ -55,6 +55,7 @@ const char* validate(const sph_params* P, const sph_buffer_desc* B, int32_t nbuf
   if (P->precision != SPH_FP64 && P->precision != SPH_FP32_MIXED) return "bad precision";
   if (P->turbulence != 0 && P->turbulence != 1) return "turbulence must be 0 or 1";
   if (P->obc_mode < 1 || P->obc_mode > 4) return "obc_mode must be 1..4";
+  if (!(P->tvf_alpha >= 0.0 && P->tvf_alpha <= 1.0)) return "tvf_alpha must be in [0, 1]";
   if (!(P->dp > 0) || !(P->h > 0) || !(P->rho0 > 0) || !(P->c0 > 0)) return "dp, h, rho0, c0 must be > 0";
   if (!(P->nu_l >= 0)) return "nu_l must be >= 0";
   if (!(P->cell_size >= 2.0 * P->h)) return "cell_size must be >= 2h";
@@ -161,7 +162,8 @@ struct Plan {
       off_nut[2], off_tag[2], off_pid[2], off_p[2], off_vol[2], off_B[6], off_anu[3], off_cell,
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
-      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate;
+      off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate,
+      off_shift[3];
   int n_cand;
 };
 
@@ -197,6 +199,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   for (int k = 0; k < 3; ++k) pl->off_prec[k] = L.take((P->dim == 3 || k < 2) ? C * 4 * sT : 0);
   for (int k = 0; k < 2; ++k) pl->off_drec[k] = L.take(C * 4 * sT);
   for (int k = 0; k < 3; ++k) pl->off_arec[k] = L.take((P->dim == 3 || k < 2) ? C * 4 * sT : 0);
+  for (int k = 0; k < 3; ++k) pl->off_shift[k] = L.take(P->tvf_alpha != 0.0 ? C * sT : 0);
   pl->off_key = L.take(C * 4);
   pl->off_slot = L.take(C * 4);
   pl->off_perm = L.take(C * 4);
@@ -530,6 +533,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   for (int k = 0; k < 3; ++k) F.prec[k] = w + pl.off_prec[k];
   for (int k = 0; k < 2; ++k) F.drec[k] = w + pl.off_drec[k];
   for (int k = 0; k < 3; ++k) F.arec[k] = w + pl.off_arec[k];
+  for (int k = 0; k < 3; ++k) F.shift[k] = params->tvf_alpha != 0.0 ? w + pl.off_shift[k] : nullptr;
   F.nbr_k = params->dim == 2 ? kNbrMax2 : kNbrMax3;
   if (const char* nl = std::getenv("SPHX_NBR_LIST")) c->use_nbr = std::atoi(nl) != 0;
   Scratch& S = c->S;
@@ -801,6 +805,10 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
     prof_end(c);
     if (e != hipSuccess) return hip_fail(c, e, "density");
   }
+  if (c->F.shift[0]) {   // transport-velocity shift of the start-of-step state
+    e = launch_shift_apply(c);
+    if (e != hipSuccess) return hip_fail(c, e, "shift");
+  }
   c->step += 1;
   c->t += dt_adv;
   c->moved = true;
@@ -955,6 +963,8 @@ sph_status adjoint_check(sph_ctx* c, const sph_adjoint_ctrl* ctl, const void* ad
                          size_t adj_bytes) {
   if (!ctl) return fail(c, SPH_E_ARG, "null argument");
   if (c->P.turbulence) return fail(c, SPH_E_ARG, "the adjoint needs a laminar context");
+  if (c->P.tvf_alpha != 0.0)
+    return fail(c, SPH_E_ARG, "the adjoint is defined without the transport-velocity shift");
   if (ctl->n_ac < 1 || !(ctl->dt_adv > 0)) return fail(c, SPH_E_ARG, "bad dt_adv / n_ac");
   if (!ctl->dec_by_pid || ctl->pid_cap < (int64_t)ctl->next_pid)
     return fail(c, SPH_E_ARG, "dec_by_pid with pid_cap >= next_pid is required");

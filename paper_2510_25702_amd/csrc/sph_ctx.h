@@ -50,6 +50,7 @@ struct Fields {
   void* prec[3];           // position, p, volume (negative: wall), B
   void* drec[2];           // position, velocity, p, volume (negative: wall)
   void* arec[3];           // position, velocity, volume (negative: wall), RANS fields
+  void* shift[3];          // transport-velocity shift of the step (NULL: off)
 };
 
 struct Scratch {
@@ -150,6 +151,9 @@ hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_
 // updated arrays for the next build (launch_build_cells with keys_done)
 hipError_t launch_reduce(sph_ctx* c, double* out_host3, bool after_update = false,
                          bool keys = false);
+// Adds the transport-velocity shift of the advection pass to the positions
+// of fluid particles (the end of the advection step).
+hipError_t launch_shift_apply(sph_ctx* c);
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
                             const sph_rates* out);
 hipError_t launch_pressure(sph_ctx* c, double dt, bool rates_only, const sph_rates* out);

@@ -44,7 +44,7 @@ class sph_params(C.Structure):
                 ("cfl_ac", C.c_double), ("u_ref", C.c_double),
                 ("cell_size", C.c_double), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("capacity", C.c_int64),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("tvf_alpha", C.c_double)]
 
 
 class sph_buffer_desc(C.Structure):
@@ -65,7 +65,7 @@ class sph_particles(C.Structure):
 
 class sph_rates(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in
-                ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p")]
+                ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p", "shift")]
 
 
 class sph_buffer_counts(C.Structure):
@@ -340,6 +340,7 @@ def make_params(p: dict, precision: int, capacity: int) -> sph_params:
         P.g[k], P.lo[k], P.hi[k] = p["g"][k], p["lo"][k], p["hi"][k]
     P.capacity = int(capacity)
     P.seed = int(p["seed"])
+    P.tvf_alpha = float(p.get("tvf_alpha", 0.0))
     return P
 
 
@@ -500,14 +501,18 @@ class Simulation:
         out = dict(ap=torch.zeros(3, n, **f64), drho=torch.zeros(n, **f64),
                    anu=torch.zeros(3, n, **f64), gradv=torch.zeros(9, n, **f64),
                    dk=torch.zeros(n, **f64), deps=torch.zeros(n, **f64),
-                   B=torch.zeros(9, n, **f64), p=torch.zeros(n, **f64))
+                   B=torch.zeros(9, n, **f64), p=torch.zeros(n, **f64),
+                   shift=torch.zeros(3, n, **f64))
         turb = bool(self.pdict["turbulence"])
-        ptr = lambda f: out[f].data_ptr() if (turb or f not in ("gradv", "dk", "deps")) else None
-        R = sph_rates(*[ptr(f) for f in ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p")])
+        tvf = float(self.pdict.get("tvf_alpha", 0.0)) != 0.0
+        ptr = lambda f: out[f].data_ptr() if ((turb or f not in ("gradv", "dk", "deps"))
+                                              and (tvf or f != "shift")) else None
+        R = sph_rates(*[ptr(f) for f in ("ap", "drho", "anu", "gradv", "dk", "deps", "B", "p",
+                                         "shift")])
         sph_eval_rates(self.ctx, R)
         self.stream.synchronize()
         res = {f: t.cpu().numpy() for f, t in out.items()}
-        for f in ("ap", "anu", "gradv", "B"):
+        for f in ("ap", "anu", "gradv", "B", "shift"):
             res[f] = res[f].T.copy()
         return res
 
