@@ -1076,6 +1076,14 @@ static uint32_t decide(const ora_params* P, const ora_buffer* B, int nbuf,
       if (in_region(dim, &B[q], y2))
         return ORA_DEC_REVERT_RELABEL | ((uint32_t)b->id << 8) | ((uint32_t)B[q].id << 16);
     }
+    /* out through the side of its box into no buffer region: behind the plane
+     * of any buffer's open face it has left the domain at a corner, where
+     * two open boundaries meet, and is deleted like one crossing a face */
+    for (int q = 0; q < nbuf; ++q) {
+      double y2[3];
+      to_local(&B[q], x, y2);
+      if (y2[0] < 0.0) return ORA_DEC_DELETE | ((uint32_t)b->id << 8);
+    }
     return ORA_DEC_REVERT | ((uint32_t)b->id << 8);
   }
   if (kind != ORA_FLUID) return ORA_DEC_NONE;

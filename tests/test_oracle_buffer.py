@@ -87,6 +87,24 @@ def test_buffer_particle_outside_its_box_reverts(ora):
     assert [act(d) for d in dec] == [ORA_DEC_REVERT, ORA_DEC_REVERT]
 
 
+def test_buffer_particle_leaving_a_corner_is_deleted(ora):
+    # two open faces meet at a corner: x = 1 (outlet, facing -x) and y = 1
+    # (far field, facing -y, covering 0.2 <= x <= 0.8).  An outlet particle
+    # that leaves its box through y = 1 lands in no buffer region and lies
+    # behind the far-field face: deleted.  One that leaves its box through
+    # y = 1 while still in front of every face plane (a box side bordering
+    # fluid) reverts, as does one below the far-field face.
+    out = cases.Buffer(2, (1.0, 0.5, 0.0), cases._frame2(-1.0, 0.0), 4 * DP, (0.5, 0.0),
+                       0.5 * DP)
+    top = cases.Buffer(5, (0.5, 1.0, 0.0), cases._frame2(0.0, -1.0), 4 * DP, (0.3, 0.0),
+                       0.5 * DP)
+    B2 = make_tag(BUFFER, 2)
+    pts = [(0.95, 1.01), (0.95, 0.99), (0.95, -0.01)]
+    s, dec = decisions(ora, crafted(pts, [B2, B2, B2], [out, top]))
+    assert [act(d) for d in dec] == [ORA_DEC_DELETE, ORA_DEC_NONE, ORA_DEC_REVERT]
+    assert ((dec[0] >> 8) & 0xFF) == 2
+
+
 def test_buffer_id_prevents_erroneous_deletion(ora):
     # Sec. 3.2, first issue: a particle of the inflow buffer lying in the
     # deletion half-space of the outflow buffer is not deleted by it.
