@@ -83,6 +83,13 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
       if (in_region(a.dim, b2, y2))
         return kDecRevertRelabel | ((uint32_t)b.id << 8) | ((uint32_t)b2.id << 16);
     }
+    // out through a side of its box into no region and behind some buffer's
+    // open-face plane: it left the domain at a corner of two open boundaries
+    for (int q2 = 0; q2 < a.nbuf; ++q2) {
+      double y2[3];
+      to_local(a.bufs[q2], x0, x1, x2, y2);
+      if (y2[0] < 0.0) return kDecDelete | ((uint32_t)b.id << 8);
+    }
     return kDecRevert | ((uint32_t)b.id << 8);
   }
   for (int q = 0; q < a.nbuf; ++q) {

@@ -391,6 +391,36 @@ def test_crafted_decisions_bit_exact(sph, ora):
     assert len({d & 0xFF for d in oo.values()}) == 6
 
 
+def test_corner_decisions_bit_exact(sph, ora):
+    # two open faces meeting at a corner (outlet x = 1 facing -x, far field
+    # y = 1 facing -y): particles of both buffers on a grid around the corner,
+    # including ones out through a box side behind the other face (deleted)
+    from tests.test_oracle_buffer import crafted, DP
+    from cases import BUFFER, FLUID, make_tag
+    out = cases.Buffer(2, (1.0, 0.5, 0.0), cases._frame2(-1.0, 0.0), 4 * DP, (0.5, 0.0),
+                       0.5 * DP)
+    top = cases.Buffer(5, (0.5, 1.0, 0.0), cases._frame2(0.0, -1.0), 4 * DP, (0.3, 0.0),
+                       0.5 * DP)
+    pts, tags = [], []
+    for x in np.linspace(0.7, 1.05, 15):
+        for y in np.linspace(0.75, 1.05, 13):
+            for t in (make_tag(FLUID), make_tag(BUFFER, 2), make_tag(BUFFER, 5)):
+                pts.append((x, y))
+                tags.append(t)
+    c = crafted(pts, tags, [out, top])
+    dec_o = ora.OracleSim(c).decisions()
+    g = gpu_sim(sph, c, sph.SPH_FP64)
+    g.build_cells()
+    dec_g = g.decisions()
+    go = {int(p): int(d) for p, d in zip(g.state()["pid"], dec_g)}
+    oo = {int(p): int(d) for p, d in zip(c.pid, dec_o)}
+    assert go == oo
+    # the corner rule fires: BUFFER(2) out of its box (y > 1) is deleted
+    corner = [d for (x, y), t, d in zip(pts, tags, dec_o)
+              if t == make_tag(BUFFER, 2) and y > 1.0 and 0.8 < x < 1.0]
+    assert corner and all(d & 0xFF == 3 for d in corner)
+
+
 @pytest.mark.parametrize("pname,prec", [("fp64", 0), ("fp32", 1)])
 def test_many_injections_in_one_update(sph, ora, pname, prec):
     # more injections in one update than one wavefront sorts in its registers
