@@ -50,6 +50,9 @@ def parse():
                          "calibration under rocprofv3) and exit")
     ap.add_argument("--laminar-jet", action="store_true",
                     help="laminar plane jet (Re 40) against the closed-form jet; prints one JSON line")
+    ap.add_argument("--jet-steps", type=int, default=20000,
+                    help="advection steps of --laminar-jet (the mean is over the last quarter, "
+                         "at most 5000)")
     ap.add_argument("--obc-ablation", action="store_true",
                     help="only run the open-boundary ablation of Table 2 (Cases 1-4) on the "
                          "laminar channel and print its JSON line")
@@ -325,9 +328,15 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
             np.add.at(acc[q], b, v[sel, 0])
             np.add.at(cnt[q], b, 1)
     secs = time.perf_counter() - t0
+    head = {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
+                     f"tvf_alpha {c.params['tvf_alpha']}, {steps} steps (t = "
+                     f"{sph.sph_get_clock(g.ctx)[1]:.0f}), mean of the last {navg}",
+            "ms_per_step": round(1e3 * secs / max(steps, 1), 4)}
     u = acc / np.maximum(cnt, 1)
     yc = -W + (np.arange(ny) + 0.5) * dp
     uc = u[:, np.abs(yc) < dp].mean(axis=1)
+    if not np.all(uc > 0.05):   # the jet has not reached every station yet
+        return dict(head, note="jet not developed over the stations; no similarity figures")
     half = []
     for q in range(len(xs)):
         prof, up = u[q], yc > 0
@@ -351,9 +360,7 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
     prof = 1.0 / np.cosh(0.8814 * eta) ** 2
     l2 = float(np.sqrt(np.mean((coll - prof)[m] ** 2) / np.mean(prof[m] ** 2)))
     mom = (u ** 2).sum(axis=1) * dp
-    return {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
-                     f"tvf_alpha {c.params['tvf_alpha']}, {steps} steps (t = "
-                     f"{sph.sph_get_clock(g.ctx)[1]:.0f}), mean of the last {navg}",
+    return {**head,
             "uc_m3_slope_rel_err": round(float(s_u / th_u - 1.0), 4),
             "uc_m3_corr": round(float(np.corrcoef(xs, uc ** -3)[0, 1]), 5),
             "uc_virtual_origin": round(float(-i_u / s_u), 2),
@@ -560,7 +567,9 @@ def main():
         print(json.dumps({"calibration_copy_bytes": n, "copies": 5}), flush=True)
         return
     if args.laminar_jet:
-        print(json.dumps({"laminar_jet": laminar_jet()}), flush=True)
+        print(json.dumps({"laminar_jet": laminar_jet(steps=args.jet_steps,
+                                                     navg=min(5000, args.jet_steps // 4))}),
+              flush=True)
         return
     if args.obc_ablation:
         print(json.dumps({"obc_ablation": obc_ablation(steps=6000, navg=2000)}), flush=True)
