@@ -50,6 +50,8 @@ def parse():
                          "calibration under rocprofv3) and exit")
     ap.add_argument("--laminar-jet", action="store_true",
                     help="laminar plane jet (Re 40) against the closed-form jet; prints one JSON line")
+    ap.add_argument("--jet-precision", type=int, default=1, choices=(0, 1),
+                    help="--laminar-jet arithmetic: 0 FP64, 1 FP32-mixed")
     ap.add_argument("--jet-steps", type=int, default=20000,
                     help="advection steps of --laminar-jet (the mean is over the last quarter, "
                          "at most 5000)")
@@ -568,7 +570,8 @@ def main():
         return
     if args.laminar_jet:
         print(json.dumps({"laminar_jet": laminar_jet(steps=args.jet_steps,
-                                                     navg=min(5000, args.jet_steps // 4))}),
+                                                     navg=min(5000, args.jet_steps // 4),
+                                                     precision=args.jet_precision)}),
               flush=True)
         return
     if args.obc_ablation:
