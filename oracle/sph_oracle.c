@@ -1076,13 +1076,21 @@ static uint32_t decide(const ora_params* P, const ora_buffer* B, int nbuf,
       if (in_region(dim, &B[q], y2))
         return ORA_DEC_REVERT_RELABEL | ((uint32_t)b->id << 8) | ((uint32_t)B[q].id << 16);
     }
-    /* out through the side of its box into no buffer region: behind the plane
-     * of any buffer's open face it has left the domain at a corner, where
-     * two open boundaries meet, and is deleted like one crossing a face */
+    /* out through the side of its box into no buffer region: if it is
+     * behind the open-face plane of a buffer whose face, extended along its
+     * plane by the particle's own buffer length (to the generation line) and
+     * the kernel support 2h, reaches it, it has left the domain through that
+     * face at a corner where two open boundaries meet, and is deleted like
+     * a particle crossing a face (Sec. 2.4.3).  A face plane far away (a
+     * channel bent by more than 180 degrees) does not delete it (Sec. 3.2). */
+    double m = (b->length + b->fringe) + 2.0 * P->h;
     for (int q = 0; q < nbuf; ++q) {
       double y2[3];
       to_local(&B[q], x, y2);
-      if (y2[0] < 0.0) return ORA_DEC_DELETE | ((uint32_t)b->id << 8);
+      if (!(y2[0] < 0.0)) continue;
+      if (fabs(y2[1]) > B[q].half_width[0] + m) continue;
+      if (dim == 3 && fabs(y2[2]) > B[q].half_width[1] + m) continue;
+      return ORA_DEC_DELETE | ((uint32_t)b->id << 8);
     }
     return ORA_DEC_REVERT | ((uint32_t)b->id << 8);
   }

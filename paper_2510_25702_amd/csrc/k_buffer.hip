@@ -45,6 +45,7 @@ struct BufArgs {
   uint32_t* log;            // decisions by particle id (record), or NULL
   int64_t pid_cap;          // length of forced / log
   int n;                    // particle slots (forced replay: every slot)
+  double two_h;             // kernel support 2h
 };
 
 __device__ __forceinline__ bool in_box(const int c[3], const BufDev& b, int dim) {
@@ -83,12 +84,20 @@ __device__ uint32_t decide(const BufArgs& a, double x0, double x1, double x2, ui
       if (in_region(a.dim, b2, y2))
         return kDecRevertRelabel | ((uint32_t)b.id << 8) | ((uint32_t)b2.id << 16);
     }
-    // out through a side of its box into no region and behind some buffer's
-    // open-face plane: it left the domain at a corner of two open boundaries
+    // out through a side of its box into no region and behind the open-face
+    // plane of a buffer whose face, extended along its plane by this
+    // particle's buffer length to the generation line and by 2h, reaches it:
+    // it left the domain at a corner of two open boundaries.  A far plane
+    // (a channel bent by more than 180 degrees) does not delete it.
+    const double m = __dadd_rn(b.gen, a.two_h);
     for (int q2 = 0; q2 < a.nbuf; ++q2) {
+      const BufDev& b2 = a.bufs[q2];
       double y2[3];
-      to_local(a.bufs[q2], x0, x1, x2, y2);
-      if (y2[0] < 0.0) return kDecDelete | ((uint32_t)b.id << 8);
+      to_local(b2, x0, x1, x2, y2);
+      if (!(y2[0] < 0.0)) continue;
+      if (fabs(y2[1]) > __dadd_rn(b2.hw[0], m)) continue;
+      if (a.dim == 3 && fabs(y2[2]) > __dadd_rn(b2.hw[1], m)) continue;
+      return kDecDelete | ((uint32_t)b.id << 8);
     }
     return kDecRevert | ((uint32_t)b.id << 8);
   }
@@ -376,6 +385,7 @@ BufArgs make_bufargs(sph_ctx* c, bool dry, uint32_t* dec_out) {
   a.log = nullptr;
   a.pid_cap = 0;
   a.n = (int)c->n_total;
+  a.two_h = 2.0 * c->P.h;
   return a;
 }
 

@@ -105,6 +105,24 @@ def test_buffer_particle_leaving_a_corner_is_deleted(ora):
     assert ((dec[0] >> 8) & 0xFF) == 2
 
 
+def test_far_face_plane_does_not_delete_a_particle_out_of_its_box(ora):
+    # a channel bent by more than 180 degrees: buffer 3's open face (y = 5,
+    # facing +y, 2.5 <= x <= 3.5) has the whole lower region behind its plane.
+    # A particle of the inlet buffer 1 (x = 0, facing +x, 0 <= y <= 1) that
+    # slips out of its box through y = 1 (near-wall particles can cross the
+    # dummy interface a little, Sec. 4.3) is behind that far plane but has
+    # not left the domain there: it reverts (Sec. 3.2, first issue).  Behind
+    # its own face at the same time (a corner of its own face) it is deleted.
+    b1 = inlet(1, origin=(0.0, 0.5))
+    far = cases.Buffer(3, (3.0, 5.0, 0.0), cases._frame2(0.0, 1.0), 4 * DP, (0.5, 0.0),
+                       0.5 * DP)
+    B1 = make_tag(BUFFER, 1)
+    pts = [(0.1, 1.01), (0.19, 1.02), (-0.01, 1.01)]
+    s, dec = decisions(ora, crafted(pts, [B1, B1, B1], [b1, far]))
+    assert [act(d) for d in dec] == [ORA_DEC_REVERT, ORA_DEC_REVERT, ORA_DEC_DELETE]
+    assert all(((d >> 8) & 0xFF) == 1 for d in dec)
+
+
 def test_buffer_id_prevents_erroneous_deletion(ora):
     # Sec. 3.2, first issue: a particle of the inflow buffer lying in the
     # deletion half-space of the outflow buffer is not deleted by it.
