@@ -194,6 +194,18 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   const auto h = list_head<T, L>(pc, i, lane);
   const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   if (!is_real(ti)) {
+    if (a.rates_only && lane == 0) {   // walls and dead slots: zero rates
+      for (int k = 0; k < 3; ++k) {
+        if (a.o_anu) a.o_anu[(int64_t)k * a.n_out + i] = 0.0;
+        if (a.o_shift) a.o_shift[(int64_t)k * a.n_out + i] = 0.0;
+      }
+      if (TURB) {
+        if (a.o_dk) a.o_dk[i] = 0.0;
+        if (a.o_deps) a.o_deps[i] = 0.0;
+        if (a.o_gradv)
+          for (int p = 0; p < 9; ++p) a.o_gradv[(int64_t)p * a.n_out + i] = 0.0;
+      }
+    }
     if (!a.rates_only && lane == 0) {
       for (int k = 0; k < 3; ++k) a.anu[k][i] = T(0);
       a.p_out[i] = T(0);
@@ -347,7 +359,8 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   }
   if (a.tvf) {   // particles that move with the flow: fluid, extrapolating buffers
     double d[3] = {0.0, 0.0, 0.0};
-    const BufDev* bq = tag_kind(ti) == kBuffer ? &a.bufs[a.bidx[tag_bid(ti)]] : nullptr;
+    const int qs = tag_kind(ti) == kBuffer ? a.bidx[tag_bid(ti)] : -1;
+    const BufDev* bq = qs >= 0 ? &a.bufs[qs] : nullptr;   // unknown id: no shift
     if (tag_kind(ti) == kFluid || (bq && bq->vel_mode == kVelExtrapolate)) {
       for (int k = 0; k < DIM; ++k) d[k] = a.tvf_c * (double)sh[k];
       if (bq) {   // along the open face only (normal n_b removed), none near the ends
@@ -373,6 +386,8 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   if (a.rates_only) {
     if (a.o_anu)
       for (int k = 0; k < 3; ++k) a.o_anu[(int64_t)k * a.n_out + i] = anu_d[k];
+    if (a.o_shift && !a.tvf)   // shift off: zero
+      for (int k = 0; k < 3; ++k) a.o_shift[(int64_t)k * a.n_out + i] = 0.0;
     return m_pairs;
   }
   for (int k = 0; k < 3; ++k) a.anu[k][i] = (T)anu_d[k];
@@ -478,7 +493,10 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   };
   constexpr bool early = hoist_epilogue<L>();
   if (early) load_update();
-  T acc[3] = {T(0), T(0), T(0)}, s[3] = {T(0), T(0), T(0)};
+  // the pair terms in T, their sums in FP64 (a pressure sum cancels to a
+  // small fraction of its terms, so T accumulation would add its own
+  // rounding of the partial sums to that of the terms)
+  double acc[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
   constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
@@ -511,19 +529,19 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       symv<T, DIM>(Bj, gW, bj);
       symv<T, DIM>(Bi, gW, bi);
       const T vpi = Vj * pi, vpj = Vj * pj;
-      acc[0] += vpi * bj[0] + vpj * bi[0];
-      acc[1] += vpi * bj[1] + vpj * bi[1];
-      acc[2] += vpi * bj[2] + vpj * bi[2];
+      acc[0] += (double)(vpi * bj[0] + vpj * bi[0]);
+      acc[1] += (double)(vpi * bj[1] + vpj * bi[1]);
+      if (DIM == 3) acc[2] += (double)(vpi * bj[2] + vpj * bi[2]);
     } else {
       const T pj = wall ? pi : pj_rec;
       const T w = Vj * (pi + pj);
-      acc[0] += w * gW[0];
-      acc[1] += w * gW[1];
-      acc[2] += w * gW[2];
+      acc[0] += (double)(w * gW[0]);
+      acc[1] += (double)(w * gW[1]);
+      if (DIM == 3) acc[2] += (double)(w * gW[2]);
     }
-    s[0] += Vj * gW[0];
-    s[1] += Vj * gW[1];
-    s[2] += Vj * gW[2];
+    s[0] += (double)(Vj * gW[0]);
+    s[1] += (double)(Vj * gW[1]);
+    if (DIM == 3) s[2] += (double)(Vj * gW[2]);
   });
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -533,18 +551,23 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   if (lane != 0) return m_pairs;
   if (!early) load_update();
   if (qb >= 0 && a.bufs[qb].p_mode != kPNone) {
-    const T pob = a.bufs[qb].p_mode == kPPrescribed
-                      ? (T)(a.bufs[qb].p_ob * buffer_ramp(a.bufs[qb], a.t)) : pi;
-    T cc[3];
-    if (MODE == 4) symv<T, DIM>(Bi, s, cc);
-    else { cc[0] = s[0]; cc[1] = s[1]; cc[2] = s[2]; }
-    acc[0] -= T(2) * pob * cc[0];
-    acc[1] -= T(2) * pob * cc[1];
-    acc[2] -= T(2) * pob * cc[2];
+    const double pob = a.bufs[qb].p_mode == kPPrescribed
+                           ? a.bufs[qb].p_ob * buffer_ramp(a.bufs[qb], a.t)
+                           : (double)pi;
+    double cc[3];
+    if (MODE == 4) {
+      const double Bd[6] = {(double)Bi[0], (double)Bi[1], (double)Bi[2],
+                            (double)Bi[3], (double)Bi[4], (double)Bi[5]};
+      symv<double, DIM>(Bd, s, cc);
+    } else {
+      cc[0] = s[0]; cc[1] = s[1]; cc[2] = s[2];
+    }
+    acc[0] -= 2.0 * pob * cc[0];
+    acc[1] -= 2.0 * pob * cc[1];
+    acc[2] -= 2.0 * pob * cc[2];
   }
   const double inv_rho = 1.0 / rho_i;
-  const double ap[3] = {-(double)acc[0] * inv_rho, -(double)acc[1] * inv_rho,
-                        -(double)acc[2] * inv_rho};
+  const double ap[3] = {-acc[0] * inv_rho, -acc[1] * inv_rho, -acc[2] * inv_rho};
   if (a.rates_only) {
     for (int k = 0; k < 3; ++k) a.o_ap[(int64_t)k * a.n_out + i] = ap[k];
     return m_pairs;
@@ -651,7 +674,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       };
       constexpr bool early = hoist_epilogue<L>();
       if (early) load_update();
-      T sum = T(0);
+      double sum = 0.0;   // FP64 sum of T terms (near-cancelling, see the pressure pass)
       int m = 0;
       for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec, h,
                                       [&](int j, const T r[3], T r2, const V4<T>* q) {
@@ -673,14 +696,14 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
                (DIM == 3 ? (vi[2] - vj2) * r[2] : T(0));
           dp = pi - pj;
         }
-        sum += Vj * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr);
+        sum += (double)(Vj * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr));
         ++m;
       });
       cnt = m;
       sum = team_sum<L>(sum);
       if (lane == 0) {
         if (!early) load_update();
-        const double drho = 2.0 * rho_i * (double)sum;
+        const double drho = 2.0 * rho_i * sum;
         if (a.rates_only) {
           a.o_drho[i] = drho;
         } else {
@@ -926,6 +949,26 @@ __global__ void k_neighbors(int n, const double* x0, const double* x1, const dou
         }
       }
     }
+  if (!FILL) row[i] = m;
+}
+
+// The pairs the pair passes of a step visit: particle i's candidates (the
+// per-step list, or the cell stencil when the list is off) that pass the
+// passes' own test |r_ij|^2 < (2h)^2 on cell-relative positions in the pair
+// precision, in visiting order; none for particles that are not real.
+template <typename T, int DIM, int FILL>
+__global__ void k_walk_pairs(int n, PairCtx<T> pc, int32_t* row, int32_t* col, int64_t cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int m = 0;
+  const int64_t o = FILL ? row[i] : 0;
+  if (is_real(pc.tag[i])) {
+    const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+    for_neighbors<T, DIM, 1>(pc, i, 0, xi, [&](int j, const T*, T) {
+      if (FILL && o + m < cap) col[o + m] = j;
+      ++m;
+    });
+  }
   if (!FILL) row[i] = m;
 }
 
@@ -1266,6 +1309,28 @@ hipError_t shift_apply_impl(sph_ctx* c) {
 }
 
 template <typename T, int DIM>
+hipError_t walk_pairs_impl(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                           int64_t* n_pairs) {
+  const int64_t n = c->n_total;
+  PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+  pc.pairs = nullptr;
+  int32_t* counts = c->S.slot;   // scratch (rewritten by every cell build)
+  k_walk_pairs<T, DIM, 0><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, counts, col, cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan_excl(c, counts, (int)n, row_ptr);
+  if (e != hipSuccess) return e;
+  int32_t* total = reinterpret_cast<int32_t*>(c->pinned);
+  e = hipMemcpyAsync(total, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  *n_pairs = *total;
+  k_walk_pairs<T, DIM, 1><<<nblk(n), 256, 0, c->stream>>>((int)n, pc, row_ptr, col, cap);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
 hipError_t export_B_impl(sph_ctx* c, double* B) {
   Fields& F = c->F;
   const int64_t n = c->n_total;
@@ -1311,9 +1376,12 @@ hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update, bool keys
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }
 
-hipError_t launch_shift_apply(sph_ctx* c) { return SPHX_DISPATCH(shift_apply_impl, c); }
+hipError_t launch_walk_pairs(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                             int64_t* n_pairs) {
+  return SPHX_DISPATCH(walk_pairs_impl, c, row_ptr, col, cap, n_pairs);
+}
 
-hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
+hipError_t launch_shift_apply(sph_ctx* c) { return SPHX_DISPATCH(shift_apply_impl, c); }
 
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs) {

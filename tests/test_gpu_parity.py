@@ -391,6 +391,36 @@ def test_crafted_decisions_bit_exact(sph, ora):
     assert len({d & 0xFF for d in oo.values()}) == 6
 
 
+def test_far_plane_decisions_bit_exact(sph, ora):
+    # a buffer particle out of its box through a side while behind a far
+    # buffer's face plane (a channel bent by more than 180 degrees) reverts;
+    # at its own face's corner it is deleted: every particle of a grid around
+    # the inlet's upper side, both buffers' tags, against the oracle
+    from tests.test_oracle_buffer import crafted, DP
+    from cases import BUFFER, FLUID, make_tag
+    b1 = cases.Buffer(1, (0.0, 0.5, 0.0), cases._frame2(1.0, 0.0), 4 * DP, (0.5, 0.0),
+                      0.5 * DP)
+    far = cases.Buffer(3, (3.0, 5.0, 0.0), cases._frame2(0.0, 1.0), 4 * DP, (0.5, 0.0),
+                       0.5 * DP)
+    pts, tags = [], []
+    for x in np.linspace(-0.05, 0.3, 15):
+        for y in np.linspace(0.8, 1.1, 13):
+            for t in (make_tag(FLUID), make_tag(BUFFER, 1), make_tag(BUFFER, 3)):
+                pts.append((x, y))
+                tags.append(t)
+    c = crafted(pts, tags, [b1, far])
+    dec_o = ora.OracleSim(c).decisions()
+    g = gpu_sim(sph, c, sph.SPH_FP64)
+    g.build_cells()
+    dec_g = g.decisions()
+    go = {int(p): int(d) for p, d in zip(g.state()["pid"], dec_g)}
+    oo = {int(p): int(d) for p, d in zip(c.pid, dec_o)}
+    assert go == oo
+    acts = [d & 0xFF for (x, y), t, d in zip(pts, tags, dec_o)
+            if t == make_tag(BUFFER, 1) and y > 1.0 and x > 0.0]
+    assert acts and all(a == 4 for a in acts)   # reverted, not deleted
+
+
 def test_corner_decisions_bit_exact(sph, ora):
     # two open faces meeting at a corner (outlet x = 1 facing -x, far field
     # y = 1 facing -y): particles of both buffers on a grid around the corner,
