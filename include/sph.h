@@ -225,9 +225,10 @@ sph_status sph_set_clock(sph_ctx* ctx, int64_t step, double t);
 sph_status sph_get_clock(const sph_ctx* ctx, int64_t* step, double* t, uint64_t* next_pid);
 
 /* Cell-linked-list build (Sec. 2.4.3: rebuilt after deletion every advection
- * step): counting sort of all particles by cell id (ties by particle id),
- * dropping particles tagged SPH_DEAD, and permutation of every field into
- * cell order.  Asynchronous. */
+ * step): stable counting sort of all particles by cell id (particles of one
+ * cell keep their relative order in the current arrays), dropping particles
+ * tagged SPH_DEAD, and permutation of every field into cell order.
+ * Asynchronous. */
 sph_status sph_build_cells(sph_ctx* ctx);
 
 /* Correction matrix B_i, Eq. (equ-B-matrix), with the mirror boundary
@@ -307,6 +308,20 @@ sph_status sph_eval_rates(sph_ctx* ctx, const sph_rates* out);
  * sph_build_cells since the last position change.  Synchronises. */
 sph_status sph_neighbors(sph_ctx* ctx, int32_t* row_ptr, int32_t* col,
                          int64_t cap, int64_t* n_pairs);
+
+/* The neighbour pairs that the pair passes of a step visit (Sec. 2.4.1: the
+ * cell-linked list; the sums of Eqs. (equ-B-matrix), (eq-discretize-momentum-
+ * p-RKGC), (discretize-continuity-equ-riemann) and (eq-discretize-momentum-
+ * ARD2) run over them): the candidates of the per-step neighbour list built
+ * by sph_correction (the cell stencil when that list is switched off) that
+ * pass the passes' own test |x_i - x_j|^2 < (2h)^2, evaluated in the pair
+ * precision on cell-relative positions.  CSR in the current order, row_ptr
+ * (device int32 [n_total + 1]) and col (device int32 [cap], visiting order);
+ * particles that are not real have empty rows.  *n_pairs receives the total;
+ * SPH_E_CAPACITY if it exceeds cap (row_ptr is still valid).  Requires
+ * sph_correction since the last position change (SPH_E_STATE).  Synchronises. */
+sph_status sph_step_pairs(sph_ctx* ctx, int32_t* row_ptr, int32_t* col, int64_t cap,
+                          int64_t* n_pairs);
 
 /* Kernel timing with HIP events on the context stream. */
 sph_status sph_profile_enable(sph_ctx* ctx, int32_t on);

@@ -12,10 +12,6 @@
 
 using namespace sphx;
 
-namespace sphx {
-hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
-}
-
 namespace {
 
 const char* kNoCtx = "sph: null context";
@@ -658,12 +654,22 @@ sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph
     return fail(c, SPH_E_ARG, "x, v, rho, tag and pid are required");
   if (c->P.turbulence && n > 0 && (!src->k || !src->eps))
     return fail(c, SPH_E_ARG, "k and eps are required with turbulence");
-  HIPCHK(c, launch_set_particles(c, n, src), "set_particles");
-  // count walls / real particles on the host side of the copy
+  // the tags on the host first: a buffer particle must name a configured
+  // buffer (Sec. 3.2), checked before anything is written; also the counts
+  // of walls and real particles
   std::vector<uint32_t> tags((size_t)n);
-  if (n > 0)
+  if (n > 0) {
     HIPCHK(c, hipMemcpyAsync(tags.data(), src->tag, n * 4, hipMemcpyDeviceToHost, c->stream),
            "set_particles tags");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "set_particles tags sync");
+  }
+  for (auto t : tags) {
+    if (tag_kind(t) != kBuffer) continue;
+    bool known = false;
+    for (int q = 0; q < c->nbuf; ++q) known |= c->bufs_h[q].id == (int32_t)tag_bid(t);
+    if (!known) return fail(c, SPH_E_ARG, "a buffer particle names an unknown buffer id");
+  }
+  HIPCHK(c, launch_set_particles(c, n, src), "set_particles");
   uint64_t np = next_pid;
   HIPCHK(c, hipMemcpyAsync(c->S.next_pid, &np, 8, hipMemcpyHostToDevice, c->stream), "next_pid");
   HIPCHK(c, hipMemsetAsync(c->S.flags, 0, 4, c->stream), "flags");
@@ -865,7 +871,7 @@ sph_status sph_eval_rates(sph_ctx* c, const sph_rates* out) {
   if (!c->cells_valid || c->moved || !c->B_valid)
     return fail(c, SPH_E_STATE, "sph_eval_rates needs sph_build_cells and sph_correction");
   HIPCHK(c, launch_prepare_pv(c, out), "prepare_pv");
-  if (out->anu || out->gradv || out->dk || out->deps)
+  if (out->anu || out->gradv || out->dk || out->deps || out->shift)
     HIPCHK(c, launch_advection(c, 0.0, 0.0, true, out), "advection rates");
   if (out->ap) HIPCHK(c, launch_pressure(c, 0.0, true, out), "pressure rates");
   if (out->drho) HIPCHK(c, launch_density(c, 0.0, false, true, out), "density rates");
@@ -881,6 +887,19 @@ sph_status sph_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap
   HIPCHK(c, launch_neighbors(c, row_ptr, col, cap, n_pairs), "neighbors");
   HIPCHK(c, hipStreamSynchronize(c->stream), "neighbors sync");
   if (*n_pairs > cap) return fail(c, SPH_E_CAPACITY, "neighbour list longer than cap");
+  return SPH_OK;
+}
+
+sph_status sph_step_pairs(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                          int64_t* n_pairs) {
+  if (!c) return SPH_E_ARG;
+  if (!row_ptr || !n_pairs || cap < 0 || (cap > 0 && !col))
+    return fail(c, SPH_E_ARG, "bad pair-list arguments");
+  if (!c->cells_valid || c->moved || !c->B_valid)
+    return fail(c, SPH_E_STATE, "sph_step_pairs needs sph_build_cells and sph_correction");
+  HIPCHK(c, launch_walk_pairs(c, row_ptr, col, cap, n_pairs), "step pairs");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "step pairs sync");
+  if (*n_pairs > cap) return fail(c, SPH_E_CAPACITY, "pair list longer than cap");
   return SPH_OK;
 }
 

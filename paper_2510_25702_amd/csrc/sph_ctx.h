@@ -168,6 +168,12 @@ hipError_t launch_buffer_undo(sph_ctx* c, bool all_slots);
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs);
 hipError_t launch_export_B(sph_ctx* c, double* B);
+// exclusive scan of n counts into out[0..n] (out[n] = total)
+hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
+// the pairs the pair passes visit (CSR in the current order); synchronises
+// once to read the total
+hipError_t launch_walk_pairs(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                             int64_t* n_pairs);
 
 // sensitivity (k_adjoint.hip)
 size_t adjoint_ws_bytes(const sph_ctx* c, int max_nac);

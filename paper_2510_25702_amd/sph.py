@@ -123,6 +123,8 @@ EXPORTS = {
     "sph_eval_rates": (C.c_int, [C.c_void_p, C.POINTER(sph_rates)]),
     "sph_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                 C.POINTER(C.c_int64)]),
+    "sph_step_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.POINTER(C.c_int64)]),
     "sph_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sph_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sph_kernel_stats)]),
     "sph_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -247,6 +249,13 @@ def sph_neighbors(ctx, row_ptr, col_ptr, cap):
     n = C.c_int64()
     _check(ctx, lib().sph_neighbors(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
                                     C.byref(n)))
+    return n.value
+
+
+def sph_step_pairs(ctx, row_ptr, col_ptr, cap):
+    n = C.c_int64()
+    _check(ctx, lib().sph_step_pairs(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
+                                     C.byref(n)))
     return n.value
 
 
@@ -523,6 +532,16 @@ class Simulation:
         cap = max(64, n * (160 if self.pdict["dim"] == 3 else 48))
         col = torch.zeros(cap, dtype=torch.int32, device=self.device)
         m = sph_neighbors(self.ctx, row.data_ptr(), col.data_ptr(), cap)
+        return row.cpu().numpy(), col.cpu().numpy()[:m]
+
+    def step_pairs(self):
+        """CSR (row_ptr, col) of the pairs the step's pair passes visit."""
+        torch = self.torch
+        n = self.n
+        row = torch.zeros(n + 1, dtype=torch.int32, device=self.device)
+        cap = max(64, n * (160 if self.pdict["dim"] == 3 else 48))
+        col = torch.zeros(cap, dtype=torch.int32, device=self.device)
+        m = sph_step_pairs(self.ctx, row.data_ptr(), col.data_ptr(), cap)
         return row.cpu().numpy(), col.cpu().numpy()[:m]
 
     def profile(self, on=True):
