@@ -19,14 +19,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+VALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks, published
 PROFILE_EVERY = 10        # steps between two event-timed steps
+
+# Algorithmic cost of one launch of a neighbour pass: each particle's own
+# input fields read once and its outputs written once (neighbour re-reads
+# that the caches serve are not counted), bytes per particle as
+# (FP32-mixed, FP64); and flops per directed pair within 2h (an FMA is 2,
+# a square root 1), (2D, 3D).  The k-epsilon advection pass adds 20 bytes
+# and 20 flops.
+ALGO_BYTES = {("correction", 2): (60, 68), ("correction", 3): (104, 108),
+              ("advection", 2): (64, 115), ("advection", 3): (96, 175),
+              ("pressure", 2): (52, 100), ("pressure", 3): (76, 148),
+              ("density", 2): (80, 108), ("density", 3): (104, 140)}
+FLOPS_PER_PAIR = {"correction": (22, 32), "advection": (35, 55), "pressure": (32, 50),
+                  "density": (26, 32)}
 
 WORKLOADS = {
     # name: (generator, kwargs, label)
     "uchannel": ("make_uchannel", {}, "2D U-channel, dp=H/40, ~50k fluid particles, Re=50"),
     "channel": ("make_channel", {}, "2D straight channel 10Hx1H, dp=H/20, 4k fluid, Re=100"),
     "jet": ("make_jet", {}, "2D turbulent plane jet 20Dx20D, dp=D/20, 160k, k-eps"),
-    "mixer": ("make_mixer", {}, "3D micro-mixer, dp=0.005, ~3.3M fluid particles"),
+    "mixer": ("make_mixer", {}, "3D self-rotating micro-mixer: chamber 1 x 0.5, four "
+              "tangential 0.1 x 0.1 inlets, axial outlet of diameter 0.2, dp=0.005, "
+              "3.29M fluid + 0.46M wall particles, Re=50, FP32-mixed"),
     "adjoint_channel": ("make_adjoint_channel", {}, "2D channel 20Hx1H, dp=H/80, 128k"),
     "jet_640k": ("make_jet", {"dp": 0.025}, "2D jet geometry at dp=D/40, 640k"),
     "jet_2560k": ("make_jet", {"dp": 0.0125}, "2D jet geometry at dp=D/80, 2.56M"),
@@ -34,12 +50,21 @@ WORKLOADS = {
 }
 
 
+# one-core oracle sample of a workload whose full step takes minutes on one
+# core: the same geometry at a coarser spacing
+CPU_SMALL = {"mixer": ("make_mixer", {"dp": 0.0125}, "the mixer geometry at dp = 0.0125")}
+SWEEP = ("uchannel", "jet", "jet_640k", "jet_2560k")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="uchannel", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="mixer", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the extra workloads (U-channel and the jet sizes)")
+    ap.add_argument("--sweep-steps", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -55,6 +80,11 @@ def parse():
     ap.add_argument("--jet-steps", type=int, default=20000,
                     help="advection steps of --laminar-jet (the mean is over the last quarter, "
                          "at most 5000)")
+    ap.add_argument("--config-run", choices=("jet", "uchannel_pressure"),
+                    help="run a configured workload for its stated steps in FP32-mixed and "
+                         "FP64 (transport-velocity shift --tvf-alpha) and print one JSON line")
+    ap.add_argument("--tvf-alpha", type=float, default=0.2)
+    ap.add_argument("--config-steps", type=int, default=0, help="--config-run steps (0: stated)")
     ap.add_argument("--obc-ablation", action="store_true",
                     help="only run the open-boundary ablation of Table 2 (Cases 1-4) on the "
                          "laminar channel and print its JSON line")
@@ -152,7 +182,8 @@ def summarize_traffic(args, cf, cw, bf, bw):
             "kernel": label, "FETCH_SIZE_KiB": round(f, 1), "WRITE_SIZE_KiB": round(w, 1),
             "bytes_per_launch": b}
         rows.append(f"| `{label}` | {f:.1f} | {w:.1f} | {b:,} |")
-    run = f"python bench.py --workload {args.workload} --steps 20 --warmup 5 --no-cpu --no-fp64 --no-adjoint"
+    run = (f"python bench.py --workload {args.workload} --steps {args.steps} --warmup "
+           f"{args.warmup} --no-cpu --no-fp64 --no-adjoint --no-sweep")
     cmds = [f"rocprofv3 --pmc FETCH_SIZE -d {cf} -o cf --output-format csv -- python bench.py --calibrate-copy 256",
             f"rocprofv3 --pmc WRITE_SIZE -d {cw} -o cw --output-format csv -- python bench.py --calibrate-copy 256",
             f"rocprofv3 --pmc FETCH_SIZE -d {bf} -o bf --output-format csv -- {run}",
@@ -166,6 +197,15 @@ def summarize_traffic(args, cf, cw, bf, bw):
                            "write_scale": round(ws, 5)},
            "commands": cmds, "kernels": kernels, "hashed_sources": list(TRAFFIC_SOURCES)}
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if os.path.exists(path):   # keep the other workloads' figures of the same sources
+        with open(path) as fh:
+            old = json.load(fh)
+        if old.get("source_hash") == rec["source_hash"]:
+            merged = dict(old.get("kernels", {}))
+            merged.update(kernels)
+            rec["kernels"] = merged
+            rec["commands_by_workload"] = dict(old.get("commands_by_workload", {}))
+    rec.setdefault("commands_by_workload", {})[args.workload] = cmds
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     md = os.path.join(ROOT, "profiles", f"hbm_traffic_{args.workload}_fp32.md")
@@ -314,11 +354,29 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
     xs = np.arange(10, 33) * D
     ny = int(round(2 * W / dp))
     acc, cnt = np.zeros((len(xs), ny)), np.zeros((len(xs), ny))
+    ids = [b.id for b in c.buffers]
+    inj, dele = np.zeros(len(ids), np.int64), np.zeros(len(ids), np.int64)
+    n_real0 = sph.sph_get_count(g.ctx)[1]
     t0 = time.perf_counter()
     for k in range(steps):
-        g.advance()
+        try:
+            _, cn = g.advance()
+        except sph.SphError as e:
+            st = g.state()
+            real = (st["tag"] & 3) <= 1
+            return {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
+                             f"tvf_alpha {c.params['tvf_alpha']}",
+                    "failed_at_step": k + 1, "t": round(sph.sph_get_clock(g.ctx)[1], 3),
+                    "error": str(e), "real_particles": [int(n_real0), int(real.sum())],
+                    "buffers": {str(b): {"injected": int(i), "deleted": int(d)}
+                                for b, i, d in zip(ids, inj, dele)},
+                    "seconds": round(time.perf_counter() - t0, 1)}
+        for q, b in enumerate(ids):
+            inj[q] += cn.n_inject[b]
+            dele[q] += cn.n_delete[b]
         if (k + 1) % 4000 == 0:
-            print(f"laminar jet: step {k + 1} of {steps}", file=sys.stderr, flush=True)
+            print(f"laminar jet: step {k + 1} of {steps}, real particles "
+                  f"{sph.sph_get_count(g.ctx)[1]}", file=sys.stderr, flush=True)
         if k < steps - navg or k % 10:
             continue
         st = g.state()
@@ -333,7 +391,10 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
     head = {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
                      f"tvf_alpha {c.params['tvf_alpha']}, {steps} steps (t = "
                      f"{sph.sph_get_clock(g.ctx)[1]:.0f}), mean of the last {navg}",
-            "ms_per_step": round(1e3 * secs / max(steps, 1), 4)}
+            "ms_per_step": round(1e3 * secs / max(steps, 1), 4),
+            "real_particles": [int(n_real0), int(sph.sph_get_count(g.ctx)[1])],
+            "buffers": {str(b): {"injected": int(i), "deleted": int(d)}
+                        for b, i, d in zip(ids, inj, dele)}}
     u = acc / np.maximum(cnt, 1)
     yc = -W + (np.arange(ny) + 0.5) * dp
     uc = u[:, np.abs(yc) < dp].mean(axis=1)
@@ -377,57 +438,225 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
             "seconds": round(secs, 1)}
 
 
-def fp32_error(r32, case):
-    """Stated error of the FP32-mixed path: its pair operators (pressure and
-    viscous accelerations, continuity rate, B, p; with turbulence also the
-    velocity gradient and the k, epsilon rates) against the FP64 path's on
-    one state, the one the timed FP32-mixed run ended in; normwise relative
-    differences, matched by particle id.  The FP64 path matches the FP64
-    oracle to 1e-12 in the parity tests."""
-    import dataclasses
+CONFIG_RUNS = {
+    # name: (case builder taking the shift coefficient, configured steps, bin box, label)
+    "jet": (lambda a: cases_mod().make_jet(tvf_alpha=a), 5000, ((0.0, 20.0), (-10.0, 10.0)),
+            "2D turbulent plane jet, k-eps, 160k particles, Re 1e4, six buffers, 5000 steps"),
+    "uchannel_pressure": (lambda a: cases_mod().make_uchannel(inlet="pressure", tvf_alpha=a),
+                          2000, ((0.0, 17.3), (0.0, 4.0)),
+                          "2D U-channel, p = 1 pressure inlet, p = 0 outlet, Re 50, 2000 steps"),
+}
+
+
+def config_run(name, alpha, steps, torch, nbins=40, navg=1000):
+    """A configured workload run for its stated number of steps in FP32-mixed
+    and in FP64 on the GPU, each stopping at the first numerical error.  The
+    real particles' velocity, pressure (and k, epsilon) are averaged on a
+    nbins x nbins grid over the last `navg` steps (every tenth step); the
+    FP32-mixed run's binned fields are compared with the FP64 run's (relative
+    L2 over the bins both runs fill)."""
     import numpy as np
     from paper_2510_25702_amd import sph
-    g = r32["sim"]
-    st = g.state()
-    step, t, npid = sph.sph_get_clock(g.ctx)
-    c = dataclasses.replace(case, x=st["x"], v=st["v"], rho=st["rho"], drho=st["drho"],
-                            k=st["k"], eps=st["eps"], tag=st["tag"], pid=st["pid"],
-                            npid=int(npid), step=int(step), t=float(t))
-    fields = ("ap", "anu", "drho", "B", "p")
-    if case.params["turbulence"]:
-        fields += ("gradv", "dk", "deps")
-    res = {}
-    for prec in (sph.SPH_FP64, sph.SPH_FP32_MIXED):
-        s = sph.Simulation(c, precision=prec)
-        s.build_cells()
-        s.correction()
-        r = s.rates()
-        order = np.argsort(s.state()["pid"])
-        res[prec] = {f: np.asarray(r[f])[order] for f in fields}
-        del s
-    out = {"state": f"end of the timed FP32-mixed run (step {step})",
-           "norm": "max |FP32-mixed - FP64| / max |FP64| per operator"}
-    for f in fields:
-        a, b = res[sph.SPH_FP32_MIXED][f], res[sph.SPH_FP64][f]
-        den = float(np.abs(b).max())
-        out[f] = float(f"{np.abs(a - b).max() / den:.3g}") if den > 0 else 0.0
+    make, nsteps, box, label = CONFIG_RUNS[name]
+    steps = steps or nsteps
+    navg = min(navg, steps // 2)
+    out = {"workload": name, "description": label, "tvf_alpha": alpha, "steps": steps,
+           "averaged_steps": navg}
+    fields = {}
+    for prec, key in ((sph.SPH_FP32_MIXED, "fp32_mixed"), (sph.SPH_FP64, "fp64")):
+        case = make(alpha)
+        P = case.params
+        g = sph.Simulation(case, precision=prec)
+        g.build_cells()
+        g.buffer_update()
+        n0 = sph.sph_get_count(g.ctx)[1]
+        ids = [b.id for b in case.buffers]
+        inj, dele = np.zeros(len(ids), np.int64), np.zeros(len(ids), np.int64)
+        acc = {f: np.zeros((nbins, nbins)) for f in ("u", "v", "p", "k", "eps")}
+        cnt = np.zeros((nbins, nbins))
+        rec = {}
+        t0 = time.perf_counter()
+        for k in range(steps):
+            try:
+                _, cn = g.advance()
+            except sph.SphError as e:
+                rec["failed_at_step"] = k + 1
+                rec["error"] = str(e)
+                break
+            for q, b in enumerate(ids):
+                inj[q] += cn.n_inject[b]
+                dele[q] += cn.n_delete[b]
+            if k >= steps - navg and k % 10 == 0:
+                st = g.state()
+                real = (st["tag"] & 3) <= 1
+                x, v = st["x"][real], st["v"][real]
+                kk, ee, rho = st["k"][real], st["eps"][real], st["rho"][real]
+                p = P["rho0"] * P["c0"] ** 2 * (rho / P["rho0"] - 1.0)
+                if P["turbulence"]:
+                    p = p + 2.0 / 3.0 * rho * kk
+                ix = np.floor((x[:, 0] - box[0][0]) / (box[0][1] - box[0][0]) * nbins).astype(int)
+                iy = np.floor((x[:, 1] - box[1][0]) / (box[1][1] - box[1][0]) * nbins).astype(int)
+                ok = (ix >= 0) & (ix < nbins) & (iy >= 0) & (iy < nbins)
+                for f, val in (("u", v[:, 0]), ("v", v[:, 1]), ("p", p), ("k", kk),
+                               ("eps", ee)):
+                    np.add.at(acc[f], (ix[ok], iy[ok]), val[ok])
+                np.add.at(cnt, (ix[ok], iy[ok]), 1)
+            if (k + 1) % 1000 == 0:
+                print(f"{name} {key}: step {k + 1} of {steps}", file=sys.stderr, flush=True)
+        secs = time.perf_counter() - t0
+        step, t, _ = sph.sph_get_clock(g.ctx)
+        rec.update(steps_done=int(step), t=round(float(t), 4), seconds=round(secs, 1),
+                   real_particles=[int(n0), int(sph.sph_get_count(g.ctx)[1])],
+                   buffers={str(b): {"injected": int(i), "deleted": int(d)}
+                            for b, i, d in zip(ids, inj, dele)})
+        out[key] = rec
+        if "failed_at_step" not in rec:
+            fields[key] = ({f: a / np.maximum(cnt, 1) for f, a in acc.items()}, cnt > 0)
+        del g
+    if len(fields) == 2:
+        (a, ma), (b, mb) = fields["fp32_mixed"], fields["fp64"]
+        m = ma & mb
+        err = {}
+        for f in ("u", "v", "p", "k", "eps"):
+            den = float(np.sqrt(np.mean(b[f][m] ** 2)))
+            if den > 0:
+                err[f] = float(f"{np.sqrt(np.mean((a[f][m] - b[f][m]) ** 2)) / den:.3g}")
+        out["fp32_vs_fp64_binned_fields"] = {"bins": f"{nbins}x{nbins}", "filled": int(m.sum()),
+                                             "rel_L2": err}
     return out
 
 
-def roofline(stats):
-    dom = max(("pressure", "density", "advection", "correction", "cells"),
-              key=lambda k: stats[k].total_ms)
+def _state_case(g, case):
+    import dataclasses
+    from paper_2510_25702_amd import sph
+    st = g.state()
+    step, t, npid = sph.sph_get_clock(g.ctx)
+    return dataclasses.replace(case, x=st["x"], v=st["v"], rho=st["rho"], drho=st["drho"],
+                               k=st["k"], eps=st["eps"], tag=st["tag"], pid=st["pid"],
+                               npid=int(npid), step=int(step), t=float(t))
+
+
+def stated_error(r32, case, threads):
+    """Stated error of each GPU path against the FP64 oracle on one state,
+    the one the timed FP32-mixed run ended in: the pair operators (pressure
+    and viscous accelerations, continuity rate, correction matrix; with
+    turbulence the velocity gradient and the k, epsilon rates) of the
+    FP32-mixed and the FP64 path, normwise (max |GPU - oracle| / max |oracle|),
+    matched by particle id.  Up to 300k particles the oracle evaluates every
+    particle; above, a sample of 96 fluid particles away from the buffers,
+    each with everything within 4h + 2dp of it (its neighbours and theirs)."""
+    import dataclasses
+    import numpy as np
+    import oracle
+    from paper_2510_25702_amd import sph
+    c = _state_case(r32["sim"], case)
+    fields = ["ap", "anu", "drho", "B"]
+    if case.params["turbulence"]:
+        fields += ["gradv", "dk", "deps"]
+    h, dp = c.params["h"], c.params["dp"]
+    if c.n <= 300000:
+        sub, picks = c, np.nonzero((c.tag & 3) != cases_mod().WALL)[0]
+        sample = f"all {len(picks)} real particles"
+    else:
+        from scipy.spatial import cKDTree
+        cm = cases_mod()
+        far = np.ones(c.n, bool)
+        for b in c.buffers:
+            R = np.array(b.frame, float).reshape(3, 3)
+            y = (c.x - np.array(b.origin, float)) @ R.T
+            hw = list(b.half_width) + [0.0]
+            inside = (y[:, 0] > -10 * h) & (y[:, 0] < b.length + b.fringe + 10 * h)
+            for k in range(1, c.params["dim"]):
+                inside &= np.abs(y[:, k]) < hw[k - 1] + 10 * h
+            far &= ~inside
+        cand = np.nonzero(((c.tag & 3) == cm.FLUID) & far)[0]
+        picks = np.random.default_rng(5).choice(cand, 96, replace=False)
+        near = np.unique(np.concatenate(cKDTree(c.x).query_ball_point(c.x[picks],
+                                                                       4 * h + 2 * dp)))
+        sub = dataclasses.replace(c, x=c.x[near].copy(), v=c.v[near].copy(),
+                                  rho=c.rho[near].copy(), k=c.k[near].copy(),
+                                  eps=c.eps[near].copy(), tag=c.tag[near].copy(),
+                                  pid=c.pid[near].copy(), drho=c.drho[near].copy())
+        sample = (f"96 fluid particles away from the buffers, the oracle on their "
+                  f"{len(near)}-particle neighbourhoods")
+    ref = oracle.OracleSim(sub, threads=threads)
+    Bo, _ = ref.correction()
+    ro = ref.rates(Bo)
+    ro["B"] = Bo
+    si = {int(p): i for i, p in enumerate(sub.pid)}
+    io = np.array([si[int(c.pid[p])] for p in picks])
+    out = {"state": f"end of the timed FP32-mixed run (step {c.step})", "sample": sample,
+           "norm": "max |GPU - FP64 oracle| / max |FP64 oracle| per operator"}
+    for prec, key in ((sph.SPH_FP32_MIXED, "fp32_mixed"), (sph.SPH_FP64, "fp64")):
+        g = sph.Simulation(c, precision=prec)
+        g.build_cells()
+        g.correction()
+        r = g.rates()
+        gi = {int(p): i for i, p in enumerate(g.state()["pid"])}
+        ig = np.array([gi[int(c.pid[p])] for p in picks])
+        e = {}
+        for f in fields:
+            a, b = np.asarray(r[f])[ig], np.asarray(ro[f])[io]
+            den = float(np.abs(b).max())
+            e[f] = float(f"{np.abs(a - b).max() / den:.3g}") if den > 0 else 0.0
+        out[key] = e
+        del g
+    return out
+
+
+def cases_mod():
+    import cases
+    return cases
+
+
+def walked_pairs(g):
+    """Directed pairs within 2h that one pair pass visits at the current
+    state (sph_step_pairs' count over the real particles)."""
+    import ctypes as C
+    from paper_2510_25702_amd import sph
+    torch = g.torch
+    row = torch.zeros(g.n + 1, dtype=torch.int32, device=g.device)
+    n = C.c_int64()
+    st = sph.lib().sph_step_pairs(g.ctx, C.c_void_p(row.data_ptr()), None, 0, C.byref(n))
+    if st not in (sph.SPH_OK, sph.SPH_E_CAPACITY):
+        raise sph.SphError(st, "sph_step_pairs")
+    return int(n.value)
+
+
+def roofline(stats, dim, prec, pairs_per_launch, n_slots, turb):
+    """Roofline of the dominant neighbour pass (most kernel time per step):
+    its algorithmic bytes per launch (bytes per particle x the particle
+    slots one launch processes) and flops per launch (flops per pair x the
+    directed pairs within 2h it visits), over its average launch duration
+    (HIP events recorded by the launch at the kernel's start and end on the
+    library's stream).  Bound: the VALU when the arithmetic intensity is
+    above the ridge point (peak flops / 8 TB/s), else HBM; both fractions are
+    given."""
+    passes = ("pressure", "density", "advection", "correction")
+    dom = max(passes, key=lambda k: stats[k].total_ms)
     s = stats[dom]
-    # the neighbour passes' events are recorded by their launches at the
-    # kernel's own start and end
-    avg_ms = s.total_ms / max(1, s.launches)
-    bytes_per_launch = s.bytes / max(1, s.launches)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return dom, dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                     kernel=dom, avg_launch_us=round(avg_ms * 1e3, 3),
-                     algorithmic_bytes_per_launch=int(bytes_per_launch),
-                     launches=int(s.launches))
+    avg_s = s.total_ms * 1e-3 / max(1, s.launches)
+    pi = 0 if prec == "fp32" else 1
+    bpp = ALGO_BYTES[(dom, dim)][pi] + (20 if (turb and dom == "advection") else 0)
+    fpp = FLOPS_PER_PAIR[dom][0 if dim == 2 else 1] + (20 if (turb and dom == "advection") else 0)
+    nbytes = bpp * n_slots
+    flops = fpp * pairs_per_launch
+    gbs = nbytes / avg_s / 1e9
+    tfs = flops / avg_s / 1e12
+    peak_f = VALU_PEAK_TFLOPS[prec]
+    ai = flops / nbytes
+    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+    hbm = dict(achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(gbs / HBM_PEAK_GBS, 4))
+    alu = dict(achieved=round(tfs, 3), peak=peak_f, unit="TFLOP/s", frac=round(tfs / peak_f, 4))
+    main, other = (dict(bound="alu", **alu), dict(hbm=hbm)) if ai > ridge else \
+        (dict(bound="hbm", **hbm), dict(alu=alu))
+    return dom, dict(main, traffic=None, kernel=dom, avg_launch_us=round(avg_s * 1e6, 3),
+                     launches=int(s.launches), algorithmic_bytes_per_launch=int(nbytes),
+                     bytes_per_particle=bpp, particles_per_launch=int(n_slots),
+                     flops_per_launch=int(flops), flops_per_pair=fpp,
+                     pairs_per_launch=int(pairs_per_launch),
+                     arithmetic_intensity=round(ai, 2), ridge=round(ridge, 2), **other)
 
 
 def _adjoint_run(case, precision, steps, K, torch):
@@ -520,11 +749,22 @@ def recorded_traffic(workload, kernel, precision):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def cpu_baseline(case, seconds):
+def oracle_threads():
+    """Host threads for the oracle: the cores this process may run on, at
+    most OMP_NUM_THREADS when that is set (the host's share for one GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(case, seconds, threads, what):
+    """The FP64 oracle timed on the host: advection steps of `case` from its
+    initial state, each followed by its buffer update, until `seconds` have
+    passed (at least one); particle-steps/s over the real particles."""
     import oracle
-    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    nthreads = max(1, min(nthreads, 16))
-    s = oracle.OracleSim(case, threads=nthreads)
+    s = oracle.OracleSim(case, threads=threads)
     s.buffer_update()
     t0 = time.perf_counter()
     psteps = 0
@@ -537,9 +777,42 @@ def cpu_baseline(case, seconds):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
-    return dict(value=round(psteps / dt, 1), unit="particle-steps/s", cores=nthreads,
-                kind="oracle", sample=f"first {k} advection steps (+ buffer updates) of the "
-                                      f"same workload from its initial state, {dt:.1f} s")
+    return dict(value=round(psteps / dt, 1), unit="particle-steps/s", cores=threads,
+                kind="oracle", sample=f"the first {k} advection step(s) (+ buffer updates) of "
+                                      f"{what} ({case.n} particles) from its initial state, "
+                                      f"{dt:.1f} s")
+
+
+def gpu_leg(case, precision, steps, warmup, torch):
+    """One timed run and its figures (value, ms per step, pairs/s, roofline)."""
+    from paper_2510_25702_amd import sph
+    r = run_gpu(case, precision, steps, warmup, torch)
+    g = r["sim"]
+    prec = "fp32" if precision == sph.SPH_FP32_MIXED else "fp64"
+    dom, roof = roofline(r["stats"], case.params["dim"], prec, walked_pairs(g), g.n,
+                         bool(case.params["turbulence"]))
+    return r, dict(value=round(r["particle_steps"] / r["seconds"], 1),
+                   ms_per_step=round(1e3 * r["seconds"] / steps, 4),
+                   pairs_per_s=round(r["pairs"] / r["seconds"], 1),
+                   acoustic_substeps=int(r["n_ac"]), roofline=roof)
+
+
+def sweep(names, steps, warmup, torch):
+    from paper_2510_25702_amd import sph
+    out = {}
+    for name in names:
+        case = make_case(name)
+        row = {"description": WORKLOADS[name][2], "particles_total": int(case.n),
+               "steps": steps}
+        for prec, key in ((sph.SPH_FP32_MIXED, "fp32_mixed"), (sph.SPH_FP64, "fp64")):
+            r, fig = gpu_leg(case, prec, steps, warmup, torch)
+            row[key] = fig
+            del r
+        row["fp32_over_fp64"] = round(row["fp32_mixed"]["value"] / row["fp64"]["value"], 3)
+        out[name] = row
+        print(f"sweep {name}: {row['fp32_mixed']['value']:.4g} / {row['fp64']['value']:.4g} "
+              f"particle-steps/s", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -574,23 +847,28 @@ def main():
                                                      precision=args.jet_precision)}),
               flush=True)
         return
+    if args.config_run:
+        print(json.dumps({"config_run": config_run(args.config_run, args.tvf_alpha,
+                                                    args.config_steps, torch)}), flush=True)
+        return
     if args.obc_ablation:
         print(json.dumps({"obc_ablation": obc_ablation(steps=6000, navg=2000)}), flush=True)
         return
     from paper_2510_25702_amd import sph
     case = make_case(args.workload)
-    r32 = run_gpu(case, sph.SPH_FP32_MIXED, args.steps, args.warmup, torch)
-    value = r32["particle_steps"] / r32["seconds"]
-    dom, roof = roofline(r32["stats"])
-    roof["traffic"] = recorded_traffic(args.workload, dom, "fp32")
+    r32, f32 = gpu_leg(case, sph.SPH_FP32_MIXED, args.steps, args.warmup, torch)
+    print(f"{args.workload} FP32-mixed: {f32['value']:.4g} particle-steps/s", file=sys.stderr,
+          flush=True)
+    roof = f32["roofline"]
+    roof["traffic"] = recorded_traffic(args.workload, roof["kernel"], "fp32")
     out = {
         "metric": "particle-steps/s + neighbor pairs/s, FP32-mixed vs FP64 at stated error",
-        "value": round(value, 1),
+        "value": f32["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
+        "ms_per_step": f32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -598,33 +876,44 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload][2],
                    "particles_real": int(r32["n_real"]), "particles_total": int(case.n),
-                   "precision": "fp32-mixed (f32 pair arithmetic; f64 density, position, "
-                                "correction inverse)",
-                   "acoustic_substeps": r32["n_ac"]},
-        "pairs_per_s": round(r32["pairs"] / r32["seconds"], 1),
+                   "precision": "fp32-mixed (f32 pair arithmetic with f64 pressure and "
+                                "continuity sums; f64 density, position, correction inverse)",
+                   "acoustic_substeps": f32["acoustic_substeps"]},
+        "pairs_per_s": f32["pairs_per_s"],
         "pairs_per_step": round(r32["pairs"] / args.steps, 1),
         "roofline": roof,
         "kernels_sampled_every": PROFILE_EVERY,
         "kernels": {k: {"ms": round(v.total_ms, 3), "launches": int(v.launches),
                         "avg_us": round(1e3 * v.total_ms / max(1, v.launches), 3),
-                        "GBps_algorithmic": round(v.bytes / max(1e-12, v.total_ms * 1e-3) / 1e9, 1)}
+                        "GBps_all_own_fields": round(v.bytes / max(1e-12, v.total_ms * 1e-3) / 1e9, 1)}
                     for k, v in r32["stats"].items() if v.launches},
     }
     if not args.no_fp64:
         steps64 = args.fp64_steps or args.steps
-        r64 = run_gpu(case, sph.SPH_FP64, steps64, args.warmup, torch)
-        v64 = r64["particle_steps"] / r64["seconds"]
-        _, roof64 = roofline(r64["stats"])
-        out["fp64"] = {"value": round(v64, 1), "unit": "particle-steps/s", "steps": steps64,
-                       "ms_per_step": round(1e3 * r64["seconds"] / steps64, 4),
-                       "pairs_per_s": round(r64["pairs"] / r64["seconds"], 1),
-                       "roofline": roof64}
-        out["fp32_over_fp64"] = round(value / v64, 3)
-    out["fp32_error_vs_fp64"] = fp32_error(r32, case)
+        r64, f64 = gpu_leg(case, sph.SPH_FP64, steps64, args.warmup, torch)
+        out["fp64"] = dict(f64, unit="particle-steps/s", steps=steps64)
+        out["fp32_over_fp64"] = round(f32["value"] / f64["value"], 3)
+        del r64
+    threads = oracle_threads()
+    out["stated_error_vs_fp64_oracle"] = stated_error(r32, case, threads)
+    del r32
+    if not args.no_sweep:
+        out["sweep"] = sweep([w for w in SWEEP if w != args.workload], args.sweep_steps,
+                             args.warmup, torch)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps, args.adjoint_checkpoint, torch)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_seconds)
+        big = args.workload in CPU_SMALL
+        cb = cpu_baseline(make_case(args.workload), 0.0 if big else args.cpu_seconds, threads,
+                          f"the {args.workload} workload")
+        if big:
+            gen, kw, what = CPU_SMALL[args.workload]
+            import cases
+            small = getattr(cases, gen)(**kw)
+        else:
+            small, what = make_case(args.workload), f"the {args.workload} workload"
+        cb["single_core"] = cpu_baseline(small, 0.0 if big else args.cpu_seconds, 1, what)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -227,7 +227,8 @@ def make_adjoint_channel(dp=None, seed=4, steps=100, n_coef=16, amp=0.1, length=
 # leg, both open faces at x = 0.
 # ----------------------------------------------------------------------------
 def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
-                  noise=1e-3, seed=1, steps=2000, ramp_time=5.0, inlet="velocity"):
+                  noise=1e-3, seed=1, steps=2000, ramp_time=5.0, inlet="velocity",
+                  tvf_alpha=0.0):
     """U-channel with legs of length Lleg joined by a 180-degree bend.
 
     The driving pressure drop p_in sets the Poiseuille estimate of the mean
@@ -245,6 +246,7 @@ def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
     nu = math.sqrt(G * H * H / (12.0 * Re))
     U = Re * nu / H
     P = base_params(2, dp, c0=c0, nu_l=nu, u_ref=U, seed=seed)
+    P["tvf_alpha"] = tvf_alpha
     ext = 4 * dp
     x0 = -ext
     span = lattice2(x0, Lleg + cy + H + 4 * dp, -4 * dp, 2 * cy + 4 * dp, dp)
