@@ -309,6 +309,23 @@ sph_status sph_eval_rates(sph_ctx* ctx, const sph_rates* out);
 sph_status sph_neighbors(sph_ctx* ctx, int32_t* row_ptr, int32_t* col,
                          int64_t cap, int64_t* n_pairs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * sph_neighbors with its scratch memory -- the per-particle neighbour counts
+ * and the partial sums of their scan -- in a device array of the library
+ * instead of the context's workspace.  The array holds
+ * SPH_NOALLOC_MAX_PARTICLES + 4096 int32 (16 MiB) per device, from the
+ * first sph_create on that device until the process ends; the call
+ * allocates nothing (the total is read back through the context's pinned
+ * buffer).  SPH_E_ARG when the context holds more than
+ * SPH_NOALLOC_MAX_PARTICLES particles.  Every call on one device shares the
+ * array: calls that overlap on a device (any context, any stream) race and
+ * must be serialised by the caller.  Otherwise as sph_neighbors (same
+ * results, same errors).  Synchronises. */
+#define SPH_NOALLOC_MAX_PARTICLES 4194304
+sph_status sph_neighbors_noalloc(sph_ctx* ctx, int32_t* row_ptr, int32_t* col, int64_t cap,
+                                 int64_t* n_pairs);
+
 /* The neighbour pairs that the pair passes of a step visit (Sec. 2.4.1: the
  * cell-linked list; the sums of Eqs. (equ-B-matrix), (eq-discretize-momentum-
  * p-RKGC), (discretize-continuity-equ-riemann) and (eq-discretize-momentum-

@@ -437,14 +437,19 @@ hipError_t get_impl(sph_ctx* c, const sph_particles* d) {
 
 }  // namespace
 
-hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) {
+hipError_t launch_scan_excl_part(sph_ctx* c, const int32_t* in, int n, int32_t* out,
+                                 int32_t* part) {
   const int nb = (n + kScanTile - 1) / kScanTile + (n == 0);
   if (nb > kScanTile) return hipErrorInvalidValue;
-  k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, c->S.block_sums, nullptr);
-  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(c->S.block_sums, nb, out, n, nullptr, nullptr);
-  k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(const_cast<int32_t*>(in), n, c->S.block_sums,
-                                                    out, 0, nullptr);
+  k_scan_reduce<<<nb, kScanThreads, 0, c->stream>>>(in, n, part, nullptr);
+  k_scan_parts<<<1, kScanThreads, 0, c->stream>>>(part, nb, out, n, nullptr, nullptr);
+  k_scan_apply<<<nb, kScanThreads, 0, c->stream>>>(const_cast<int32_t*>(in), n, part, out, 0,
+                                                    nullptr);
   return hipGetLastError();
+}
+
+hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out) {
+  return launch_scan_excl_part(c, in, n, out, c->S.block_sums);
 }
 
 hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n) {

@@ -11,9 +11,37 @@
 // the inversion of the correction matrix stay in FP64.  Every particle sums
 // its own neighbours (gather form) and the team reduces in a fixed order:
 // no floating-point atomics, results are deterministic.
+#include <mutex>
+
 #include "sph_pairs.h"
 
 namespace sphx {
+
+// Device memory of sph_neighbors_noalloc, for callers that cannot allocate:
+// per-particle neighbour counts and the partial sums of their scan.  One
+// copy per device, held until the process ends and shared by every call on
+// that device.  Host code uses its device address (noalloc_scratch_init),
+// never this name.
+constexpr int64_t kNoAllocMaxN = SPH_NOALLOC_MAX_PARTICLES;
+constexpr int64_t kNoAllocParts = 4096;   // scan tiles of 4096 counts
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxN + kNoAllocParts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = static_cast<int32_t*>(p);
+  return hipSuccess;
+}
 
 namespace {
 
@@ -1375,6 +1403,47 @@ hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update, bool keys
 }
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }
+
+hipError_t launch_neighbors_noalloc(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                                    int64_t* n_pairs) {
+  const int64_t n = c->n_total;
+  int32_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device >= 0 && c->device < kMaxDevices) base = g_scratch_dev[c->device];
+  }
+  if (!base || n > kNoAllocMaxN) return hipErrorInvalidValue;
+  int32_t* counts = base;                  // [n]
+  int32_t* part = base + kNoAllocMaxN;     // [kNoAllocParts]
+  const double rc = 2.0 * c->P.h;
+  const double rc2 = rc * rc;
+  Fields& F = c->F;
+  const int nb = nblk(n);
+  auto go = [&](auto dimtag, auto filltag, int32_t* row) {
+    constexpr int D = decltype(dimtag)::value;
+    constexpr int FL = decltype(filltag)::value;
+    k_neighbors<D, FL><<<nb, 256, 0, c->stream>>>(
+        (int)n, F.x[0].live(), F.x[1].live(), F.x[2].live(), F.cell, c->S.cell_start,
+        c->grid.n[0], c->grid.n[1], rc2, row, col, cap);
+  };
+  using D2 = std::integral_constant<int, 2>;
+  using D3 = std::integral_constant<int, 3>;
+  using F0 = std::integral_constant<int, 0>;
+  using F1 = std::integral_constant<int, 1>;
+  if (c->P.dim == 2) go(D2{}, F0{}, counts); else go(D3{}, F0{}, counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan_excl_part(c, counts, (int)n, row_ptr, part);
+  if (e != hipSuccess) return e;
+  int32_t* total = reinterpret_cast<int32_t*>(c->pinned);   // the context's pinned buffer
+  e = hipMemcpyAsync(total, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  *n_pairs = *total;
+  if (c->P.dim == 2) go(D2{}, F1{}, row_ptr); else go(D3{}, F1{}, row_ptr);
+  return hipGetLastError();
+}
 
 hipError_t launch_walk_pairs(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                              int64_t* n_pairs) {

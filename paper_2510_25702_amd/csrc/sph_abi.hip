@@ -492,6 +492,12 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   c->ws_bytes = ws_bytes;
   c->cap = params->capacity;
   (void)hipGetDevice(&c->device);
+  // the device address of the library's array for sph_neighbors_noalloc,
+  // taken once per device while it is current
+  if (noalloc_scratch_init(c->device) != hipSuccess) {
+    delete c;
+    return SPH_E_HIP;
+  }
   grid_of(params, &c->grid);
   if (const char* tl = std::getenv("SPHX_TEAM_LANES")) {   // tuning knob: 1, 2, 4 or 8
     int v = std::atoi(tl);
@@ -886,6 +892,21 @@ sph_status sph_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap
     return fail(c, SPH_E_STATE, "sph_neighbors needs a cell build after the last position change");
   HIPCHK(c, launch_neighbors(c, row_ptr, col, cap, n_pairs), "neighbors");
   HIPCHK(c, hipStreamSynchronize(c->stream), "neighbors sync");
+  if (*n_pairs > cap) return fail(c, SPH_E_CAPACITY, "neighbour list longer than cap");
+  return SPH_OK;
+}
+
+sph_status sph_neighbors_noalloc(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                                 int64_t* n_pairs) {
+  if (!c) return SPH_E_ARG;
+  if (!row_ptr || !n_pairs || cap < 0 || (cap > 0 && !col))
+    return fail(c, SPH_E_ARG, "bad neighbour arguments");
+  if (c->n_total > SPH_NOALLOC_MAX_PARTICLES)
+    return fail(c, SPH_E_ARG, "more particles than SPH_NOALLOC_MAX_PARTICLES");
+  if (!c->cells_valid || c->moved)
+    return fail(c, SPH_E_STATE, "sph_neighbors_noalloc needs a cell build after the last position change");
+  HIPCHK(c, launch_neighbors_noalloc(c, row_ptr, col, cap, n_pairs), "neighbors_noalloc");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "neighbors_noalloc sync");
   if (*n_pairs > cap) return fail(c, SPH_E_CAPACITY, "neighbour list longer than cap");
   return SPH_OK;
 }

@@ -168,8 +168,17 @@ hipError_t launch_buffer_undo(sph_ctx* c, bool all_slots);
 hipError_t launch_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                             int64_t* n_pairs);
 hipError_t launch_export_B(sph_ctx* c, double* B);
-// exclusive scan of n counts into out[0..n] (out[n] = total)
+// exclusive scan of n counts into out[0..n] (out[n] = total); the partial
+// sums of up to 4096 tiles in the workspace, or in `part`
 hipError_t launch_scan_excl(sph_ctx* c, const int32_t* in, int n, int32_t* out);
+hipError_t launch_scan_excl_part(sph_ctx* c, const int32_t* in, int n, int32_t* out,
+                                 int32_t* part);
+// The library's own device array of sph_neighbors_noalloc: its address on
+// `device` (the current device), taken once per device.
+hipError_t noalloc_scratch_init(int device);
+// sph_neighbors with its scratch in that array; synchronises
+hipError_t launch_neighbors_noalloc(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
+                                    int64_t* n_pairs);
 // the pairs the pair passes visit (CSR in the current order); synchronises
 // once to read the total
 hipError_t launch_walk_pairs(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,

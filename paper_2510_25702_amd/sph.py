@@ -125,6 +125,8 @@ EXPORTS = {
                                 C.POINTER(C.c_int64)]),
     "sph_step_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_int64)]),
+    "sph_neighbors_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.POINTER(C.c_int64)]),
     "sph_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sph_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sph_kernel_stats)]),
     "sph_pair_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -249,6 +251,13 @@ def sph_neighbors(ctx, row_ptr, col_ptr, cap):
     n = C.c_int64()
     _check(ctx, lib().sph_neighbors(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
                                     C.byref(n)))
+    return n.value
+
+
+def sph_neighbors_noalloc(ctx, row_ptr, col_ptr, cap):
+    n = C.c_int64()
+    _check(ctx, lib().sph_neighbors_noalloc(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
+                                            C.byref(n)))
     return n.value
 
 
