@@ -207,6 +207,35 @@ const char* sph_last_error(const sph_ctx* ctx);
 sph_status sph_set_particles(sph_ctx* ctx, int64_t n, uint64_t next_pid,
                              const sph_particles* src);
 
+/* Zero-copy access to the particle arrays (Sec. 2.4.3: particles are
+ * appended and overwritten in place in preallocated arrays).  Field ids of
+ * sph_field_offset and their element types. */
+enum { SPH_FIELD_X0 = 0, SPH_FIELD_X1 = 1, SPH_FIELD_X2 = 2, SPH_FIELD_V0 = 3,
+       SPH_FIELD_V1 = 4, SPH_FIELD_V2 = 5, SPH_FIELD_RHO = 6, SPH_FIELD_DRHO = 7,
+       SPH_FIELD_K = 8, SPH_FIELD_EPS = 9, SPH_FIELD_TAG = 10, SPH_FIELD_PID = 11,
+       SPH_FIELD_COUNT = 12 };
+enum { SPH_DTYPE_F64 = 0, SPH_DTYPE_F32 = 1, SPH_DTYPE_U32 = 2 };
+
+/* Byte offset, inside the workspace given to sph_create, of the live array
+ * of `field` (capacity entries in the library's current particle order) and
+ * its element type: FP64 for positions and density; the pair precision
+ * (SPH_DTYPE_F64, or SPH_DTYPE_F32 in SPH_FP32_MIXED contexts) for velocity,
+ * continuity rate, k and epsilon; uint32 for tags and ids.  The caller may
+ * wrap the array in a tensor view and read or write particles in place.  An
+ * offset holds until the next call that builds cells, steps, updates the
+ * buffers, advances or sets particles (they move the live arrays between two
+ * slots): take it again after any of them.  SPH_E_ARG for an unknown field. */
+sph_status sph_field_offset(const sph_ctx* ctx, int32_t field, size_t* offset, int32_t* dtype);
+
+/* Declares that the caller has written n_total particles (<= capacity) into
+ * the live arrays of sph_field_offset, and sets the id of the next injected
+ * particle: the library derives the eddy viscosity C_mu k^2 / epsilon
+ * (Table 1) from the k and epsilon written, counts the real particles and
+ * invalidates the cell list -- what sph_set_particles does after its copy.
+ * SPH_E_ARG (nothing changed) for a count out of range or a buffer particle
+ * whose tag names no configured buffer.  Synchronises. */
+sph_status sph_set_count(sph_ctx* ctx, int64_t n_total, uint64_t next_pid);
+
 /* Number of particle slots currently used (n_total includes particles
  * tagged SPH_DEAD by the last buffer update until the next cell build) and
  * of real (fluid + buffer) particles. */

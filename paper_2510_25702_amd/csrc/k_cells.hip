@@ -38,12 +38,25 @@ __global__ void k_set_particles(int n, const double* __restrict__ x, const doubl
   V2[i] = (T)v[2 * n + i];
   R[i] = rho[i];
   DR[i] = drho ? (T)drho[i] : T(0);
-  double k = (turb && kk) ? kk[i] : 0.0, e = (turb && ee) ? ee[i] : 0.0;
+  // nu_t of the stored (pair-precision) k and epsilon, as k_derive_nut
+  const double k = (double)(T)((turb && kk) ? kk[i] : 0.0);
+  const double e = (double)(T)((turb && ee) ? ee[i] : 0.0);
   K[i] = (T)k;
   E[i] = (T)e;
   NT[i] = (T)((turb && e > 0.0) ? Cmu * k * k / e : 0.0);
   TG[i] = tag[i];
   PD[i] = pid[i];
+}
+
+// Eddy viscosity of particles written in place: C_mu k^2 / epsilon from the
+// stored k and epsilon (as k_set_particles computes it from its inputs).
+template <typename T>
+__global__ void k_derive_nut(int n, const T* __restrict__ K, const T* __restrict__ E,
+                             T* __restrict__ NT, double Cmu, int turb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double k = turb ? (double)K[i] : 0.0, e = turb ? (double)E[i] : 0.0;
+  NT[i] = (T)((turb && e > 0.0) ? Cmu * k * k / e : 0.0);
 }
 
 template <typename T>
@@ -299,7 +312,7 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     a.xo[k][d] = xv[k];
-    double org = (k < DIM) ? a.g.lo[k] + (double)cc[k] * a.g.cs : 0.0;
+    double org = (k < DIM) ? cell_centre(a.g.lo[k], cc[k], a.g.cs) : 0.0;
     xr[k] = (T)(xv[k] - org);
     a.xro[k][d] = xr[k];
     a.vo[k][d] = vr[k];
@@ -460,6 +473,22 @@ hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n) {
 
 hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src) {
   return c->P.precision == SPH_FP64 ? set_impl<double>(c, n, src) : set_impl<float>(c, n, src);
+}
+
+hipError_t launch_derive_nut(sph_ctx* c, int64_t n) {
+  Fields& F = c->F;
+  const int nb = (int)((n + 255) / 256) + (n == 0);
+  if (c->P.precision == SPH_FP64)
+    k_derive_nut<double><<<nb, 256, 0, c->stream>>>((int)n, tp<double>(F.k.live()),
+                                                     tp<double>(F.eps.live()),
+                                                     tp<double>(F.nut.live()), c->P.Cmu,
+                                                     c->P.turbulence);
+  else
+    k_derive_nut<float><<<nb, 256, 0, c->stream>>>((int)n, tp<float>(F.k.live()),
+                                                    tp<float>(F.eps.live()),
+                                                    tp<float>(F.nut.live()), c->P.Cmu,
+                                                    c->P.turbulence);
+  return hipGetLastError();
 }
 
 hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst) {

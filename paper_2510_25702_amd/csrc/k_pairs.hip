@@ -427,7 +427,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   // first half density update of the first acoustic sub-step
   const double rho_h = rho_i + a.half_dt * (double)drho_i;
   a.rho[i] = rho_h;
-  const T p_h = (T)eos(rho_h, k_new, C.rho0, C.c0, TURB);
+  const T p_h = (T)eos(rho_h, (double)(T)k_new, C.rho0, C.c0, TURB);
   const T v_h = (T)(C.mass / rho_h);
   a.p_out[i] = p_h;
   a.vol_out[i] = v_h;
@@ -451,6 +451,7 @@ __global__ __launch_bounds__(256) void k_advection(int n, PairCtx<T> pc, Consts<
 template <typename T>
 struct PressArgs {
   const T *p;
+  const T* k;               // turbulent kinetic energy (p_eff of the records)
   const double* rho;
   const T* B[6];
   T* v[3];
@@ -529,12 +530,23 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
-    const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+    T gW[3];
+    if constexpr (f64_kernel<T, DIM>()) {
+      double rr;
+      const double fd = dw_over_r_d<T>(r, C.inv_h_d, C.kf_d, &rr);
+      gW[0] = (T)(fd * (double)r[0]);
+      gW[1] = (T)(fd * (double)r[1]);
+      gW[2] = T(0);
+    } else {
+      const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+      gW[0] = f * r[0];
+      gW[1] = f * r[1];
+      gW[2] = DIM == 3 ? f * r[2] : T(0);
+    }
     const T volw = DIM == 2 ? q[0].d : q[1].a;
     const bool wall = volw < T(0);
     const T Vj = wall ? -volw : volw;
     const T pj_rec = DIM == 2 ? q[0].c : q[0].d;
-    const T gW[3] = {f * r[0], f * r[1], DIM == 3 ? f * r[2] : T(0)};
     if (MODE >= 2) {
       // (p_i B_j + p_j B_i) gradW; wall: p_w = p_i, B_w = B_i
       T Bj[6];
@@ -621,8 +633,8 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       a.v[k][i] = vt;
       const double xn = xd[k] + a.dt * (double)vt;
       a.xo[k][i] = xn;
-      const double rel = xn - (C.grid.lo[k] + (double)cc3[k] * C.grid.cs);
-      if (!(rel >= -C.skin && rel <= C.grid.cs + C.skin)) bad = true;
+      const double rel = xn - cell_centre(C.grid.lo[k], cc3[k], C.grid.cs);
+      if (!(fabs(rel) <= 0.5 * C.grid.cs + C.skin)) bad = true;
       if (a.xrb[0]) {
         const double dd = rel - (double)xrb_i[k];
         d2 += dd * dd;
@@ -636,7 +648,11 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       xnew[k] = xr_i[k];
     }
   }
-  write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, vol_i);
+  T plo = T(0);   // the FP64 remainder of p_i (2D FP32: continuity pressure differences)
+  if constexpr (f64_kernel<T, DIM>())
+    plo = (T)(eos(rho_i, C.turbulence ? (double)a.k[i] : 0.0, C.rho0, C.c0, C.turbulence) -
+              (double)pi);
+  write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, vol_i, plo);
   if (a.xrb[0] && !(d2 <= C.skin * C.skin)) atomicOr(a.stale_w, 1u);
   if (bad) atomicOr(a.flags, kFlagSkin);
   return m_pairs;
@@ -694,6 +710,11 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       // wide teams, after the sum by narrow ones
       const bool next = !a.rates_only && !a.last;
       double rho_i = 0.0, k_i = 0.0;
+      // 2D FP32: p_i in FP64 from the density it came from (Eq. eos), so
+      // that p_i - p_j keeps its digits with the record's p + p_lo
+      double pid = 0.0;
+      if constexpr (f64_kernel<T, DIM>())
+        pid = eos(a.rho[i], C.turbulence ? (double)a.k[i] : 0.0, C.rho0, C.c0, C.turbulence);
       T Bw[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
       auto load_update = [&]() {
         rho_i = a.rho[i];
@@ -722,7 +743,10 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
           const T pj = DIM == 2 ? q[1].a : q[1].c;
           vr = (vi[0] - vj0) * r[0] + (vi[1] - vj1) * r[1] +
                (DIM == 3 ? (vi[2] - vj2) * r[2] : T(0));
-          dp = pi - pj;
+          if constexpr (f64_kernel<T, DIM>())
+            dp = (T)(pid - ((double)pj + (double)q[1].c));
+          else
+            dp = pi - pj;
         }
         sum += (double)(Vj * f * (T(0.5) * vr + dp * C.inv_2rc0_t * rr));
         ++m;
@@ -799,7 +823,7 @@ __global__ void k_prepare_pv(int n, Consts<T> C, PvArgs<T> a) {
   load_B<T, DIM>(a.B, i, B);
   const T v[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
   write_prec<T, DIM>(a.prec, i, x, pt, vt, B);
-  write_drec<T, DIM>(a.drec, i, x, v, pt, vt);
+  write_drec<T, DIM>(a.drec, i, x, v, pt, vt, f64_kernel<T, DIM>() ? (T)(pp - (double)pt) : T(0));
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,6 +1202,7 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
   Fields& F = c->F;
   PressArgs<T> a;
   a.p = tp<T>(F.p.live());
+  a.k = tp<T>(F.k.live());
   a.rho = F.rho.live();
   for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(F.B[k]);
   for (int k = 0; k < 3; ++k) {

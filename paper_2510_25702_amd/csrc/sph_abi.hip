@@ -653,29 +653,28 @@ sph_status sph_destroy(sph_ctx* c) {
 
 const char* sph_last_error(const sph_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
 
-sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph_particles* src) {
-  if (!c) return SPH_E_ARG;
-  if (!src || n < 0 || n > c->cap) return fail(c, SPH_E_ARG, "bad particle count or source");
-  if (n > 0 && (!src->x || !src->v || !src->rho || !src->tag || !src->pid))
-    return fail(c, SPH_E_ARG, "x, v, rho, tag and pid are required");
-  if (c->P.turbulence && n > 0 && (!src->k || !src->eps))
-    return fail(c, SPH_E_ARG, "k and eps are required with turbulence");
-  // the tags on the host first: a buffer particle must name a configured
-  // buffer (Sec. 3.2), checked before anything is written; also the counts
-  // of walls and real particles
-  std::vector<uint32_t> tags((size_t)n);
+// Tags of n particles read to the host and checked: a buffer particle must
+// name a configured buffer (Sec. 3.2).  Nothing is written.
+sph_status read_tags(sph_ctx* c, const uint32_t* tag_dev, int64_t n, std::vector<uint32_t>* tags) {
+  tags->assign((size_t)n, 0u);
   if (n > 0) {
-    HIPCHK(c, hipMemcpyAsync(tags.data(), src->tag, n * 4, hipMemcpyDeviceToHost, c->stream),
-           "set_particles tags");
-    HIPCHK(c, hipStreamSynchronize(c->stream), "set_particles tags sync");
+    HIPCHK(c, hipMemcpyAsync(tags->data(), tag_dev, n * 4, hipMemcpyDeviceToHost, c->stream),
+           "tags");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "tags sync");
   }
-  for (auto t : tags) {
+  for (auto t : *tags) {
     if (tag_kind(t) != kBuffer) continue;
     bool known = false;
     for (int q = 0; q < c->nbuf; ++q) known |= c->bufs_h[q].id == (int32_t)tag_bid(t);
     if (!known) return fail(c, SPH_E_ARG, "a buffer particle names an unknown buffer id");
   }
-  HIPCHK(c, launch_set_particles(c, n, src), "set_particles");
+  return SPH_OK;
+}
+
+// The state after n particles were written into the live arrays: next id,
+// cleared flags, counts, invalid cell list.
+sph_status adopt_particles(sph_ctx* c, int64_t n, uint64_t next_pid,
+                           const std::vector<uint32_t>& tags) {
   uint64_t np = next_pid;
   HIPCHK(c, hipMemcpyAsync(c->S.next_pid, &np, 8, hipMemcpyHostToDevice, c->stream), "next_pid");
   HIPCHK(c, hipMemsetAsync(c->S.flags, 0, 4, c->stream), "flags");
@@ -694,6 +693,54 @@ sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph
   c->B_valid = false;
   c->moved = false;
   return SPH_OK;
+}
+
+sph_status sph_set_particles(sph_ctx* c, int64_t n, uint64_t next_pid, const sph_particles* src) {
+  if (!c) return SPH_E_ARG;
+  if (!src || n < 0 || n > c->cap) return fail(c, SPH_E_ARG, "bad particle count or source");
+  if (n > 0 && (!src->x || !src->v || !src->rho || !src->tag || !src->pid))
+    return fail(c, SPH_E_ARG, "x, v, rho, tag and pid are required");
+  if (c->P.turbulence && n > 0 && (!src->k || !src->eps))
+    return fail(c, SPH_E_ARG, "k and eps are required with turbulence");
+  std::vector<uint32_t> tags;
+  sph_status st = read_tags(c, src->tag, n, &tags);   // before anything is written
+  if (st != SPH_OK) return st;
+  HIPCHK(c, launch_set_particles(c, n, src), "set_particles");
+  return adopt_particles(c, n, next_pid, tags);
+}
+
+sph_status sph_field_offset(const sph_ctx* c, int32_t field, size_t* offset, int32_t* dtype) {
+  if (!c || !offset || !dtype) return SPH_E_ARG;
+  const Fields& F = c->F;
+  const int32_t pt = c->P.precision == SPH_FP64 ? SPH_DTYPE_F64 : SPH_DTYPE_F32;
+  const void* p = nullptr;
+  int32_t t = SPH_DTYPE_F64;
+  switch (field) {
+    case SPH_FIELD_X0: case SPH_FIELD_X1: case SPH_FIELD_X2:
+      p = F.x[field - SPH_FIELD_X0].live(); break;
+    case SPH_FIELD_V0: case SPH_FIELD_V1: case SPH_FIELD_V2:
+      p = F.v[field - SPH_FIELD_V0].live(); t = pt; break;
+    case SPH_FIELD_RHO: p = F.rho.live(); break;
+    case SPH_FIELD_DRHO: p = F.drho.live(); t = pt; break;
+    case SPH_FIELD_K: p = F.k.live(); t = pt; break;
+    case SPH_FIELD_EPS: p = F.eps.live(); t = pt; break;
+    case SPH_FIELD_TAG: p = F.tag.live(); t = SPH_DTYPE_U32; break;
+    case SPH_FIELD_PID: p = F.pid.live(); t = SPH_DTYPE_U32; break;
+    default: return SPH_E_ARG;
+  }
+  *offset = (size_t)((const char*)p - c->ws);
+  *dtype = t;
+  return SPH_OK;
+}
+
+sph_status sph_set_count(sph_ctx* c, int64_t n_total, uint64_t next_pid) {
+  if (!c) return SPH_E_ARG;
+  if (n_total < 0 || n_total > c->cap) return fail(c, SPH_E_ARG, "bad particle count");
+  std::vector<uint32_t> tags;
+  sph_status st = read_tags(c, c->F.tag.live(), n_total, &tags);
+  if (st != SPH_OK) return st;
+  HIPCHK(c, launch_derive_nut(c, n_total), "derive nu_t");
+  return adopt_particles(c, n_total, next_pid, tags);
 }
 
 sph_status sph_get_count(const sph_ctx* c, int64_t* n_total, int64_t* n_real) {
@@ -887,7 +934,8 @@ sph_status sph_eval_rates(sph_ctx* c, const sph_rates* out) {
 
 sph_status sph_neighbors(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap, int64_t* n_pairs) {
   if (!c) return SPH_E_ARG;
-  if (!row_ptr || !n_pairs || cap < 0) return fail(c, SPH_E_ARG, "bad neighbour arguments");
+  if (!row_ptr || !n_pairs || cap < 0 || (cap > 0 && !col))
+    return fail(c, SPH_E_ARG, "bad neighbour arguments");
   if (!c->cells_valid || c->moved)
     return fail(c, SPH_E_STATE, "sph_neighbors needs a cell build after the last position change");
   HIPCHK(c, launch_neighbors(c, row_ptr, col, cap, n_pairs), "neighbors");

@@ -137,6 +137,9 @@ namespace sphx {
 hipError_t launch_zero_i32(sph_ctx* c, int32_t* p, int64_t n);
 hipError_t launch_set_particles(sph_ctx* c, int64_t n, const sph_particles* src);
 hipError_t launch_get_particles(sph_ctx* c, const sph_particles* dst);
+// eddy viscosity C_mu k^2 / epsilon of the n live particles (after the
+// caller wrote k and epsilon in place)
+hipError_t launch_derive_nut(sph_ctx* c, int64_t n);
 // With ns (device {n_in, n_out, skip}, written by the post-update reduction)
 // the sizes are read on the device and n_in / n_grid are upper bounds.
 // keys_done: that reduction also computed the cell keys, slots and counts

@@ -66,6 +66,7 @@ struct Consts {
   double skin;          // allowed distance of a particle outside its build cell
   uint64_t seed;
   T h_t, rc2_t, cs_t, inv_h_t, kf_t;  // kf = -5 alpha / h^2 (dW/dr / r prefactor)
+  double inv_h_d, kf_d;               // the same in FP64
   T rho0_t, c0_t, eta_t, inv_2rc0_t, mu_R_t;   // mu_R_t = rho0 h / 2
 };
 
@@ -103,6 +104,13 @@ __device__ __forceinline__ bool contained(int dim, const BufDev& b, const double
 
 __device__ __forceinline__ int cell_coord(double x, double lo, double cs) {
   return (int)floor(__ddiv_rn(dsub(x, lo), cs));
+}
+
+// Centre of cell c along one axis: the origin of the cell-relative positions
+// (|x - centre| <= cs / 2 + skin, one bit more of FP32 precision than
+// positions relative to the cell's corner).
+__host__ __device__ inline double cell_centre(double lo, int c, double cs) {
+  return lo + ((double)c + 0.5) * cs;
 }
 
 // ---------------------------------------------------------------------------

@@ -190,14 +190,17 @@ __device__ __forceinline__ void write_prec(V4<T>* const* pr, int i, const T x[3]
 }
 
 // Record of particle j for the continuity pass: position, velocity, p, V
-// (negative for a wall).  2D: {x0, x1, v0, v1} {p, Vw, 0, 0};
+// (negative for a wall).  2D: {x0, x1, v0, v1} {p, Vw, p_lo, 0} where p_lo
+// is what the FP64 pressure loses in its rounding to p (FP32 pairs: p + p_lo
+// carries it to FP64 accuracy, so that a pressure difference of two
+// neighbours keeps its digits; 0 in FP64);
 // 3D: {x0, x1, x2, v0} {v1, v2, p, Vw}.
 template <typename T, int DIM>
 __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3], const T v[3],
-                                           T p, T volw) {
+                                           T p, T volw, T plo = T(0)) {
   if (DIM == 2) {
     dr[0][i] = V4<T>{x[0], x[1], v[0], v[1]};
-    dr[1][i] = V4<T>{p, volw, T(0), T(0)};
+    dr[1][i] = V4<T>{p, volw, plo, T(0)};
   } else {
     dr[0][i] = V4<T>{x[0], x[1], x[2], v[0]};
     dr[1][i] = V4<T>{v[1], v[2], p, volw};
@@ -603,6 +606,34 @@ __device__ __forceinline__ void load_B(const T* const* Bp, int i, T B[6]) {
   }
 }
 
+// The 2D pressure pass in FP32 evaluates the kernel function in FP64: its
+// sum cancels to a small fraction of its terms, and the FP32 kernel
+// polynomial's rounding is the largest part of its error against FP64 (the
+// pass has idle VALU cycles in 2D).
+template <typename T, int DIM>
+constexpr bool f64_kernel() {
+  return DIM == 2 && sizeof(T) == 4;
+}
+
+// (dW/dr)/r and r of a pair in FP64 from its offset components in T:
+// r^2 from exact FP64 squares, 1/r from the FP32 reciprocal square root
+// refined by one Newton step in FP64 (relative error ~1e-14).
+template <typename T>
+__device__ __forceinline__ double dw_over_r_d(const T r[3], double inv_h, double kf,
+                                              double* rr) {
+  const double r0 = (double)r[0], r1 = (double)r[1];
+  const double r2 = r0 * r0 + r1 * r1;
+  double q = 0.0;
+  if (r2 > 0.0) {
+    const double y0 = (double)rsqrtf((float)r2);
+    const double y = y0 * (1.5 - 0.5 * r2 * y0 * y0);
+    q = r2 * y;
+  }
+  *rr = q;
+  const double t = 1.0 - 0.5 * q * inv_h;
+  return kf * t * t * t;
+}
+
 __device__ __forceinline__ double eos(double rho, double k, double rho0, double c0, int turb) {
   double p = rho0 * c0 * c0 * (rho / rho0 - 1.0);
   if (turb) p += (2.0 / 3.0) * rho * k;
@@ -684,6 +715,8 @@ inline Consts<T> make_consts(const sph_ctx* c) {
   C.cs_t = (T)P.cell_size;
   C.inv_h_t = (T)(1.0 / P.h);
   C.kf_t = (T)(-5.0 * alpha / (P.h * P.h));
+  C.inv_h_d = 1.0 / P.h;
+  C.kf_d = -5.0 * alpha / (P.h * P.h);
   C.rho0_t = (T)P.rho0;
   C.c0_t = (T)P.c0;
   C.eta_t = (T)P.eta;

@@ -123,6 +123,9 @@ EXPORTS = {
     "sph_eval_rates": (C.c_int, [C.c_void_p, C.POINTER(sph_rates)]),
     "sph_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                 C.POINTER(C.c_int64)]),
+    "sph_field_offset": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t),
+                                   C.POINTER(C.c_int32)]),
+    "sph_set_count": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64]),
     "sph_step_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_int64)]),
     "sph_neighbors_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -259,6 +262,20 @@ def sph_neighbors_noalloc(ctx, row_ptr, col_ptr, cap):
     _check(ctx, lib().sph_neighbors_noalloc(ctx, C.c_void_p(row_ptr), C.c_void_p(col_ptr), cap,
                                             C.byref(n)))
     return n.value
+
+
+FIELDS = {"x0": 0, "x1": 1, "x2": 2, "v0": 3, "v1": 4, "v2": 5, "rho": 6, "drho": 7, "k": 8,
+          "eps": 9, "tag": 10, "pid": 11}
+
+
+def sph_field_offset(ctx, field):
+    off, dt = C.c_size_t(), C.c_int32()
+    _check(ctx, lib().sph_field_offset(ctx, int(field), C.byref(off), C.byref(dt)))
+    return off.value, dt.value
+
+
+def sph_set_count(ctx, n_total, next_pid):
+    _check(ctx, lib().sph_set_count(ctx, int(n_total), int(next_pid)))
 
 
 def sph_step_pairs(ctx, row_ptr, col_ptr, cap):
@@ -542,6 +559,19 @@ class Simulation:
         col = torch.zeros(cap, dtype=torch.int32, device=self.device)
         m = sph_neighbors(self.ctx, row.data_ptr(), col.data_ptr(), cap)
         return row.cpu().numpy(), col.cpu().numpy()[:m]
+
+    def field_view(self, name):
+        """In-place tensor view (capacity entries) of a live particle array;
+        valid until the next call that moves the arrays (build, step,
+        update, advance, set)."""
+        torch = self.torch
+        off, dt = sph_field_offset(self.ctx, FIELDS[name])
+        tdt, size = {0: (torch.float64, 8), 1: (torch.float32, 4), 2: (torch.int32, 4)}[dt]
+        start = (self.ws_ptr - self.ws.data_ptr()) + off
+        return self.ws[start:start + self.capacity * size].view(tdt)
+
+    def set_count(self, n_total, next_pid):
+        sph_set_count(self.ctx, n_total, next_pid)
 
     def step_pairs(self):
         """CSR (row_ptr, col) of the pairs the step's pair passes visit."""

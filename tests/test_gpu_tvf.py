@@ -153,6 +153,18 @@ def test_adjoint_refuses_the_shift(sph):
     # the shift on has no adjoint workspace and its adjoint step is refused
     g = sph.Simulation(with_tvf(cases.make_channel(L=2.0)), precision=0)
     assert sph.sph_adjoint_workspace_size(g.ctx, 4) == 0
+    torch = g.torch
+    dec = torch.zeros(g.n + 8192, dtype=torch.int32, device=g.device)
+    ws = torch.zeros(1 << 20, dtype=torch.uint8, device=g.device)
+    ctl = sph.sph_adjoint_ctrl()
+    ctl.step, ctl.t, ctl.next_pid = 0, 0.0, int(g.case.next_pid)
+    ctl.dt_adv, ctl.n_ac = 1e-3, 1
+    ctl.dec_by_pid = dec.data_ptr()
+    ctl.pid_cap = dec.numel()
+    base = (ws.data_ptr() + 255) & ~255
+    with pytest.raises(sph.SphError) as e:
+        sph.sph_adjoint_forward(g.ctx, ctl, base, (1 << 20) - 256)
+    assert e.value.status == sph.SPH_E_ARG
 
 
 def test_shift_keeps_the_laminar_jet_lips_regular(sph):
