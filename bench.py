@@ -505,6 +505,16 @@ def config_run(name, alpha, steps, torch, nbins=40, navg=1000):
                 print(f"{name} {key}: step {k + 1} of {steps}", file=sys.stderr, flush=True)
         secs = time.perf_counter() - t0
         step, t, _ = sph.sph_get_clock(g.ctx)
+        st = g.state()
+        real = (st["tag"] & 3) <= 1
+        rec["final_max"] = {"speed": float(np.linalg.norm(st["v"][real], axis=1).max()),
+                            "k": float(st["k"][real].max()), "eps": float(st["eps"][real].max()),
+                            "rho_min": float(st["rho"][real].min()),
+                            "rho_max": float(st["rho"][real].max())}
+        if cnt.any():
+            m = cnt > 0
+            rec["binned_rms"] = {f: float(f"{np.sqrt(np.mean((a / np.maximum(cnt, 1))[m] ** 2)):.4g}")
+                                 for f, a in acc.items()}
         rec.update(steps_done=int(step), t=round(float(t), 4), seconds=round(secs, 1),
                    real_particles=[int(n0), int(sph.sph_get_count(g.ctx)[1])],
                    buffers={str(b): {"injected": int(i), "deleted": int(d)}
