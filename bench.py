@@ -84,6 +84,8 @@ def parse():
                     help="run a configured workload for its stated steps in FP32-mixed and "
                          "FP64 (transport-velocity shift --tvf-alpha) and print one JSON line")
     ap.add_argument("--tvf-alpha", type=float, default=0.2)
+    ap.add_argument("--p-far", type=float, default=0.0,
+                    help="--config-run jet: pressure of the outlet and far-field buffers")
     ap.add_argument("--config-steps", type=int, default=0, help="--config-run steps (0: stated)")
     ap.add_argument("--obc-ablation", action="store_true",
                     help="only run the open-boundary ablation of Table 2 (Cases 1-4) on the "
@@ -331,7 +333,7 @@ def obc_ablation(steps=3000, navg=1000, precision=0):
     return out
 
 
-def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
+def laminar_jet(steps=20000, navg=5000, precision=1, nf=10, p_far=0.0):
     """The laminar plane jet of Sec. 4.3 (Re 40, slot D = 2, 40 D x 40 D, nf
     particles across the slot, six buffers of Table 3, transport-velocity
     shift on) against the closed-form plane laminar jet: centre-line speed
@@ -345,7 +347,7 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
     import numpy as np
     import cases
     from paper_2510_25702_amd import sph
-    c = cases.make_laminar_jet(nf=nf)
+    c = cases.make_laminar_jet(nf=nf, p_far=p_far)
     D, U, Re = 2.0, 1.0, 40.0
     nu, K, dp, W = U * D / Re, U * U * D, D / nf, 40.0
     g = sph.Simulation(c, precision=precision)
@@ -389,7 +391,7 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
             np.add.at(cnt[q], b, 1)
     secs = time.perf_counter() - t0
     head = {"setup": f"Re {Re:g}, D {D:g}, 40Dx40D, N_f {nf}, {c.x.shape[0]} particles, "
-                     f"tvf_alpha {c.params['tvf_alpha']}, {steps} steps (t = "
+                     f"tvf_alpha {c.params['tvf_alpha']}, far-field p {p_far:g}, {steps} steps (t = "
                      f"{sph.sph_get_clock(g.ctx)[1]:.0f}), mean of the last {navg}",
             "ms_per_step": round(1e3 * secs / max(steps, 1), 4),
             "real_particles": [int(n_real0), int(sph.sph_get_count(g.ctx)[1])],
@@ -440,15 +442,17 @@ def laminar_jet(steps=20000, navg=5000, precision=1, nf=10):
 
 CONFIG_RUNS = {
     # name: (case builder taking the shift coefficient, configured steps, bin box, label)
-    "jet": (lambda a: cases_mod().make_jet(tvf_alpha=a), 5000, ((0.0, 20.0), (-10.0, 10.0)),
+    "jet": (lambda a, pf=0.0: cases_mod().make_jet(tvf_alpha=a, p_far=pf), 5000,
+            ((0.0, 20.0), (-10.0, 10.0)),
             "2D turbulent plane jet, k-eps, 160k particles, Re 1e4, six buffers, 5000 steps"),
-    "uchannel_pressure": (lambda a: cases_mod().make_uchannel(inlet="pressure", tvf_alpha=a),
+    "uchannel_pressure": (lambda a, pf=0.0: cases_mod().make_uchannel(inlet="pressure",
+                                                                        tvf_alpha=a),
                           2000, ((0.0, 17.3), (0.0, 4.0)),
                           "2D U-channel, p = 1 pressure inlet, p = 0 outlet, Re 50, 2000 steps"),
 }
 
 
-def config_run(name, alpha, steps, torch, nbins=40, navg=1000):
+def config_run(name, alpha, steps, torch, nbins=40, navg=1000, p_far=0.0):
     """A configured workload run for its stated number of steps in FP32-mixed
     and in FP64 on the GPU, each stopping at the first numerical error.  The
     real particles' velocity, pressure (and k, epsilon) are averaged on a
@@ -461,10 +465,10 @@ def config_run(name, alpha, steps, torch, nbins=40, navg=1000):
     steps = steps or nsteps
     navg = min(navg, steps // 2)
     out = {"workload": name, "description": label, "tvf_alpha": alpha, "steps": steps,
-           "averaged_steps": navg}
+           "averaged_steps": navg, "p_far": p_far}
     fields = {}
     for prec, key in ((sph.SPH_FP32_MIXED, "fp32_mixed"), (sph.SPH_FP64, "fp64")):
-        case = make(alpha)
+        case = make(alpha, p_far)
         P = case.params
         g = sph.Simulation(case, precision=prec)
         g.build_cells()
@@ -801,10 +805,12 @@ def gpu_leg(case, precision, steps, warmup, torch):
     prec = "fp32" if precision == sph.SPH_FP32_MIXED else "fp64"
     dom, roof = roofline(r["stats"], case.params["dim"], prec, walked_pairs(g), g.n,
                          bool(case.params["turbulence"]))
+    kern = {k: {"avg_us": round(1e3 * v.total_ms / max(1, v.launches), 3),
+                "launches": int(v.launches)} for k, v in r["stats"].items() if v.launches}
     return r, dict(value=round(r["particle_steps"] / r["seconds"], 1),
                    ms_per_step=round(1e3 * r["seconds"] / steps, 4),
                    pairs_per_s=round(r["pairs"] / r["seconds"], 1),
-                   acoustic_substeps=int(r["n_ac"]), roofline=roof)
+                   acoustic_substeps=int(r["n_ac"]), roofline=roof, kernels=kern)
 
 
 def sweep(names, steps, warmup, torch):
@@ -854,12 +860,14 @@ def main():
     if args.laminar_jet:
         print(json.dumps({"laminar_jet": laminar_jet(steps=args.jet_steps,
                                                      navg=min(5000, args.jet_steps // 4),
-                                                     precision=args.jet_precision)}),
+                                                     precision=args.jet_precision,
+                                                     p_far=args.p_far)}),
               flush=True)
         return
     if args.config_run:
         print(json.dumps({"config_run": config_run(args.config_run, args.tvf_alpha,
-                                                    args.config_steps, torch)}), flush=True)
+                                                    args.config_steps, torch,
+                                                    p_far=args.p_far)}), flush=True)
         return
     if args.obc_ablation:
         print(json.dumps({"obc_ablation": obc_ablation(steps=6000, navg=2000)}), flush=True)

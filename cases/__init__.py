@@ -292,8 +292,12 @@ def make_uchannel(dp=None, H=1.0, Lleg=13.275, p_in=1.0, Re=50.0, c0=10.0,
 # ----------------------------------------------------------------------------
 def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
              turb_int=0.05, mix_len=0.07, noise=0.05, seed=2, steps=5000, turbulence=1,
-             tvf_alpha=0.0, corner_overhang=0.0, pad_cells=3):
-    """Plane jet with the six buffers of Table 3.  corner_overhang widens the
+             tvf_alpha=0.2, corner_overhang=0.0, pad_cells=3, p_far=0.0):
+    """Plane jet with the six buffers of Table 3 and the transport-velocity
+    shift (tvf_alpha; without it the shear layers at the slot lips cavitate
+    within about 500 steps).  p_far is the pressure of the outlet and the two
+    far-field buffers (Table 3 names a far-field pressure without a value);
+    the ambient starts at rest at that pressure.  corner_overhang widens the
     outlet buffer's transverse box past y = +-W (the corner cells it shares
     with the far-field buffers): a slow particle there that moves out through
     the top or bottom stays an outlet particle instead of turning into a
@@ -315,7 +319,7 @@ def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
                 turb_mode=TURB_FREESTREAM, k_bc=k_in, eps_bc=eps_in,
                 profile=PROFILE_UNIFORM, u0=U, noise_amp=noise)
     b2 = Buffer(2, (L, 0.0, 0.0), _frame2(-1.0, 0.0), Lb, (W + corner_overhang, 0.0), f,
-                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=0.0)
+                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=p_far)
     hw_side = (W - D / 2) / 2
     b3 = Buffer(3, (0.0, D / 2 + hw_side, 0.0), ex, Lb, (hw_side, 0.0), f,
                 vel_mode=VEL_PRESCRIBED, p_mode=P_EXTRAPOLATE,
@@ -324,17 +328,20 @@ def make_jet(dp=None, D=1.0, L=20.0, W=10.0, U=1.0, Re=1e4, c0=10.0,
     b4 = dataclasses.replace(b3, id=4, origin=(0.0, -(D / 2 + hw_side), 0.0))
     hw_tb = L / 2 - Lb
     b5 = Buffer(5, (L / 2, W, 0.0), _frame2(0.0, -1.0), Lb, (hw_tb, 0.0), f,
-                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=0.0)
+                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=p_far)
     b6 = Buffer(6, (L / 2, -W, 0.0), _frame2(0.0, 1.0), Lb, (hw_tb, 0.0), f,
-                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=0.0)
+                vel_mode=VEL_EXTRAPOLATE, p_mode=P_PRESCRIBED, p_ob=p_far)
     wall = np.zeros((0, 3))
-    return _assemble("jet", P, [b1, b2, b3, b4, b5, b6], fluid, wall, steps,
-                     k0=k_a, eps0=eps_a, pad_cells=pad_cells,
-                     note=f"plane jet D={D} {L}x{2 * W} dp={dp} Re={Re:g} "
-                          f"k_in={k_in:.4g} eps_in={eps_in:.4g}")
+    c = _assemble("jet", P, [b1, b2, b3, b4, b5, b6], fluid, wall, steps,
+                  k0=k_a, eps0=eps_a, pad_cells=pad_cells,
+                  note=f"plane jet D={D} {L}x{2 * W} dp={dp} Re={Re:g} "
+                       f"k_in={k_in:.4g} eps_in={eps_in:.4g}")
+    if p_far:
+        c.rho[:] = P["rho0"] * (1.0 + p_far / (P["rho0"] * c0 * c0))
+    return c
 
 
-def make_laminar_jet(nf=10, Re=40.0, tvf_alpha=0.2, steps=20000, seed=2):
+def make_laminar_jet(nf=10, Re=40.0, tvf_alpha=0.2, steps=20000, seed=2, p_far=0.0):
     """Laminar plane jet of Sec. 4.3: slot width D = 2, domain 40 D long and
     2 x 20 D wide, nf particles across the slot, uniform inlet speed 1, the
     six buffers of Table 3, no inlet noise, with the transport-velocity
@@ -344,7 +351,7 @@ def make_laminar_jet(nf=10, Re=40.0, tvf_alpha=0.2, steps=20000, seed=2):
     D = 2.0
     dp = D / nf
     return make_jet(dp=dp, D=D, L=40 * D, W=20 * D, U=1.0, Re=Re, noise=0.0, seed=seed,
-                    steps=steps, turbulence=0, tvf_alpha=tvf_alpha, pad_cells=20)
+                    steps=steps, turbulence=0, tvf_alpha=tvf_alpha, pad_cells=20, p_far=p_far)
 
 
 # ----------------------------------------------------------------------------
