@@ -157,7 +157,8 @@ struct AdjDev {
   int nx, ny;
   double csz, rc2, inv_h, kf;
   const uint32_t* nbr;       // the step's neighbour list (NULL: scan the stencil)
-  const int32_t* ncnt;
+  const int32_t* ncnt;       // entries per particle (kNbrNoList: overflowed, stencil)
+  int nk;                    // entries the list holds per particle
   const uint32_t* stale;     // [2] outgrown-list words of the replayed step
   // snapshots
   double* X;                 // [(N+1)][3][cap]
@@ -199,8 +200,8 @@ template <int DIM, int L, typename Fn>
 __device__ __forceinline__ void adj_neighbors(const AdjDev& A, const double* const xr[3], int i,
                                               int lane, Fn&& fn) {
   const double xi0 = xr[0][i], xi1 = xr[1][i], xi2 = DIM == 3 ? xr[2][i] : 0.0;
-  if (A.nbr && !(A.stale[0] | A.stale[1])) {
-    const int cnt = A.ncnt[i];
+  const int cnt = (A.nbr && !(A.stale[0] | A.stale[1])) ? A.ncnt[i] : kNbrNoList;
+  if (cnt <= A.nk) {   // an overflowed list: the stencil below
     for (int kb = lane; kb < cnt; kb += kUnroll * L) {
       uint32_t e[kUnroll];
 #pragma unroll
@@ -299,8 +300,8 @@ template <int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void adj_neighbors_rec(const AdjDev& A, const V4<double>* const* rec,
                                                   int i, int lane, const double xi[3], Fn&& fn) {
   constexpr int U = SPHX_ADJ_UNROLL;
-  if (A.nbr && !(A.stale[0] | A.stale[1])) {
-    const int cnt = A.ncnt[i];
+  const int cnt = (A.nbr && !(A.stale[0] | A.stale[1])) ? A.ncnt[i] : kNbrNoList;
+  if (cnt <= A.nk) {   // an overflowed list: the stencil below
     for (int kb = lane; kb < cnt; kb += U * L) {
       uint32_t e[U];
 #pragma unroll
@@ -1431,6 +1432,7 @@ AdjDev make_adj(sph_ctx* c, char* ws, const AdjLayout& L, int n, int64_t pid_cap
   A.ny = c->grid.n[1];
   A.csz = c->P.cell_size;
   A.nbr = (const uint32_t*)(ws + L.nbr);   // used unless the kept stale words say so
+  A.nk = c->F.nbr_k;
   A.ncnt = (const int32_t*)(ws + L.ncnt);
   A.stale = (const uint32_t*)(ws + L.stale);
   const double rc = 2.0 * c->P.h;

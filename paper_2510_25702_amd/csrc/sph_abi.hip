@@ -328,7 +328,6 @@ sph_status check_flags(sph_ctx* c, uint32_t f) {
   if (f & kFlagCapacity) return fail(c, SPH_E_CAPACITY, "particle capacity / injection limit exceeded");
   if (f & kFlagOutOfGrid) return fail(c, SPH_E_NUMERIC, "particle outside the cell grid");
   if (f & kFlagSkin) return fail(c, SPH_E_NUMERIC, "particle moved beyond the cell skin in one step");
-  if (f & kFlagNbrOverflow) return fail(c, SPH_E_NUMERIC, "neighbour list overflow");
   if (f & kFlagCountMismatch) return fail(c, SPH_E_NUMERIC, "cell count mismatch");
   if (f & kFlagNonFinite) return fail(c, SPH_E_NUMERIC, "non-finite value");
   return SPH_OK;

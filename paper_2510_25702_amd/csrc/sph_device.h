@@ -14,6 +14,7 @@ constexpr int kWave = 64;
 constexpr int kNbrMax2 = 64;            // neighbour-list entries per particle (2D)
 constexpr int kNbrMax3 = 256;           // (3D)
 constexpr int kNbrIdxBits = 27;         // list entry = j | stencil offset code << 27
+constexpr int kNbrNoList = 0x7FFFFFFF;  // list count of a particle whose list overflowed
 constexpr uint32_t kNbrIdxMask = (1u << kNbrIdxBits) - 1u;
 constexpr int kPairShards = 64;        // pair counters, one per 128-byte line
 constexpr int kPairShardStride = 16;    // long longs between two counters
@@ -29,7 +30,7 @@ enum : uint32_t { kDecNone = 0, kDecRelabel = 1, kDecInject = 2, kDecDelete = 3,
 // error flags raised by kernels (device word, read at synchronisation points)
 enum : uint32_t { kFlagOutOfGrid = 1u, kFlagSkin = 2u, kFlagNonFinite = 4u,
                   kFlagInjectOverflow = 8u, kFlagCapacity = 16u,
-                  kFlagCountMismatch = 32u, kFlagNbrOverflow = 64u };
+                  kFlagCountMismatch = 32u };
 
 __host__ __device__ inline uint32_t tag_kind(uint32_t t) { return t & 3u; }
 __host__ __device__ inline uint32_t tag_bid(uint32_t t) { return (t >> 8) & 0xFFu; }

@@ -97,8 +97,8 @@ __device__ __forceinline__ uint32_t nbr_code(int dx, int dy, int dz) {
 template <typename T, int DIM, int L, typename Fn>
 __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int lane,
                                               const T xi[3], Fn&& fn) {
-  if (pc.nbr && !(pc.stale && *pc.stale)) {
-    const int cnt = pc.ncnt[i];
+  const int cnt = (pc.nbr && !(pc.stale && *pc.stale)) ? pc.ncnt[i] : kNbrNoList;
+  if (cnt <= pc.nk) {   // a particle whose list overflowed scans the stencil
     for (int kb = lane; kb < cnt; kb += kUnroll * L) {
       uint32_t e[kUnroll];
 #pragma unroll
@@ -387,9 +387,10 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
   };
   if (!head_early<L>()) {
     // the count and each batch's entries after the tag test; a slot past
-    // the count repeats the batch's first entry
-    if (pc.nbr && !(pc.stale && *pc.stale)) {
-      const int cnt = pc.ncnt[i];
+    // the count repeats the batch's first entry (an overflowed list: the
+    // stencil below)
+    const int cnt = (pc.nbr && !(pc.stale && *pc.stale)) ? pc.ncnt[i] : kNbrNoList;
+    if (cnt <= pc.nk) {
       for (int kb = lane; kb < cnt; kb += kUnroll * L) {
         uint32_t e[kUnroll];
 #pragma unroll
@@ -411,7 +412,7 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
       }
       return;
     }
-  } else if (pc.nbr && !h.stale) {
+  } else if (pc.nbr && !h.stale && h.cnt <= pc.nk) {
     const int cnt = h.cnt;
     uint32_t e[kUnroll];
 #pragma unroll
@@ -597,10 +598,9 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
       }
     }
   }
-  if (lane == 0) {
-    if (cnt > o.K) atomicOr(o.flags, kFlagNbrOverflow);
-    o.ncnt[i] = cnt < o.K ? cnt : o.K;
-  }
+  // more candidates than the list holds (a particle in a cluster denser
+  // than the lattice): the passes scan the stencil for this particle
+  if (lane == 0) o.ncnt[i] = cnt <= o.K ? cnt : kNbrNoList;
   if (o.kstage > 0) {
     // the team's lanes wrote the staged entries; LDS operations of one
     // wavefront complete in order, the barrier keeps the compiler's order

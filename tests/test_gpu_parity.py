@@ -876,3 +876,58 @@ def test_set_count_rejects_unknown_buffer_ids(sph):
         g.set_count(g.capacity + 1, c.next_pid)
     assert e.value.status == sph.SPH_E_ARG
     assert sph.sph_get_count(g.ctx)[0] == before["pid"].shape[0]
+
+
+# --------------------------------------------------------------------------
+# a cluster denser than the per-step list holds: those particles' lists
+# overflow and the passes scan the cell stencil for them
+# --------------------------------------------------------------------------
+def cluster_case(dim, n_cluster, radius_h, seed=3):
+    c = block_case(dim=dim, n_side=14 if dim == 2 else 9, dp=0.1, jitter=0.2, seed=seed)
+    h = c.params["h"]
+    rng = np.random.default_rng(seed)
+    ctr = np.full(3, 0.7 if dim == 2 else 0.45)
+    if dim == 2:
+        ctr[2] = 0.0
+    pts = []
+    while len(pts) < n_cluster:
+        p = ctr + radius_h * h * rng.uniform(-1, 1, 3)
+        if dim == 2:
+            p[2] = 0.0
+        if np.linalg.norm(p - ctr) <= radius_h * h:
+            pts.append(p)
+    x = np.concatenate([c.x, np.array(pts)])
+    n = x.shape[0]
+    c = dataclasses.replace(c, x=x, v=np.zeros((n, 3)), rho=np.ones(n), k=np.zeros(n),
+                            eps=np.zeros(n), tag=np.zeros(n, np.uint32),
+                            pid=np.arange(n, dtype=np.uint32))
+    cases._set_bounds(c.params, x)
+    return cases.perturbed_state(c, seed=seed + 1)
+
+
+@pytest.mark.parametrize("dim,n_cluster,radius_h", [(2, 90, 1.2), (3, 320, 1.2)])
+@pytest.mark.parametrize("pname,prec,tol", PREC)
+def test_overflowing_lists_fall_back_to_the_stencil(sph, ora, dim, n_cluster, radius_h, pname,
+                                                    prec, tol):
+    from scipy.spatial import cKDTree
+    c = cluster_case(dim, n_cluster, radius_h)
+    K = 64 if dim == 2 else 256
+    # more than K candidates within the list radius (the cell size) for some
+    # particles
+    cnt = np.array([len(a) - 1 for a in
+                    cKDTree(c.x).query_ball_point(c.x, c.params["cell_size"])])
+    assert cnt.max() > K
+    ref = ora.OracleSim(c, threads=8)
+    Bo, _ = ref.correction()
+    ro = ref.rates(Bo)
+    g = gpu_sim(sph, c, prec)
+    g.build_cells()
+    g.correction()
+    rg = g.rates()
+    gi = pid_index(g.state()["pid"])
+    idx_g = np.array([gi[int(p)] for p in c.pid])
+    errs = {f: normwise(rg[f][idx_g], ro[f]) for f in ("ap", "drho", "anu", "p")}
+    errs["B"] = normwise(rg["B"][idx_g], Bo)
+    assert max(errs.values()) < tol, errs
+    # and the step runs (no overflow error)
+    g.step()
