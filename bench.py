@@ -77,10 +77,12 @@ def parse():
                     help="laminar plane jet (Re 40) against the closed-form jet; prints one JSON line")
     ap.add_argument("--jet-precision", type=int, default=1, choices=(0, 1),
                     help="--laminar-jet arithmetic: 0 FP64, 1 FP32-mixed")
-    ap.add_argument("--jet-steps", type=int, default=20000,
+    ap.add_argument("--jet-nf", type=int, default=20,
+                    help="--laminar-jet particles across the slot (N_f)")
+    ap.add_argument("--jet-steps", type=int, default=30000,
                     help="advection steps of --laminar-jet (the mean is over the last quarter, "
                          "at most 5000)")
-    ap.add_argument("--config-run", choices=("jet", "uchannel_pressure"),
+    ap.add_argument("--config-run", choices=("jet", "uchannel_pressure", "mixer"),
                     help="run a configured workload for its stated steps in FP32-mixed and "
                          "FP64 (transport-velocity shift --tvf-alpha) and print one JSON line")
     ap.add_argument("--tvf-alpha", type=float, default=0.2)
@@ -445,6 +447,8 @@ CONFIG_RUNS = {
     "jet": (lambda a, pf=0.0: cases_mod().make_jet(tvf_alpha=a, p_far=pf), 5000,
             ((0.0, 20.0), (-10.0, 10.0)),
             "2D turbulent plane jet, k-eps, 160k particles, Re 1e4, six buffers, 5000 steps"),
+    "mixer": (lambda a, pf=0.0: cases_mod().make_mixer(), 500, ((-0.55, 0.55), (-0.55, 0.55)),
+              "3D micro-mixer, 3.75M particles, Re 50, 500 steps (fields binned in x-y)"),
     "uchannel_pressure": (lambda a, pf=0.0: cases_mod().make_uchannel(inlet="pressure",
                                                                         tvf_alpha=a),
                           2000, ((0.0, 17.3), (0.0, 4.0)),
@@ -470,6 +474,7 @@ def config_run(name, alpha, steps, torch, nbins=40, navg=1000, p_far=0.0):
     for prec, key in ((sph.SPH_FP32_MIXED, "fp32_mixed"), (sph.SPH_FP64, "fp64")):
         case = make(alpha, p_far)
         P = case.params
+        out["tvf_alpha"] = float(P.get("tvf_alpha", 0.0))
         g = sph.Simulation(case, precision=prec)
         g.build_cells()
         g.buffer_update()
@@ -861,7 +866,7 @@ def main():
         print(json.dumps({"laminar_jet": laminar_jet(steps=args.jet_steps,
                                                      navg=min(5000, args.jet_steps // 4),
                                                      precision=args.jet_precision,
-                                                     p_far=args.p_far)}),
+                                                     nf=args.jet_nf, p_far=args.p_far)}),
               flush=True)
         return
     if args.config_run:

@@ -12,12 +12,25 @@ Bars:
     GPU's own FP64 rollout (at the full adjoint-channel size too);
   * checkpointed and unsegmented reverse sweeps agree bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
 import cases
 
 pytestmark = pytest.mark.gpu
+
+
+def _threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", n)), n))
+
+
+THREADS = _threads()
 
 
 @pytest.fixture(scope="module")
@@ -489,3 +502,46 @@ def test_state_cotangent_dot_product_3d(sph, sens, field):
     fd = (run(1, eps) - run(-1, eps)) / (2 * eps)
     print(f"3D {field}: adjoint {pred:.12e} fd {fd:.12e}", flush=True)
     assert abs(pred - fd) <= 1e-5 * max(abs(fd), 1e-12) + 1e-12
+
+
+@pytest.mark.parametrize("pname,prec", [("fp64", 0), ("fp32", 1)])
+def test_adjoint_configured_run_against_oracle_finite_differences(sph, sens, ora, pname, prec):
+    # the configured sensitivity run: the adjoint channel at full size (20H x H,
+    # dp = H/80, ~138k particles), 100 steps, checkpoints every 10; the GPU
+    # replays the oracle's own events and its adjoint gradient is compared with
+    # the oracle's central differences of the same frozen-event map, stored by
+    # tests/golden/make_adjoint_fd.py (three coefficients, both objectives).
+    # The FP32-mixed forward gives the FP64 scheme's gradient at its FP32
+    # trajectory, within the same 1e-4.
+    import json
+    import torch
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint_channel_fd.json")
+    ref = json.load(open(path))
+    steps = ref["steps"]
+    c = cases.make_adjoint_channel(steps=steps)
+    assert c.n == ref["particles"]
+    J_o, log, _ = ora.rollout(c, steps, c.objective, threads=THREADS)
+    assert np.abs(J_o - np.array(ref["J_mean"])).max() <= 1e-12 * np.abs(J_o).max()
+    sim = sph.Simulation(c, precision=prec)
+    pid_cap = int(c.next_pid) + 8192
+    start = sim.save()
+    recs = oracle_records(torch, sens, log, pid_cap)
+    desc = sph.make_objective(c.objective, BID)
+    J, _ = gpu_rollout(sph, sens, sim, start, desc, pid_cap, steps, recs)
+    assert np.abs(J - J_o).max() <= (1e-10 if prec == 0 else 1e-5) * np.abs(J_o).max()
+    cf = [int(m) for m in ref["coefs"]]
+    g = {}
+    for k in range(2):
+        gJ = [1.0, 0.0] if k == 0 else [0.0, 1.0]
+        g[k] = gpu_gradient(sph, sens, sim, start, desc, pid_cap, steps, recs, gJ, K=10)[cf]
+    fd_tau = np.array([ref["grad"][str(m)][1] for m in cf])
+    err = rel_max(g[1], fd_tau)
+    print(f"configured adjoint run {pname}: wall shear gradient {g[1]}, oracle {fd_tau}, "
+          f"max rel err {err:.3e}; outlet flux gradient {g[0]}", flush=True)
+    assert err <= 1e-4
+    # in 100 steps (t = 0.4) no disturbance of the inlet reaches the outlet
+    # slab 20H downstream: the oracle's central differences of the slab flux
+    # are exactly zero, and the adjoint's are negligible beside the shear's
+    fd_q = np.array([ref["grad"][str(m)][0] for m in cf])
+    assert np.all(fd_q == 0.0)
+    assert np.abs(g[0]).max() <= 1e-9 * np.abs(fd_tau).max()
