@@ -80,7 +80,7 @@ typedef struct {
                            that particles may travel within one advection step */
   double lo[3], hi[3];  /* cell-grid bounds; particles must stay at least one
                            cell inside them */
-  int64_t capacity;     /* particle slots: real + wall + reserve for injection, < 2^27 */
+  int64_t capacity;     /* particle slots: real + wall + reserve for injection, < 2^26 */
   uint64_t seed;        /* counter-based random numbers (inlet noise) */
   double tvf_alpha;     /* transport-velocity shift (Sec. 2.3 names the formulation
                            and cites it without a formula; the form used is

@@ -202,31 +202,26 @@ __device__ __forceinline__ void adj_neighbors(const AdjDev& A, const double* con
   const double xi0 = xr[0][i], xi1 = xr[1][i], xi2 = DIM == 3 ? xr[2][i] : 0.0;
   const int cnt = (A.nbr && !(A.stale[0] | A.stale[1])) ? A.ncnt[i] : kNbrNoList;
   if (cnt <= A.nk) {   // an overflowed list: the stencil below
-    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+    constexpr int kG = kUnroll / list_vec<DIM, L, kUnroll>();   // groups per batch
+    for (int g0 = 0; list_entry<DIM, L, kUnroll>(g0, lane, 0) < cnt; g0 += kG) {
       uint32_t e[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int k = kb + u * L;
-        e[u] = A.nbr[(int64_t)(k < cnt ? k : kb) * A.cap + i];
-      }
+      list_batch<DIM, L, kUnroll>(A.nbr, A.cap, i, lane, g0, cnt, e);
       double q0[kUnroll], q1[kUnroll], q2[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int j = (int)(e[u] & kNbrIdxMask);
+        const int j = list_j<DIM, L>(e, u, list_entry<DIM, L, kUnroll>(g0, lane, u) < cnt);
         q0[u] = xr[0][j];
         q1[u] = xr[1][j];
         q2[u] = DIM == 3 ? xr[2][j] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        if (kb + u * L >= cnt) break;
+        if (list_entry<DIM, L, kUnroll>(g0, lane, u) >= cnt) break;
         const int j = (int)(e[u] & kNbrIdxMask);
-        const int code = (int)(e[u] >> kNbrIdxBits);
-        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
         double r[3];
-        r[0] = (xi0 - q0[u]) + (-(double)dx * A.csz);
-        r[1] = (xi1 - q1[u]) + (-(double)dy * A.csz);
-        r[2] = DIM == 3 ? (xi2 - q2[u]) + (-(double)dz * A.csz) : 0.0;
+        r[0] = (xi0 - q0[u]) + nbr_shift<double>(e[u], 0, A.csz);
+        r[1] = (xi1 - q1[u]) + nbr_shift<double>(e[u], 1, A.csz);
+        r[2] = DIM == 3 ? (xi2 - q2[u]) + nbr_shift<double>(e[u], 2, A.csz) : 0.0;
         const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                                    : r[0] * r[0] + r[1] * r[1];
         if (r2 < A.rc2) fn(j, r, r2);
@@ -302,30 +297,25 @@ __device__ __forceinline__ void adj_neighbors_rec(const AdjDev& A, const V4<doub
   constexpr int U = SPHX_ADJ_UNROLL;
   const int cnt = (A.nbr && !(A.stale[0] | A.stale[1])) ? A.ncnt[i] : kNbrNoList;
   if (cnt <= A.nk) {   // an overflowed list: the stencil below
-    for (int kb = lane; kb < cnt; kb += U * L) {
+    constexpr int kG = U / list_vec<DIM, L, U>();   // groups per batch
+    for (int g0 = 0; list_entry<DIM, L, U>(g0, lane, 0) < cnt; g0 += kG) {
       uint32_t e[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = kb + u * L;
-        e[u] = A.nbr[(int64_t)(k < cnt ? k : kb) * A.cap + i];
-      }
+      list_batch<DIM, L, U>(A.nbr, A.cap, i, lane, g0, cnt, e);
       V4<double> q[U][NR];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = (int)(e[u] & kNbrIdxMask);
+        const int j = list_j<DIM, L>(e, u, list_entry<DIM, L, U>(g0, lane, u) < cnt);
 #pragma unroll
         for (int w = 0; w < NR; ++w) q[u][w] = rec[w][j];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (kb + u * L >= cnt) break;
+        if (list_entry<DIM, L, U>(g0, lane, u) >= cnt) break;
         const int j = (int)(e[u] & kNbrIdxMask);
-        const int code = (int)(e[u] >> kNbrIdxBits);
-        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
         double r[3];
-        r[0] = (xi[0] - q[u][0].a) + (-(double)dx * A.csz);
-        r[1] = (xi[1] - q[u][0].b) + (-(double)dy * A.csz);
-        r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-(double)dz * A.csz) : 0.0;
+        r[0] = (xi[0] - q[u][0].a) + nbr_shift<double>(e[u], 0, A.csz);
+        r[1] = (xi[1] - q[u][0].b) + nbr_shift<double>(e[u], 1, A.csz);
+        r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + nbr_shift<double>(e[u], 2, A.csz) : 0.0;
         const double r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                                    : r[0] * r[0] + r[1] * r[1];
         if (r2 < A.rc2) fn(j, r, r2, q[u]);
@@ -1751,9 +1741,13 @@ hipError_t adjoint_keep_step(sph_ctx* c, char* ws, int N, int n_step) {
     e = hipMemcpyAsync(ws + L.cs, c->S.cell_start, ((size_t)c->grid.ncell + 1) * 4,
                        hipMemcpyDeviceToDevice, st);
   const bool list = c->use_nbr && c->nbr_valid;
-  if (e == hipSuccess && list && n_step > 0)
-    e = hipMemcpy2DAsync(ws + L.nbr, (size_t)cap * 4, c->F.nbr, (size_t)cap * 4,
-                         (size_t)n_step * 4, (size_t)c->F.nbr_k, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && list && n_step > 0) {
+    // rows of chunks (nbr_index): C entries of every particle per row
+    const size_t C = c->P.dim == 3 ? nbr_chunk<3>() : nbr_chunk<2>();
+    e = hipMemcpy2DAsync(ws + L.nbr, (size_t)cap * 4 * C, c->F.nbr, (size_t)cap * 4 * C,
+                         (size_t)n_step * 4 * C, (size_t)c->F.nbr_k / C,
+                         hipMemcpyDeviceToDevice, st);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + L.ncnt, c->F.ncnt, (size_t)n_step * 4, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) {

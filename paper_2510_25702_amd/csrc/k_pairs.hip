@@ -77,7 +77,7 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   T A[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   auto acc = [&](const T r[3], T r2, T Vj) {
-    const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+    const T f = dw_over_r<T>(pair_dist(r2), C.inv_h_t, C.kf_t);
     const T Vf = Vj * f;
     A[0] -= Vf * r[0] * r[0];
     A[1] -= Vf * r[0] * r[1];
@@ -219,7 +219,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   int m_pairs = 0;
   // the tag, the position and the head of the list load together
   const uint32_t ti = pc.tag[i];
-  const auto h = list_head<T, L>(pc, i, lane);
+  const auto h = list_head<T, DIM, L>(pc, i, lane);
   const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   if (!is_real(ti)) {
     if (a.rates_only && lane == 0) {   // walls and dead slots: zero rates
@@ -276,7 +276,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
-    const T rr = sqrt(r2);
+    const T rr = pair_dist(r2);
     const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
     T vj[3], volw, nut_rj, k_j, eps_j;
     if (DIM == 2) {
@@ -483,7 +483,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   // the particle's own operands and the head of its list load with its tag
   // (every slot below n holds valid data): none of them waits for the test
   const uint32_t ti = pc.tag[i];
-  const auto h = list_head<T, L>(pc, i, lane);
+  const auto h = list_head<T, DIM, L>(pc, i, lane);
   const T xr_i[3] = {pc.xr[0][i], pc.xr[1][i], pc.xr[2][i]};
   const T xi[3] = {xr_i[0], xr_i[1], DIM == 3 ? xr_i[2] : T(0)};
   const T pi = a.p[i];
@@ -538,7 +538,7 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       gW[1] = (T)(fd * (double)r[1]);
       gW[2] = T(0);
     } else {
-      const T f = dw_over_r<T>(sqrt(r2), C.inv_h_t, C.kf_t);
+      const T f = dw_over_r<T>(pair_dist(r2), C.inv_h_t, C.kf_t);
       gW[0] = f * r[0];
       gW[1] = f * r[1];
       gW[2] = DIM == 3 ? f * r[2] : T(0);
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
   if (i < n) {
     // the tag, the position and the head of the list load together
     const uint32_t ti = pc.tag[i];
-    const auto h = list_head<T, L>(pc, i, lane);
+    const auto h = list_head<T, DIM, L>(pc, i, lane);
     const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
     if (is_real(ti)) {
       const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
       int m = 0;
       for_neighbors_rec<T, DIM, L, 2>(pc, i, lane, xi, a.drec, h,
                                       [&](int j, const T r[3], T r2, const V4<T>* q) {
-        const T rr = sqrt(r2);
+        const T rr = pair_dist(r2);
         const T f = dw_over_r<T>(rr, C.inv_h_t, C.kf_t);
         const T volw = DIM == 2 ? q[1].b : q[1].d;
         const bool wall = volw < T(0);

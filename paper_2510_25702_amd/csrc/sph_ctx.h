@@ -42,7 +42,7 @@ struct Fields {
   void* anu[3];            // viscous acceleration of the advection step
   int32_t* cell;           // build-time cell id per particle
   // per-step neighbour list (radius = cell size), built with B
-  uint32_t* nbr;           // [K][cap] j | stencil offset code << 27
+  uint32_t* nbr;           // [K/C][cap][C] j | stencil offset code << 27 (nbr_index)
   int32_t* ncnt;           // [cap] entries of particle i
   void* xrb[3];            // cell-relative positions at the list build
   int nbr_k;               // K

@@ -13,9 +13,29 @@ constexpr int kMaxInject = 4096;
 constexpr int kWave = 64;
 constexpr int kNbrMax2 = 64;            // neighbour-list entries per particle (2D)
 constexpr int kNbrMax3 = 256;           // (3D)
-constexpr int kNbrIdxBits = 27;         // list entry = j | stencil offset code << 27
+// list entry = j | (dx + 1) << 26 | (dy + 1) << 28 | (dz + 1) << 30, with
+// (dx, dy, dz) the cell of j relative to the cell of i
+constexpr int kNbrIdxBits = 26;
 constexpr int kNbrNoList = 0x7FFFFFFF;  // list count of a particle whose list overflowed
 constexpr uint32_t kNbrIdxMask = (1u << kNbrIdxBits) - 1u;
+// Entry k of particle i in the per-step neighbour list: chunks of C
+// consecutive entries of one particle, chunk c of every particle in one row
+// of `stride` chunks.  3D lists (about 170 entries) take C = 4 (16 bytes): a
+// particle's appends stay within a few lines and a team reads whole chunks
+// (the 3.75M-particle mixer's list build 6.50 -> 5.22 ms).  2D lists (about
+// 36 entries) keep C = 1, one row per entry: there the 16-byte chunks made
+// the passes at 2.56M particles 10-15 % slower and gained nothing at 57.6k.
+template <int DIM>
+constexpr int nbr_chunk() {
+  return DIM == 3 ? 4 : 1;
+}
+template <int DIM>
+__host__ __device__ inline int64_t nbr_index(int k, int i, int64_t stride) {
+  constexpr uint32_t C = nbr_chunk<DIM>();
+  // k, i >= 0 and stride < 2^26: unsigned shifts and one 32 x 32 -> 64 product
+  const uint32_t ku = (uint32_t)k;
+  return (int64_t)(((uint64_t)(ku / C) * (uint32_t)stride + (uint32_t)i) * C + ku % C);
+}
 constexpr int kPairShards = 64;        // pair counters, one per 128-byte line
 constexpr int kPairShardStride = 16;    // long longs between two counters
 
@@ -80,6 +100,13 @@ __device__ __forceinline__ T dw_over_r(T r, T inv_h, T kf) {
   T t = T(1) - T(0.5) * r * inv_h;
   return kf * t * t * t;
 }
+
+// Pair distance |r| from r^2 in the pair passes.  FP32: the hardware square
+// root, within one ulp (the correctly rounded library sequence adds about
+// fifteen instructions per candidate, executed by the whole wavefront, far
+// below the FP32-mixed pair terms' own rounding).  FP64: the library one.
+__device__ __forceinline__ float pair_dist(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+__device__ __forceinline__ double pair_dist(double r2) { return sqrt(r2); }
 
 // ---------------------------------------------------------------------------
 // Buffer geometry in FP64 without contraction (bit-reproducible predicates).

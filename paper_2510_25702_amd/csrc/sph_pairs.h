@@ -79,8 +79,9 @@ __device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
 // time: their positions are loaded together before any is tested, so that
 // the loads of one batch are in flight at once.
 // With a neighbour list (built with B after the cell build, radius = cell
-// size) the candidates are its entries, in the same order as the stencil
-// scan: the same pairs are visited in the same order.  The list covers every
+// size) the candidates are its entries (in stencil order, shared among the
+// lanes as list_vec states): the same pairs as the stencil scan, summed per
+// lane in another grouping.  The list covers every
 // pair within 2h while no particle has moved more than (cell size - 2h) / 2
 // since it was built; the pressure pass flags the step's list as outgrown
 // otherwise, and the later passes of the step scan the stencil instead.
@@ -89,9 +90,91 @@ __device__ __forceinline__ void count_pairs(long long* ctr, long long m) {
 #endif
 constexpr int kUnroll = SPHX_UNROLL;
 
-// Stencil offset code of a list entry: (dx+1) + 3 (dy+1) + 9 (dz+1).
-__device__ __forceinline__ uint32_t nbr_code(int dx, int dy, int dz) {
-  return (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+// List entry of candidate j in the cell (dx, dy, dz) away from i's cell.
+__device__ __forceinline__ uint32_t nbr_pack(int j, int dx, int dy, int dz) {
+  return (uint32_t)j | (uint32_t)((dx + 1) | (dy + 1) << 2 | (dz + 1) << 4) << kNbrIdxBits;
+}
+
+// -(cell offset of entry e along axis a) * cs: the field holds d + 1 in
+// {0, 1, 2}, so cs - (d + 1) cs is -d cs, exact (a bit-field extract, a
+// conversion and one fused multiply-add).
+template <typename T>
+__device__ __forceinline__ T nbr_shift(uint32_t e, int a, T cs) {
+  const uint32_t d1 = (e >> (kNbrIdxBits + 2 * a)) & 3u;
+  return fma(-T(d1), cs, cs);
+}
+
+// The list entries a lane of a team takes: groups of V consecutive entries
+// of one chunk, group g of lane l starting at entry L V g + V l.  V is the
+// largest of 4, 2, 1 that divides the batch of U entries per lane and is at
+// most C / L (one with C or more lanes: lane l takes l, l + L, ...), so that
+// narrow teams read whole chunks with vector loads.
+template <int DIM, int L, int U>
+constexpr int list_vec() {
+  constexpr int C = nbr_chunk<DIM>();
+  constexpr int vmax = L >= C ? 1 : C / L;
+  return (vmax >= 4 && U % 4 == 0) ? 4 : ((vmax >= 2 && U % 2 == 0) ? 2 : 1);
+}
+
+// Entry of element u of the batch that starts at group g0.
+template <int DIM, int L, int U>
+__device__ __forceinline__ int list_entry(int g0, int lane, int u) {
+  constexpr int V = list_vec<DIM, L, U>();
+  return L * V * (g0 + u / V) + V * lane + u % V;
+}
+
+// The U entries of lane `lane` in the batch that starts at group g0 (whose
+// first entry is below cnt).  A group that starts at or past cnt re-reads
+// the first one, so no load leaves the rows in use; elements past cnt are
+// read but never used.
+template <int DIM, int L, int U>
+__device__ __forceinline__ void list_batch(const uint32_t* nbr, int64_t stride, int i, int lane,
+                                           int g0, int cnt, uint32_t (&e)[U]) {
+  constexpr int V = list_vec<DIM, L, U>();
+  constexpr int NV = U / V;
+  // every address first, then every load, so that the loads of a batch are
+  // in flight together
+  const uint32_t* p[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    int k = list_entry<DIM, L, U>(g0, lane, v * V);
+    if (k >= cnt) k = list_entry<DIM, L, U>(g0, lane, 0);
+    p[v] = nbr + nbr_index<DIM>(k, i, stride);
+  }
+  if constexpr (V == 4) {
+    uint4 w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = *reinterpret_cast<const uint4*>(p[v]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      e[4 * v] = w[v].x;
+      e[4 * v + 1] = w[v].y;
+      e[4 * v + 2] = w[v].z;
+      e[4 * v + 3] = w[v].w;
+    }
+  } else if constexpr (V == 2) {
+    uint2 w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = *reinterpret_cast<const uint2*>(p[v]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      e[2 * v] = w[v].x;
+      e[2 * v + 1] = w[v].y;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) e[v] = *p[v];
+  }
+}
+
+// The particle gathered for element u of a batch: its entry while valid.
+// Past the count, one-entry groups hold the batch's first entry (re-read by
+// list_batch) and wider groups any value: both gather the first entry's j,
+// which the lane loads anyway.
+template <int DIM, int L, int U>
+__device__ __forceinline__ int list_j(const uint32_t (&e)[U], int u, bool valid) {
+  constexpr int V = list_vec<DIM, L, U>();
+  return (int)(((V == 1 || valid) ? e[u] : e[0]) & kNbrIdxMask);
 }
 
 template <typename T, int DIM, int L, typename Fn>
@@ -99,31 +182,26 @@ __device__ __forceinline__ void for_neighbors(const PairCtx<T>& pc, int i, int l
                                               const T xi[3], Fn&& fn) {
   const int cnt = (pc.nbr && !(pc.stale && *pc.stale)) ? pc.ncnt[i] : kNbrNoList;
   if (cnt <= pc.nk) {   // a particle whose list overflowed scans the stencil
-    for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+    constexpr int kG = kUnroll / list_vec<DIM, L, kUnroll>();   // groups per batch
+    for (int g0 = 0; list_entry<DIM, L, kUnroll>(g0, lane, 0) < cnt; g0 += kG) {
       uint32_t e[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int k = kb + u * L;
-        e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
-      }
+      list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, g0, cnt, e);
       T q0[kUnroll], q1[kUnroll], q2[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int j = (int)(e[u] & kNbrIdxMask);
+        const int j = list_j<DIM, L>(e, u, list_entry<DIM, L, kUnroll>(g0, lane, u) < cnt);
         q0[u] = pc.xr[0][j];
         q1[u] = pc.xr[1][j];
         q2[u] = DIM == 3 ? pc.xr[2][j] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        if (kb + u * L >= cnt) break;
+        if (list_entry<DIM, L, kUnroll>(g0, lane, u) >= cnt) break;
         const int j = (int)(e[u] & kNbrIdxMask);
-        const int code = (int)(e[u] >> kNbrIdxBits);
-        const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
         T r[3];
-        r[0] = (xi[0] - q0[u]) + (-T(dx) * pc.csz);
-        r[1] = (xi[1] - q1[u]) + (-T(dy) * pc.csz);
-        r[2] = DIM == 3 ? (xi[2] - q2[u]) + (-T(dz) * pc.csz) : T(0);
+        r[0] = (xi[0] - q0[u]) + nbr_shift<T>(e[u], 0, pc.csz);
+        r[1] = (xi[1] - q1[u]) + nbr_shift<T>(e[u], 1, pc.csz);
+        r[2] = DIM == 3 ? (xi[2] - q2[u]) + nbr_shift<T>(e[u], 2, pc.csz) : T(0);
         const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                               : r[0] * r[0] + r[1] * r[1];
         if (r2 < pc.rc2) fn(j, r, r2);
@@ -241,16 +319,28 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 // The record passes carry less per candidate than the position-only loop:
 // deeper batches pay off when few lanes share a particle (measured: 6 at one
 // or two lanes); at four, with the next batch's entries loading under the
-// current records, two candidates per lane and batch are best.
+// current records, two candidates per lane and batch are best.  Two-lane
+// teams over FP32 3D records take 8 (four chunks of the list per batch; the
+// 3.75M-particle mixer: advection 1932 -> 1673 us, continuity 1853 -> 1541,
+// pressure 2357 -> 2339), FP64 3D ones keep 6 (pressure 3942 against 5374
+// us at 8).
 #ifndef SPHX_REC_UNROLL_WIDE
 #define SPHX_REC_UNROLL_WIDE 2
 #endif
 #ifndef SPHX_REC_UNROLL_NARROW
 #define SPHX_REC_UNROLL_NARROW 6
 #endif
-template <int L>
+#ifndef SPHX_REC_UNROLL_NARROW3
+#define SPHX_REC_UNROLL_NARROW3 8
+#endif
+#ifndef SPHX_REC_UNROLL_ONE
+#define SPHX_REC_UNROLL_ONE 6
+#endif
+template <typename T, int DIM, int L>
 constexpr int rec_unroll() {
-  return L >= 4 ? SPHX_REC_UNROLL_WIDE : SPHX_REC_UNROLL_NARROW;
+  if (L >= 4) return SPHX_REC_UNROLL_WIDE;
+  if (L == 1) return SPHX_REC_UNROLL_ONE;
+  return (DIM == 3 && sizeof(T) == 4) ? SPHX_REC_UNROLL_NARROW3 : SPHX_REC_UNROLL_NARROW;
 }
 
 // The start of a particle's walk of its list: the count, the stale word and
@@ -275,10 +365,10 @@ constexpr bool head_early() {
   return L >= SPHX_HEAD_MIN_LANES;
 }
 
-template <typename T, int L>
-__device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>& pc, int i,
-                                                               int lane) {
-  constexpr int U = rec_unroll<L>();
+template <typename T, int DIM, int L>
+__device__ __forceinline__ ListHead<rec_unroll<T, DIM, L>()> list_head(const PairCtx<T>& pc,
+                                                                       int i, int lane) {
+  constexpr int U = rec_unroll<T, DIM, L>();
   ListHead<U> h;
   h.cnt = 0;
   h.stale = true;
@@ -290,7 +380,7 @@ __device__ __forceinline__ ListHead<rec_unroll<L>()> list_head(const PairCtx<T>&
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = lane + u * L;
-      h.e[u] = pc.nbr[(int64_t)(k < pc.nk ? k : pc.nk - 1) * pc.nstride + i];
+      h.e[u] = pc.nbr[nbr_index<DIM>(k < pc.nk ? k : pc.nk - 1, i, pc.nstride)];
     }
   }
   return h;
@@ -323,9 +413,9 @@ constexpr bool hoist_epilogue() {
 template <typename T, int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
                                                   const T xi[3], const V4<T>* const* rec,
-                                                  const ListHead<rec_unroll<L>()>& h,
+                                                  const ListHead<rec_unroll<T, DIM, L>()>& h,
                                                   Fn&& fn) {
-  constexpr int kUnroll = rec_unroll<L>();
+  constexpr int kUnroll = rec_unroll<T, DIM, L>();
   constexpr bool kAhead = L >= SPHX_AHEAD_MIN_LANES;
   // the candidates of one batch: entries e, records q
   // 3D records span two or three vectors but about 40 % of the list's
@@ -345,20 +435,19 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
 #pragma unroll
       for (int w = 0; w < (kLazy ? 1 : NR); ++w) q[u][w] = rec[w][jv[u]];
   };
-  auto test_lazy = [&](int kb, int cnt, const uint32_t (&e)[kUnroll], V4<T> (&q)[kUnroll][NR]) {
+  auto test_lazy = [&](const bool (&valid)[kUnroll], const uint32_t (&e)[kUnroll],
+                       V4<T> (&q)[kUnroll][NR]) {
     T rv[kUnroll][3], r2v[kUnroll];
     bool ok[kUnroll];
     int jv[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       jv[u] = (int)(e[u] & kNbrIdxMask);
-      const int code = (int)(e[u] >> kNbrIdxBits);
-      const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
-      rv[u][0] = (xi[0] - q[u][0].a) + (-T(dx) * pc.csz);
-      rv[u][1] = (xi[1] - q[u][0].b) + (-T(dy) * pc.csz);
-      rv[u][2] = (xi[2] - q[u][0].c) + (-T(dz) * pc.csz);
+      rv[u][0] = (xi[0] - q[u][0].a) + nbr_shift<T>(e[u], 0, pc.csz);
+      rv[u][1] = (xi[1] - q[u][0].b) + nbr_shift<T>(e[u], 1, pc.csz);
+      rv[u][2] = (xi[2] - q[u][0].c) + nbr_shift<T>(e[u], 2, pc.csz);
       r2v[u] = (rv[u][0] * rv[u][0] + rv[u][1] * rv[u][1]) + rv[u][2] * rv[u][2];
-      ok[u] = kb + u * L < cnt && r2v[u] < pc.rc2;
+      ok[u] = valid[u] && r2v[u] < pc.rc2;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
@@ -369,17 +458,16 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
     for (int u = 0; u < kUnroll; ++u)
       if (ok[u]) fn(jv[u], rv[u], r2v[u], q[u]);
   };
-  auto test = [&](int kb, int cnt, const uint32_t (&e)[kUnroll], const V4<T> (&q)[kUnroll][NR]) {
+  auto test = [&](const bool (&valid)[kUnroll], const uint32_t (&e)[kUnroll],
+                  const V4<T> (&q)[kUnroll][NR]) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (kb + u * L >= cnt) break;
+      if (!valid[u]) break;
       const int j = (int)(e[u] & kNbrIdxMask);
-      const int code = (int)(e[u] >> kNbrIdxBits);
-      const int dx = code % 3 - 1, dy = (code / 3) % 3 - 1, dz = code / 9 - 1;
       T r[3];
-      r[0] = (xi[0] - q[u][0].a) + (-T(dx) * pc.csz);
-      r[1] = (xi[1] - q[u][0].b) + (-T(dy) * pc.csz);
-      r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + (-T(dz) * pc.csz) : T(0);
+      r[0] = (xi[0] - q[u][0].a) + nbr_shift<T>(e[u], 0, pc.csz);
+      r[1] = (xi[1] - q[u][0].b) + nbr_shift<T>(e[u], 1, pc.csz);
+      r[2] = DIM == 3 ? (xi[2] - q[u][0].c) + nbr_shift<T>(e[u], 2, pc.csz) : T(0);
       const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                             : r[0] * r[0] + r[1] * r[1];
       if (r2 < pc.rc2) fn(j, r, r2, q[u]);
@@ -391,23 +479,24 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
     // stencil below)
     const int cnt = (pc.nbr && !(pc.stale && *pc.stale)) ? pc.ncnt[i] : kNbrNoList;
     if (cnt <= pc.nk) {
-      for (int kb = lane; kb < cnt; kb += kUnroll * L) {
+      constexpr int kG = kUnroll / list_vec<DIM, L, kUnroll>();   // groups per batch
+      for (int g0 = 0; list_entry<DIM, L, kUnroll>(g0, lane, 0) < cnt; g0 += kG) {
         uint32_t e[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int k = kb + u * L;
-          e[u] = pc.nbr[(int64_t)(k < cnt ? k : kb) * pc.nstride + i];
-        }
+        list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, g0, cnt, e);
         V4<T> q[kUnroll][NR];
         int jv[kUnroll];
+        bool valid[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) jv[u] = (int)(e[u] & kNbrIdxMask);
+        for (int u = 0; u < kUnroll; ++u) {
+          valid[u] = list_entry<DIM, L, kUnroll>(g0, lane, u) < cnt;
+          jv[u] = list_j<DIM, L>(e, u, valid[u]);
+        }
         load_batch(q, jv);
         if constexpr (kLazy) {
-          test_lazy(kb, cnt, e, q);
+          test_lazy(valid, e, q);
         } else {
           pin_records<T, DIM, kUnroll, NR>(q);
-          test(kb, cnt, e, q);
+          test(valid, e, q);
         }
       }
       return;
@@ -422,25 +511,29 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int k = kb + u * L;
-          e[u] = k < cnt ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
+          e[u] = k < cnt ? pc.nbr[nbr_index<DIM>(k, i, pc.nstride)] : 0u;
         }
       }
       V4<T> q[kUnroll][NR];
       int jv[kUnroll];
+      bool valid[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) jv[u] = kb + u * L < cnt ? (int)(e[u] & kNbrIdxMask) : i;
+      for (int u = 0; u < kUnroll; ++u) {
+        valid[u] = kb + u * L < cnt;
+        jv[u] = valid[u] ? (int)(e[u] & kNbrIdxMask) : i;
+      }
       load_batch(q, jv);
       uint32_t en[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int k = kb + (kUnroll + u) * L;
-        en[u] = (kAhead && k < cnt) ? pc.nbr[(int64_t)k * pc.nstride + i] : 0u;
+        en[u] = (kAhead && k < cnt) ? pc.nbr[nbr_index<DIM>(k, i, pc.nstride)] : 0u;
       }
       if constexpr (kLazy) {
-        test_lazy(kb, cnt, e, q);
+        test_lazy(valid, e, q);
       } else {
         pin_records<T, DIM, kUnroll, NR>(q);
-        test(kb, cnt, e, q);
+        test(valid, e, q);
       }
       if (kAhead) {
 #pragma unroll
@@ -507,15 +600,16 @@ struct NbrOut {
 #ifndef SPHX_LIST_STAGE
 #define SPHX_LIST_STAGE 1
 #endif
-// The list's component-major rows make a wavefront's reads of entry k one
+// The 2D list's one-entry rows make a wavefront's reads of entry k one
 // line, but its appends scattered: each particle of a wavefront appends at
 // its own count, a different row.  With four or more lanes per particle
 // (2D, up to 260k particles) the entries are collected in LDS (16 KB or less
 // per workgroup) and written out row by row at the end of the scan: the
 // correction took 27.3 against 28.5 us at 57.6k particles and 57.3 against
 // 58.6 us at 160k.  With fewer lanes the 32-48 KB of LDS cost more
-// residency than the scattered stores (178 against 161 us at 640k), and in
-// 3D it gained nothing: there the appends go straight to the rows.
+// residency than the scattered stores (178 against 161 us at 640k).  3D
+// appends go straight to the list, whose four-entry chunks keep a particle's
+// appends within a few lines.
 template <int DIM, int L>
 constexpr int list_stage() {
   return (SPHX_LIST_STAGE && DIM == 2 && L >= 4) ? kNbrMax2 : 0;
@@ -533,6 +627,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
                                            const NbrOut<T>& o, Fn&& fn) {
   const int wl = (int)(threadIdx.x & (kWave - 1));
   const int team0 = wl - lane;   // first lane of the team in the wavefront
+  const uint64_t tmask = (L >= kWave ? ~0ull : ((1ull << L) - 1ull)) << team0;
   const int c = pc.cell[i];
   const int cx = c % pc.nx;
   const int cyz = c / pc.nx;
@@ -582,15 +677,16 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           const bool acc = in && r2 < o.rl2;
           int off = 0, tot = acc ? 1 : 0;
           if (L > 1) {
-            const unsigned long long m = __ballot(acc);
-            const unsigned long long tm = (m >> team0) & ((1ull << L) - 1ull);
-            off = __popcll(tm & ((1ull << lane) - 1ull));
+            // accepted lanes of the team; off = those below this lane
+            const uint64_t tm = (uint64_t)__ballot(acc) & tmask;
+            off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(tm >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)tm, 0u));
             tot = __popcll(tm);
           }
           if (acc && cnt + off < o.K) {
-            const uint32_t ent = (uint32_t)j | (nbr_code(dx, dy, dz) << kNbrIdxBits);
+            const uint32_t ent = nbr_pack(j, dx, dy, dz);
             if (cnt + off < o.kstage) o.stage[cnt + off] = ent;
-            else o.nbr[(int64_t)(cnt + off) * o.stride + i] = ent;
+            else o.nbr[nbr_index<DIM>(cnt + off, i, o.stride)] = ent;
           }
           cnt += tot;
           if (in && r2 < pc.rc2) fn(j, r, r2, qv[u]);
@@ -608,7 +704,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int m = cnt < o.kstage ? cnt : o.kstage;
-    for (int k = lane; k < m; k += L) o.nbr[(int64_t)k * o.stride + i] = o.stage[k];
+    for (int k = lane; k < m; k += L) o.nbr[nbr_index<DIM>(k, i, o.stride)] = o.stage[k];
   }
 }
 
