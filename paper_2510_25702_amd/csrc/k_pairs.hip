@@ -174,6 +174,9 @@ __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts
   __shared__ uint32_t stage[KS > 0 ? (256 / L) * KS : 1];
   nb.kstage = KS;
   nb.stage = KS > 0 ? stage + (threadIdx.x / L) * KS : nullptr;
+  constexpr int PQ = BUILD ? pair_queue<T, DIM>() : 0;
+  __shared__ V4<T> pqueue[PQ > 0 ? PQ * 256 : 1];
+  nb.queue = PQ > 0 ? pqueue + (threadIdx.x / kWave) * (PQ * kWave) : nullptr;
   const int m = correction_body<T, DIM, L, BUILD>(g / L, g % L, n, pc, C, a, nb);
   count_pairs(pc.pairs, m);
 }
@@ -1132,6 +1135,7 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
   nb.rl2 = (T)(rl * rl);
   nb.stage = nullptr;
   nb.kstage = 0;
+  nb.queue = nullptr;
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr) {

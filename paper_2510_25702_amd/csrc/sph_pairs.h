@@ -595,7 +595,33 @@ struct NbrOut {
   T rl2;
   uint32_t* stage;   // LDS rows of this particle's first kstage entries (NULL: none)
   int kstage;
+  V4<T>* queue;      // LDS pair queue of this wavefront (pair_queue entries per lane)
 };
+
+// Pairs within 2h found by the 3D FP32 list build wait in a per-lane queue
+// in LDS ({r, V_j}, 16 bytes) and their terms are evaluated when some lane's
+// queue is full, all queued pairs of the wavefront together.  Evaluated in
+// the scan itself, the terms ran for nearly every candidate batch (one lane
+// or another of the wavefront always had a pair within 2h, about 7 % of the
+// ~1000 candidates), at about a third of the scan's instructions.  Each lane
+// still takes its pairs in the order it found them.  Q entries per lane take
+// Q KB of LDS per wavefront: up to 7 keep five 256-lane workgroups per CU.
+// The 3.75M-particle mixer: 5106 us without the queue, 5102 / 5079 / 5017 us
+// with 4 / 6 / 7 entries (6 % fewer VALU instructions; a queue fills about
+// every 35 candidates somewhere in the wavefront).
+#ifndef SPHX_PAIR_QUEUE
+#define SPHX_PAIR_QUEUE 7
+#endif
+template <typename T, int DIM>
+constexpr int pair_queue() {
+  return (DIM == 3 && sizeof(T) == 4) ? SPHX_PAIR_QUEUE : 0;
+}
+
+// |r|^2 as every pass forms it
+template <typename T, int DIM>
+__device__ __forceinline__ T dist2(const T r[3]) {
+  return DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] : r[0] * r[0] + r[1] * r[1];
+}
 
 #ifndef SPHX_LIST_STAGE
 #define SPHX_LIST_STAGE 1
@@ -634,6 +660,21 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   const int cy = cyz % pc.ny;
   const int cz = cyz / pc.ny;
   constexpr int zr = DIM == 3 ? 1 : 0;
+  constexpr int Q = pair_queue<T, DIM>();
+  int qn = 0;   // this lane's queued pairs
+  // the queued pairs' terms, in the order the lane found them (wavefront-
+  // uniform call: every lane with a queued pair takes part)
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < (Q > 0 ? Q : 1); ++k) {
+      if (k < qn) {
+        const V4<T> e = o.queue[k * kWave + wl];
+        const T r[3] = {e.a, e.b, e.c};
+        fn(0, r, dist2<T, DIM>(r), e.d);
+      }
+    }
+    qn = 0;
+  };
   int cnt = 0;
   for (int dz = -zr; dz <= zr; ++dz) {
     // the cell ranges of the plane's three rows, loaded together (the list
@@ -656,7 +697,8 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int j = jb + u * L + lane;
-          const int js = j < j3 ? j : jb;
+          // (an index below 2^26: 32-bit offsets from the arrays' bases)
+          const uint32_t js = (uint32_t)(j < j3 ? j : jb) & kNbrIdxMask;
           q0[u] = pc.xr[0][js];
           q1[u] = pc.xr[1][js];
           q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
@@ -671,8 +713,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           r[0] = (xi[0] - q0[u]) + ox;
           r[1] = (xi[1] - q1[u]) + oy;
           r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
-          const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
-                                : r[0] * r[0] + r[1] * r[1];
+          const T r2 = dist2<T, DIM>(r);
           const bool in = j < j3 && j != i;
           const bool acc = in && r2 < o.rl2;
           int off = 0, tot = acc ? 1 : 0;
@@ -689,11 +730,20 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
             else o.nbr[nbr_index<DIM>(cnt + off, i, o.stride)] = ent;
           }
           cnt += tot;
-          if (in && r2 < pc.rc2) fn(j, r, r2, qv[u]);
+          if constexpr (Q > 0) {
+            if (in && r2 < pc.rc2) {
+              o.queue[qn * kWave + wl] = V4<T>{r[0], r[1], r[2], qv[u]};
+              ++qn;
+            }
+            if (__ballot(qn == Q)) flush();
+          } else {
+            if (in && r2 < pc.rc2) fn(j, r, r2, qv[u]);
+          }
         }
       }
     }
   }
+  if constexpr (Q > 0) flush();
   // more candidates than the list holds (a particle in a cluster denser
   // than the lattice): the passes scan the stencil for this particle
   if (lane == 0) o.ncnt[i] = cnt <= o.K ? cnt : kNbrNoList;
