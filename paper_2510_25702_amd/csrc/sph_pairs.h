@@ -289,7 +289,7 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
 #define SPHX_PIN_RECORDS 1
 #endif
 #ifndef SPHX_LAZY_MIN_NR
-#define SPHX_LAZY_MIN_NR 3
+#define SPHX_LAZY_MIN_NR 2
 #endif
 #ifndef SPHX_LAZY_MIN_NR64
 #define SPHX_LAZY_MIN_NR64 2
@@ -396,6 +396,13 @@ __device__ __forceinline__ ListHead<rec_unroll<T, DIM, L>()> list_head(const Pai
 #ifndef SPHX_AHEAD_MIN_LANES
 #define SPHX_AHEAD_MIN_LANES 1
 #endif
+// 3D teams of one or two lanes also load the next batch's list entries
+// under the current batch's records (the 3.75M-particle mixer: FP32
+// advection 1798 -> 1600 us, FP64 continuity 2826 -> 2700 us, the others
+// level or 1-3 % faster).
+#ifndef SPHX_AHEAD_NARROW3
+#define SPHX_AHEAD_NARROW3 1
+#endif
 #ifndef SPHX_HOIST_MIN_LANES
 #define SPHX_HOIST_MIN_LANES 4
 #endif
@@ -424,9 +431,12 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
   // candidates' records together and evaluates them.  The gathers, not the
   // arithmetic, bound the 3D passes.  Measured on the 3.75M-particle mixer:
   // FP32 pressure (three vectors) 2733 -> 2542 us, FP64 pressure 4942 ->
-  // 4394 us, FP64 continuity 3118 -> 2706 us; with FP32 two-vector records
-  // the second round trip costs more than the gathers it saves (continuity
-  // 1640 -> 1753 us), so those load whole batches.
+  // 4394 us, FP64 continuity 3118 -> 2706 us.  FP32 two-vector records
+  // (continuity, laminar advection) lost with one-entry list rows and the
+  // divided stencil code (continuity 1640 -> 1753 us) but gain with the
+  // chunked list, its bit-field offsets and the batches of eight (advection
+  // 1597 -> 1447 us, continuity 1551 -> 1419 us): every 3D record is
+  // gathered in two rounds.
   constexpr bool kLazy =
       DIM == 3 && NR >= (sizeof(T) == 8 ? SPHX_LAZY_MIN_NR64 : SPHX_LAZY_MIN_NR);
   auto load_batch = [&](V4<T> (&q)[kUnroll][NR], const int (&jv)[kUnroll]) {
@@ -480,9 +490,12 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
     const int cnt = (pc.nbr && !(pc.stale && *pc.stale)) ? pc.ncnt[i] : kNbrNoList;
     if (cnt <= pc.nk) {
       constexpr int kG = kUnroll / list_vec<DIM, L, kUnroll>();   // groups per batch
+      constexpr bool kAheadN = SPHX_AHEAD_NARROW3 && DIM == 3;
+      uint32_t e[kUnroll];
+      if (kAheadN && cnt > 0 && list_entry<DIM, L, kUnroll>(0, lane, 0) < cnt)
+        list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, 0, cnt, e);
       for (int g0 = 0; list_entry<DIM, L, kUnroll>(g0, lane, 0) < cnt; g0 += kG) {
-        uint32_t e[kUnroll];
-        list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, g0, cnt, e);
+        if (!kAheadN) list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, g0, cnt, e);
         V4<T> q[kUnroll][NR];
         int jv[kUnroll];
         bool valid[kUnroll];
@@ -492,11 +505,19 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
           jv[u] = list_j<DIM, L>(e, u, valid[u]);
         }
         load_batch(q, jv);
+        // the next batch's entries load under this batch's records
+        uint32_t en[kUnroll];
+        if (kAheadN && list_entry<DIM, L, kUnroll>(g0 + kG, lane, 0) < cnt)
+          list_batch<DIM, L, kUnroll>(pc.nbr, pc.nstride, i, lane, g0 + kG, cnt, en);
         if constexpr (kLazy) {
           test_lazy(valid, e, q);
         } else {
           pin_records<T, DIM, kUnroll, NR>(q);
           test(valid, e, q);
+        }
+        if (kAheadN) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) e[u] = en[u];
         }
       }
       return;
