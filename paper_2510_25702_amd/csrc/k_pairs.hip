@@ -221,8 +221,9 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   if (i >= n) return 0;
   int m_pairs = 0;
   // the tag, the position and the head of the list load together
+  constexpr int NR = (DIM == 3 && TURB) ? 3 : 2;   // record vectors
   const uint32_t ti = pc.tag[i];
-  const auto h = list_head<T, DIM, L>(pc, i, lane);
+  const auto h = list_head<T, DIM, L, NR>(pc, i, lane);
   const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
   if (!is_real(ti)) {
     if (a.rates_only && lane == 0) {   // walls and dead slots: zero rates
@@ -275,7 +276,6 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   };
   constexpr bool early = hoist_epilogue<L>();
   if (early) load_update();
-  constexpr int NR = (DIM == 3 && TURB) ? 3 : 2;
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
@@ -485,8 +485,9 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   int m_pairs = 0;
   // the particle's own operands and the head of its list load with its tag
   // (every slot below n holds valid data): none of them waits for the test
+  constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);   // record vectors
   const uint32_t ti = pc.tag[i];
-  const auto h = list_head<T, DIM, L>(pc, i, lane);
+  const auto h = list_head<T, DIM, L, NR>(pc, i, lane);
   const T xr_i[3] = {pc.xr[0][i], pc.xr[1][i], pc.xr[2][i]};
   const T xi[3] = {xr_i[0], xr_i[1], DIM == 3 ? xr_i[2] : T(0)};
   const T pi = a.p[i];
@@ -529,7 +530,6 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
   // small fraction of its terms, so T accumulation would add its own
   // rounding of the partial sums to that of the terms)
   double acc[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
-  constexpr int NR = DIM == 2 ? (MODE >= 2 ? 2 : 1) : (MODE >= 2 ? 3 : 2);
   for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.prec, h,
                                    [&](int j, const T r[3], T r2, const V4<T>* q) {
     ++m_pairs;
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_density(int n, PairCtx<T> pc, Consts<T>
   if (i < n) {
     // the tag, the position and the head of the list load together
     const uint32_t ti = pc.tag[i];
-    const auto h = list_head<T, DIM, L>(pc, i, lane);
+    const auto h = list_head<T, DIM, L, 2>(pc, i, lane);
     const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
     if (is_real(ti)) {
       const T vi[3] = {a.v[0][i], a.v[1][i], DIM == 3 ? a.v[2][i] : T(0)};

@@ -322,8 +322,11 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 // current records, two candidates per lane and batch are best.  Two-lane
 // teams over FP32 3D records take 8 (four chunks of the list per batch; the
 // 3.75M-particle mixer: advection 1932 -> 1673 us, continuity 1853 -> 1541,
-// pressure 2357 -> 2339), FP64 3D ones keep 6 (pressure 3942 against 5374
-// us at 8).
+// pressure 2357 -> 2339), and 12 over two-vector records (continuity 1423
+// -> 1342 us at three wavefronts per SIMD against four; 16: 1588 us at
+// two); fewer candidates per batch for more resident wavefronts lost (6 / 4:
+// pressure 2321 / 2386 against 2179 us).  FP64 3D ones keep 6 (pressure
+// 3942 against 5374 us at 8).
 #ifndef SPHX_REC_UNROLL_WIDE
 #define SPHX_REC_UNROLL_WIDE 2
 #endif
@@ -333,14 +336,19 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 #ifndef SPHX_REC_UNROLL_NARROW3
 #define SPHX_REC_UNROLL_NARROW3 8
 #endif
+#ifndef SPHX_REC_UNROLL_NARROW3_NR2
+#define SPHX_REC_UNROLL_NARROW3_NR2 12
+#endif
 #ifndef SPHX_REC_UNROLL_ONE
 #define SPHX_REC_UNROLL_ONE 6
 #endif
-template <typename T, int DIM, int L>
+template <typename T, int DIM, int L, int NR>
 constexpr int rec_unroll() {
   if (L >= 4) return SPHX_REC_UNROLL_WIDE;
   if (L == 1) return SPHX_REC_UNROLL_ONE;
-  return (DIM == 3 && sizeof(T) == 4) ? SPHX_REC_UNROLL_NARROW3 : SPHX_REC_UNROLL_NARROW;
+  if (DIM == 3 && sizeof(T) == 4)
+    return NR <= 2 ? SPHX_REC_UNROLL_NARROW3_NR2 : SPHX_REC_UNROLL_NARROW3;
+  return SPHX_REC_UNROLL_NARROW;
 }
 
 // The start of a particle's walk of its list: the count, the stale word and
@@ -365,10 +373,10 @@ constexpr bool head_early() {
   return L >= SPHX_HEAD_MIN_LANES;
 }
 
-template <typename T, int DIM, int L>
-__device__ __forceinline__ ListHead<rec_unroll<T, DIM, L>()> list_head(const PairCtx<T>& pc,
-                                                                       int i, int lane) {
-  constexpr int U = rec_unroll<T, DIM, L>();
+template <typename T, int DIM, int L, int NR>
+__device__ __forceinline__ ListHead<rec_unroll<T, DIM, L, NR>()> list_head(const PairCtx<T>& pc,
+                                                                           int i, int lane) {
+  constexpr int U = rec_unroll<T, DIM, L, NR>();
   ListHead<U> h;
   h.cnt = 0;
   h.stale = true;
@@ -420,9 +428,9 @@ constexpr bool hoist_epilogue() {
 template <typename T, int DIM, int L, int NR, typename Fn>
 __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, int lane,
                                                   const T xi[3], const V4<T>* const* rec,
-                                                  const ListHead<rec_unroll<T, DIM, L>()>& h,
+                                                  const ListHead<rec_unroll<T, DIM, L, NR>()>& h,
                                                   Fn&& fn) {
-  constexpr int kUnroll = rec_unroll<T, DIM, L>();
+  constexpr int kUnroll = rec_unroll<T, DIM, L, NR>();
   constexpr bool kAhead = L >= SPHX_AHEAD_MIN_LANES;
   // the candidates of one batch: entries e, records q
   // 3D records span two or three vectors but about 40 % of the list's
