@@ -252,6 +252,7 @@ def run_gpu(case, precision, steps, warmup, torch):
     t0 = time.perf_counter()
     n_ac = 0
     real_steps = 0
+    outgrown = 0
     for i in range(steps):
         # HIP events around every kernel of one step in PROFILE_EVERY (the
         # event records cost host time; the sampled launches give the
@@ -260,6 +261,7 @@ def run_gpu(case, precision, steps, warmup, torch):
         info, cnt = g.advance()
         n_ac += info.n_ac
         real_steps += cnt.n_real
+        outgrown += info.list_outgrown > 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     g.profile(False)
@@ -267,7 +269,7 @@ def run_gpu(case, precision, steps, warmup, torch):
     stats = g.kernel_stats()
     dt = t1 - t0
     return dict(seconds=dt, particle_steps=real_steps, n_real=n_real0, pairs=pairs,
-                n_ac=n_ac, stats=stats, sim=g)
+                n_ac=n_ac, stats=stats, sim=g, outgrown=outgrown)
 
 
 def obc_ablation(steps=3000, navg=1000, precision=0):
@@ -815,7 +817,8 @@ def gpu_leg(case, precision, steps, warmup, torch):
     return r, dict(value=round(r["particle_steps"] / r["seconds"], 1),
                    ms_per_step=round(1e3 * r["seconds"] / steps, 4),
                    pairs_per_s=round(r["pairs"] / r["seconds"], 1),
-                   acoustic_substeps=int(r["n_ac"]), roofline=roof, kernels=kern)
+                   acoustic_substeps=int(r["n_ac"]), list_outgrown_steps=int(r["outgrown"]),
+                   roofline=roof, kernels=kern)
 
 
 def sweep(names, steps, warmup, torch):
@@ -904,6 +907,7 @@ def main():
                    "acoustic_substeps": f32["acoustic_substeps"]},
         "pairs_per_s": f32["pairs_per_s"],
         "pairs_per_step": round(r32["pairs"] / args.steps, 1),
+        "list_outgrown_steps": f32["list_outgrown_steps"],
         "roofline": roof,
         "kernels_sampled_every": PROFILE_EVERY,
         "kernels": {k: {"ms": round(v.total_ms, 3), "launches": int(v.launches),

@@ -160,7 +160,11 @@ typedef struct {
 
 typedef struct {
   double dt_adv, dt_ac, vmax, numax, t;
-  int32_t n_ac, pad;
+  int32_t n_ac;
+  /* sph_advance: 1 when a particle outgrew the step's neighbour list (the
+   * later passes of the step scanned the cell stencil), else 0; sph_step: -1
+   * (not known before the next buffer update) */
+  int32_t list_outgrown;
   int64_t step;
 } sph_step_info;
 

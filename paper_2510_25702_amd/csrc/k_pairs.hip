@@ -169,6 +169,8 @@ __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts
   if (BUILD && g == 0) {
     nb.stale[0] = 0;
     nb.stale[1] = 0;
+    // the list radius this build takes, for the passes' check of it
+    nb.lrad[1] = (nb.tight && nb.lrad[0] > 0.0) ? 1.0 : 0.0;
   }
   constexpr int KS = BUILD ? list_stage<DIM, L>() : 0;
   __shared__ uint32_t stage[KS > 0 ? (256 / L) * KS : 1];
@@ -466,6 +468,13 @@ struct PressArgs {
   V4<T>* drec[2];           // continuity records of the new state (written)
   const T* xrb[3];          // positions at the neighbour-list build (NULL: no list)
   uint32_t* stale_w;        // outgrown-list word of the next positions
+  // the build's list radius: lrad[1] = 1 for the relative-motion radius
+  // (check |x - x_build - u_c t| <= s_i and t <= Δt_ad = lrad[0]), else the
+  // cell-size radius (check |x - x_build| <= the skin)
+  const double* lrad;
+  const T* lskin;
+  const T* cell_u[3];
+  double t_el;              // time since the build at the end of this sub-step
   const uint32_t* pid;
   const BufDev* bufs;
   const int32_t* bidx;
@@ -651,12 +660,23 @@ __device__ __forceinline__ int pressure_body(int i, int lane, int n, const PairC
       xnew[k] = xr_i[k];
     }
   }
+  if (a.xrb[0] && a.lrad[1] > 0.0) {
+    // relative-motion radius: the displacement less the cell's drift
+    d2 = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      const double dd = ((double)xnew[k] - (double)xrb_i[k]) - (double)a.cell_u[k][c] * a.t_el;
+      d2 += dd * dd;
+    }
+    const double s = (double)a.lskin[i];
+    if (!(d2 <= s * s) || !(a.t_el <= a.lrad[0] * (1.0 + 1e-9))) atomicOr(a.stale_w, 1u);
+  } else if (a.xrb[0] && !(d2 <= C.skin * C.skin)) {
+    atomicOr(a.stale_w, 1u);
+  }
   T plo = T(0);   // the FP64 remainder of p_i (2D FP32: continuity pressure differences)
   if constexpr (f64_kernel<T, DIM>())
     plo = (T)(eos(rho_i, C.turbulence ? (double)a.k[i] : 0.0, C.rho0, C.c0, C.turbulence) -
               (double)pi);
   write_drec<T, DIM>(a.drec, i, xnew, vnew, pi, vol_i, plo);
-  if (a.xrb[0] && !(d2 <= C.skin * C.skin)) atomicOr(a.stale_w, 1u);
   if (bad) atomicOr(a.flags, kFlagSkin);
   return m_pairs;
 }
@@ -889,7 +909,8 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
                                                      uint32_t* flags,
                                                      const uint64_t* next_pid, int n_alive,
                                                      int32_t* __restrict__ ns,
-                                                     int32_t* __restrict__ rb, KeyOut ko) {
+                                                     int32_t* __restrict__ rb, KeyOut ko,
+                                                     const uint32_t* __restrict__ stale) {
   __shared__ double sm[2][256 / kWave];
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < 1032; k += blockDim.x) rb[k] = counters[k];
@@ -942,10 +963,82 @@ __global__ __launch_bounds__(256) void k_reduce_post(int n, int n_max, int32_t* 
     part[1] = b;
     if (blockIdx.x == 0) {
       rb[1032] = (int32_t)*flags;
+      rb[1035] = (int32_t)(stale[0] | stale[1]);   // the step's list outgrown
       const uint64_t np = *next_pid;
       rb[1033] = (int32_t)(uint32_t)(np & 0xFFFFFFFFull);
       rb[1034] = (int32_t)(uint32_t)(np >> 32);
     }
+  }
+}
+
+// The coming advection step's Δt_ad from per-workgroup maxima {|v|^2,
+// nu_t} (the post-update reduction's, in the read-back buffer, or a fresh
+// reduction's), formed as the host forms it (dual criteria, Sec. 2.3), for
+// the list radius of a build.  lrad[0] = Δt_ad, 0 when not finite.
+__global__ __launch_bounds__(64) void k_list_dt(int nb, const double* __restrict__ part, double h,
+                                                double cfl, double u_ref, double nu_l,
+                                                double* lrad) {
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nb; q += kWave) {
+    a = fmax(a, part[2 * q]);
+    b = fmax(b, part[2 * q + 1]);
+  }
+  a = wave_max(a);
+  b = wave_max(b);
+  if (threadIdx.x == 0) {
+    const double dt = cfl * fmin(h / fmax(sqrt(a), u_ref), h * h / (2.0 * (nu_l + b)));
+    lrad[0] = (dt > 0.0 && dt < INFINITY) ? dt : 0.0;
+  }
+}
+
+// Per cell of a fresh build, for the relative-motion list radius: u_c, the
+// mean velocity of the cell's moving (real) particles, and for each of its
+// particles s_i = kListSkinFactor |v_i - u_c| Δt_ad + kListSkinFloor h, the
+// deviation from drifting with u_c allowed over the step (-1 marks a wall,
+// which does not move).  Skipped when Δt_ad is unknown.
+#ifndef SPHX_LIST_SKIN_FACTOR
+#define SPHX_LIST_SKIN_FACTOR 1.5
+#endif
+#ifndef SPHX_LIST_SKIN_FLOOR
+#define SPHX_LIST_SKIN_FLOOR 0.05
+#endif
+constexpr double kListSkinFactor = SPHX_LIST_SKIN_FACTOR;
+constexpr double kListSkinFloor = SPHX_LIST_SKIN_FLOOR;
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_cell_skin(int ncell, const int32_t* __restrict__ cs,
+                                                   const T* v0, const T* v1, const T* v2,
+                                                   const uint32_t* __restrict__ tag,
+                                                   const double* __restrict__ lrad, double h,
+                                                   const int32_t* __restrict__ ns, T* u0, T* u1,
+                                                   T* u2, T* skin) {
+  if (ns && ns[2]) return;
+  const double dt = lrad[0];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell || !(dt > 0.0)) return;
+  const int j0 = cs[c], j1 = cs[c + 1];
+  double su[3] = {0.0, 0.0, 0.0};
+  int m = 0;
+  for (int j = j0; j < j1; ++j) {
+    if (!is_real(tag[j])) continue;
+    su[0] += (double)v0[j];
+    su[1] += (double)v1[j];
+    if (DIM == 3) su[2] += (double)v2[j];
+    ++m;
+  }
+  const double inv = m > 0 ? 1.0 / m : 0.0;
+  const T u[3] = {(T)(su[0] * inv), (T)(su[1] * inv), (T)(su[2] * inv)};
+  u0[c] = u[0];
+  u1[c] = u[1];
+  if (DIM == 3) u2[c] = u[2];
+  for (int j = j0; j < j1; ++j) {
+    double sj = -1.0;   // a wall: reference velocity 0, no deviation
+    if (is_real(tag[j])) {
+      const double d0 = (double)v0[j] - (double)u[0], d1 = (double)v1[j] - (double)u[1];
+      const double d2 = DIM == 3 ? (double)v2[j] - (double)u[2] : 0.0;
+      sj = kListSkinFactor * sqrt(d0 * d0 + d1 * d1 + d2 * d2) * dt + kListSkinFloor * h;
+    }
+    skin[j] = (T)sj;
   }
 }
 
@@ -1113,9 +1206,19 @@ inline int corr_lanes(const sph_ctx* c, int64_t n) {
   }
 
 template <typename T, int DIM>
-hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
+hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight) {
   Consts<T> C = make_consts<T>(c);
   c->nbr_valid = false;
+  tight = tight && c->use_nbr;
+  if (tight) {
+    const int nc = c->grid.ncell;
+    k_cell_skin<T, DIM><<<(nc + 255) / 256, 256, 0, c->stream>>>(
+        nc, c->S.cell_start, tp<T>(c->F.v[0].live()), tp<T>(c->F.v[1].live()),
+        tp<T>(c->F.v[2].live()), c->F.tag.live(), c->S.lrad, c->P.h, ns, tp<T>(c->F.cell_u[0]),
+        tp<T>(c->F.cell_u[1]), tp<T>(c->F.cell_u[2]), tp<T>(c->F.lskin));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   PairCtx<T> pc = make_pc<T>(c, c->F.xr, c->F.x[0].cur);   // stencil: no list yet
   CorrArgs<T> a;
   for (int k = 0; k < 3; ++k) a.x[k] = c->F.x[k].live();
@@ -1136,6 +1239,12 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
   nb.stage = nullptr;
   nb.kstage = 0;
   nb.queue = nullptr;
+  nb.tight = tight ? 1 : 0;
+  nb.lrad = c->S.lrad;
+  nb.lskin = tp<T>(c->F.lskin);
+  for (int k = 0; k < 3; ++k) nb.cell_u[k] = tp<T>(c->F.cell_u[k]);
+  nb.two_h = (T)(2.0 * c->P.h);
+  nb.rl = (T)rl;
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr) {
@@ -1232,6 +1341,10 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
   a.bufs = c->S.bufs;
   a.bidx = c->S.bidx;
   a.flags = c->S.flags;
+  a.lrad = c->S.lrad;
+  a.lskin = tp<T>(F.lskin);
+  for (int k = 0; k < 3; ++k) a.cell_u[k] = tp<T>(F.cell_u[k]);
+  a.t_el = (double)(c->substep + 1) * dt;
   a.dt = dt;
   a.step = c->step;
   a.t = c->t;
@@ -1337,7 +1450,7 @@ hipError_t reduce_impl(sph_ctx* c, double* host2, bool after_update, bool keys) 
           (int)n, (int)n_max, c->S.counters, tp<T>(F.v[0].live()), tp<T>(F.v[1].live()),
           tp<T>(F.v[2].live()), F.rho.live(), tp<T>(F.nut.live()), F.tag.live(),
           c->P.turbulence, c->S.flags, c->S.next_pid, (int)c->n_alive, c->S.nstate,
-          c->pinned_dev, ko);
+          c->pinned_dev, ko, c->S.stale);
     };
     if (c->P.dim == 2) go(std::integral_constant<int, 2>());
     else go(std::integral_constant<int, 3>());
@@ -1404,8 +1517,8 @@ hipError_t export_B_impl(sph_ctx* c, double* B) {
        ? (c->P.dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)) \
        : (c->P.dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)))
 
-hipError_t launch_correction(sph_ctx* c, const int32_t* ns, int64_t n_grid) {
-  return SPHX_DISPATCH(correction_impl, c, ns, n_grid);
+hipError_t launch_correction(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight) {
+  return SPHX_DISPATCH(correction_impl, c, ns, n_grid, tight);
 }
 
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
@@ -1432,6 +1545,20 @@ hipError_t launch_reduce(sph_ctx* c, double* host2, bool after_update, bool keys
 }
 
 hipError_t launch_export_B(sph_ctx* c, double* B) { return SPHX_DISPATCH(export_B_impl, c, B); }
+
+hipError_t launch_list_dt(sph_ctx* c, bool fresh) {
+  const sph_params& P = c->P;
+  const double* part = reinterpret_cast<const double*>(c->pinned_dev + 1040);
+  int nb = c->post_blocks;
+  if (fresh) {   // the maxima of the current state (the same set of particles, exact maxima)
+    hipError_t e = launch_reduce(c, nullptr, false, false);
+    if (e != hipSuccess) return e;
+    part = c->S.red + 4;
+    nb = nblk(c->n_total);
+  }
+  k_list_dt<<<1, kWave, 0, c->stream>>>(nb, part, P.h, P.cfl_adv, P.u_ref, P.nu_l, c->S.lrad);
+  return hipGetLastError();
+}
 
 hipError_t launch_neighbors_noalloc(sph_ctx* c, int32_t* row_ptr, int32_t* col, int64_t cap,
                                     int64_t* n_pairs) {

@@ -159,7 +159,7 @@ struct Plan {
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
       off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate,
-      off_shift[3];
+      off_shift[3], off_cellu[3], off_lskin, off_lrad;
   int n_cand;
 };
 
@@ -200,6 +200,9 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_slot = L.take(C * 4);
   pl->off_perm = L.take(C * 4);
   pl->off_dec = L.take(C * 4);
+  for (int k = 0; k < 3; ++k) pl->off_cellu[k] = L.take((size_t)g.ncell * sT);
+  pl->off_lskin = L.take(C * sT);
+  pl->off_lrad = L.take(32);
   pl->off_count = L.take((size_t)g.ncell * 4);
   pl->off_cstart = L.take(((size_t)g.ncell + 1) * 4);
   pl->off_bsums = L.take(4096 * 4);
@@ -374,12 +377,16 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   bool pre = false;
   if (prelaunch) {
     const int64_t n_max = std::min<int64_t>(c->cap, c->n_total + kMaxInject);
+    // the coming step's Δt_ad for the list radius, from the maxima just reduced
+    const bool tight = c->use_nbr && c->tight_list;
+    e = tight ? launch_list_dt(c) : hipSuccess;
     profile_launch(c, SPH_K_CELLS);
-    e = launch_build_cells(c, n_max, n_max, c->S.nstate, true);   // keys came with the reduction
+    if (e == hipSuccess)
+      e = launch_build_cells(c, n_max, n_max, c->S.nstate, true);   // keys came with the reduction
     prof_end(c);
     if (e == hipSuccess) {
       profile_launch(c, SPH_K_CORRECTION);
-      e = launch_correction(c, c->S.nstate, n_max);
+      e = launch_correction(c, c->S.nstate, n_max, tight);
       prof_end(c);
     }
     if (e != hipSuccess) {
@@ -394,6 +401,7 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
   if (c->prof.on) resolve_events(c);
   const int32_t* cnt = (const int32_t*)hb;
   uint32_t flags = (uint32_t)cnt[1032];
+  c->last_outgrown = cnt[1035] != 0;
   if (flags & kFlagCapacity) {
     // nothing was injected (and the prelaunched kernels returned at once):
     // undo the tag changes the decisions applied, clear the flag and the
@@ -535,8 +543,11 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   for (int k = 0; k < 2; ++k) F.drec[k] = w + pl.off_drec[k];
   for (int k = 0; k < 3; ++k) F.arec[k] = w + pl.off_arec[k];
   for (int k = 0; k < 3; ++k) F.shift[k] = params->tvf_alpha != 0.0 ? w + pl.off_shift[k] : nullptr;
+  for (int k = 0; k < 3; ++k) F.cell_u[k] = w + pl.off_cellu[k];
+  F.lskin = w + pl.off_lskin;
   F.nbr_k = params->dim == 2 ? kNbrMax2 : kNbrMax3;
   if (const char* nl = std::getenv("SPHX_NBR_LIST")) c->use_nbr = std::atoi(nl) != 0;
+  if (const char* tl = std::getenv("SPHX_LIST_TIGHT")) c->tight_list = std::atoi(tl) != 0;
   Scratch& S = c->S;
   S.key = (int32_t*)(w + pl.off_key);
   S.slot = (int32_t*)(w + pl.off_slot);
@@ -553,6 +564,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   S.flags = (uint32_t*)(w + pl.off_flags);
   S.stale = (uint32_t*)(w + pl.off_stale);
   S.nstate = (int32_t*)(w + pl.off_nstate);
+  S.lrad = (double*)(w + pl.off_lrad);
   S.red = (double*)(w + pl.off_red);
   S.pairs = (long long*)(w + pl.off_pairs);
   S.next_pid = (uint64_t*)(w + pl.off_npid);
@@ -611,6 +623,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   if (e == hipSuccess) e = hipMemsetAsync(S.flags, 0, 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.stale, 0, 8, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.nstate, 0, 16, st);
+  if (e == hipSuccess) e = hipMemsetAsync(S.lrad, 0, 32, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.counters, 0, 1040 * 4, st);
   if (e == hipSuccess) e = hipMemsetAsync(S.count, 0, (size_t)c->grid.ncell * 4, st);
   if (e == hipSuccess)
@@ -791,7 +804,12 @@ sph_status sph_correction(sph_ctx* c) {
   if (!c->cells_valid || c->moved)
     return fail(c, SPH_E_STATE, "sph_correction needs a cell build after the last position change");
   profile_launch(c, SPH_K_CORRECTION);
-  hipError_t e = launch_correction(c);
+  // the relative-motion list radius, from the maxima of this state (the
+  // last buffer update's when they describe it, else a fresh reduction): the
+  // list is the one sph_advance builds for the same state
+  const bool tight = c->use_nbr && c->tight_list;
+  hipError_t e = tight ? launch_list_dt(c, !c->red_valid) : hipSuccess;
+  if (e == hipSuccess) e = launch_correction(c, nullptr, 0, tight);
   prof_end(c);
   if (e != hipSuccess) return hip_fail(c, e, "correction");
   c->B_valid = true;
@@ -878,6 +896,7 @@ sph_status sph_step(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* out) {
     out->numax = numax;
     out->t = c->t;
     out->n_ac = n_ac;
+    out->list_outgrown = -1;   // known after the next buffer update (sph_advance)
     out->step = c->step;
   }
   return SPH_OK;
@@ -895,6 +914,7 @@ sph_status sph_advance(sph_ctx* c, const sph_step_ctrl* ctrl, sph_step_info* inf
   }
   if (st == SPH_OK) st = sph_step(c, ctrl, info);
   if (st == SPH_OK) st = buffer_update(c, nullptr, nullptr, 0, counts, true);
+  if (st == SPH_OK && info) info->list_outgrown = c->last_outgrown ? 1 : 0;
   return st;
 }
 

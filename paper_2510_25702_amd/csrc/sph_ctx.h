@@ -51,6 +51,11 @@ struct Fields {
   void* drec[2];           // position, velocity, p, volume (negative: wall)
   void* arec[3];           // position, velocity, volume (negative: wall), RANS fields
   void* shift[3];          // transport-velocity shift of the step (NULL: off)
+  // relative-motion list radius (builds launched by sph_advance): the mean
+  // velocity of each cell's moving particles and each particle's allowed
+  // deviation from drifting with it over the step
+  void* cell_u[3];         // [ncell] (pair precision)
+  void* lskin;             // [cap] (pair precision)
 };
 
 struct Scratch {
@@ -69,6 +74,7 @@ struct Scratch {
   uint32_t* flags;         // [1] error flags
   uint32_t* stale;         // [2] neighbour list outgrown (by sub-step parity)
   int32_t* nstate;         // [4] next build's sizes after an update: n_in, n_out, skip
+  double* lrad;            // [4] Δt_ad of the coming step (0: unknown), list mode of the build
   double* red;             // reduction partials
   long long* pairs;        // [1] pair counter
   uint64_t* next_pid;      // [1]
@@ -120,6 +126,8 @@ struct sph_ctx {
   int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
   int corr_override = 0;        // lanes per particle of the correction pass (0: auto)
   bool use_nbr = true;          // neighbour passes read the per-step list
+  bool tight_list = true;       // sph_advance's builds take the relative-motion radius
+  bool last_outgrown = false;   // the last updated step's list was outgrown
   bool nbr_valid = false;       // the list matches the current cell build
   int substep = 0;              // acoustic sub-step being launched
   bool red_valid = false;       // red_v2 / red_nut hold the reduction of the current state
@@ -146,7 +154,14 @@ hipError_t launch_derive_nut(sph_ctx* c, int64_t n);
 // (launch_reduce with keys), so the build starts at the scan.
 hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out,
                               const int32_t* ns = nullptr, bool keys_done = false);
-hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_grid = 0);
+// tight: the list takes the relative-motion radius (the coming step's Δt_ad
+// on the device, from launch_list_dt); otherwise the cell size
+hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_grid = 0,
+                             bool tight = false);
+// the coming step's Δt_ad, as the host forms it, into S.lrad[0]: from the
+// post-update reduction's maxima (a build launched before the host has
+// them), or with fresh a reduction of the current state first
+hipError_t launch_list_dt(sph_ctx* c, bool fresh = false);
 // time-step reduction (max |v|^2, max nu_t, flags) into S.red[0..2], and
 // into host memory when out_host3 is given; after_update also covers the
 // particles the last buffer update appended

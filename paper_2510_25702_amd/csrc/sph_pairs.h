@@ -625,6 +625,14 @@ struct NbrOut {
   uint32_t* stage;   // LDS rows of this particle's first kstage entries (NULL: none)
   int kstage;
   V4<T>* queue;      // LDS pair queue of this wavefront (pair_queue entries per lane)
+  // relative-motion radius (tight, with lrad[0] = the step's Δt_ad > 0): j is
+  // listed when |r_ij| < 2h + s_i + s_j + |u_c(i) - u_c(j)| Δt_ad (u_c(j) = 0
+  // for a wall), at most the cell size rl; otherwise when |r_ij| < rl
+  int tight;
+  double* lrad;
+  const T* lskin;
+  const T* cell_u[3];
+  T two_h, rl;
 };
 
 // Pairs within 2h found by the 3D FP32 list build wait in a per-lane queue
@@ -689,6 +697,17 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   const int cy = cyz % pc.ny;
   const int cz = cyz / pc.ny;
   constexpr int zr = DIM == 3 ? 1 : 0;
+  // relative-motion radius (NbrOut): the parts of i's bound, a wall's term
+  const bool tight = o.tight && o.lrad[0] > 0.0;
+  T rad_i = o.rl, du_wall = T(0), uc_i[3] = {T(0), T(0), T(0)}, dt_l = T(0);
+  if (tight) {
+    dt_l = (T)o.lrad[0];
+    rad_i = o.two_h + o.lskin[i];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) uc_i[k] = o.cell_u[k][c];
+    du_wall = pair_dist(DIM == 3 ? (uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) + uc_i[2] * uc_i[2]
+                                 : uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) * dt_l;
+  }
   constexpr int Q = pair_queue<T, DIM>();
   int qn = 0;   // this lane's queued pairs
   // the queued pairs' terms, in the order the lane found them (wavefront-
@@ -720,9 +739,22 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
       const int dy = r3 - 1;
       const int j0 = rows[r3][0], j1 = rows[r3][1], j2 = rows[r3][2], j3 = rows[r3][3];
       const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      // |u_c(i) - u_c| Δt_ad for the row's three cells
+      T du[3] = {T(0), T(0), T(0)};
+      if (tight) {
+        const int cb = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx - 1;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          T d[3] = {T(0), T(0), T(0)};
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) d[k] = uc_i[k] - o.cell_u[k][cb + q];
+          du[q] = pair_dist(DIM == 3 ? (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+                                     : d[0] * d[0] + d[1] * d[1]) * dt_l;
+        }
+      }
       // the same trip count for every lane of the team
       for (int jb = j0; jb < j3; jb += kUnroll * L) {
-        T q0[kUnroll], q1[kUnroll], q2[kUnroll], qv[kUnroll];
+        T q0[kUnroll], q1[kUnroll], q2[kUnroll], qv[kUnroll], qs[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int j = jb + u * L + lane;
@@ -732,6 +764,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           q1[u] = pc.xr[1][js];
           q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
           qv[u] = pc.vol[js];   // with the positions: one round trip per batch
+          qs[u] = tight ? o.lskin[js] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -744,7 +777,15 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
           const T r2 = dist2<T, DIM>(r);
           const bool in = j < j3 && j != i;
-          const bool acc = in && r2 < o.rl2;
+          T rad2 = o.rl2;
+          if (tight) {
+            // a wall (s_j < 0) does not move; a little above for rounding
+            const T dux = dx < 0 ? du[0] : (dx == 0 ? du[1] : du[2]);
+            const T rad = rad_i + (qs[u] < T(0) ? du_wall : qs[u] + dux);
+            const T rc = rad * T(1.00002);
+            rad2 = rc < o.rl ? rc * rc : o.rl2;
+          }
+          const bool acc = in && r2 < rad2;
           int off = 0, tot = acc ? 1 : 0;
           if (L > 1) {
             // accepted lanes of the team; off = those below this lane

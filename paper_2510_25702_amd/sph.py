@@ -81,7 +81,7 @@ class sph_step_ctrl(C.Structure):
 class sph_step_info(C.Structure):
     _fields_ = [("dt_adv", C.c_double), ("dt_ac", C.c_double), ("vmax", C.c_double),
                 ("numax", C.c_double), ("t", C.c_double), ("n_ac", C.c_int32),
-                ("pad", C.c_int32), ("step", C.c_int64)]
+                ("list_outgrown", C.c_int32), ("step", C.c_int64)]
 
 
 class sph_kernel_stats(C.Structure):
