@@ -59,7 +59,17 @@ struct CorrArgs {
   int mirror;
 };
 
-template <typename T, int DIM, int L, bool BUILD>
+// The 3D correction runs as two kernels: the stencil scan writes the list
+// only (MOMENT false), then the kernel without BUILD takes the moment and B
+// over the list it wrote (~100 entries instead of ~1000 candidates whose
+// terms a wavefront evaluated on nearly every batch).  2D scans ~100
+// candidates against ~25 entries and keeps one kernel.
+template <int DIM>
+constexpr bool split_correction() {
+  return DIM == 3;
+}
+
+template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true>
 __device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
                                                const Consts<T>& C, const CorrArgs<T>& a,
                                                const NbrOut<T>& nb) {
@@ -67,6 +77,13 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   int m_pairs = 0;
   const uint32_t ti = pc.tag[i];
   if (BUILD) build_begin<T, DIM>(pc, i, lane, nb);
+  if (BUILD && !MOMENT) {
+    if (is_real(ti)) {
+      const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      scan_build<T, DIM, L, 0>(pc, i, lane, xi, nb, [](int, const T*, T, T) {});
+    }
+    return m_pairs;
+  }
   if (!is_real(ti)) {
     if (lane == 0) {
       a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
@@ -158,7 +175,7 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   return m_pairs;
 }
 
-template <typename T, int DIM, int L, bool BUILD>
+template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true>
 __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
                                                     NbrOut<T> nb, const int32_t* __restrict__ ns) {
   if (ns) {   // sizes on the device: the build of this state was prelaunched
@@ -176,10 +193,10 @@ __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts
   __shared__ uint32_t stage[KS > 0 ? (256 / L) * KS : 1];
   nb.kstage = KS;
   nb.stage = KS > 0 ? stage + (threadIdx.x / L) * KS : nullptr;
-  constexpr int PQ = BUILD ? pair_queue<T, DIM>() : 0;
+  constexpr int PQ = (BUILD && MOMENT) ? pair_queue<T, DIM>() : 0;
   __shared__ V4<T> pqueue[PQ > 0 ? PQ * 256 : 1];
   nb.queue = PQ > 0 ? pqueue + (threadIdx.x / kWave) * (PQ * kWave) : nullptr;
-  const int m = correction_body<T, DIM, L, BUILD>(g / L, g % L, n, pc, C, a, nb);
+  const int m = correction_body<T, DIM, L, BUILD, MOMENT>(g / L, g % L, n, pc, C, a, nb);
   count_pairs(pc.pairs, m);
 }
 
@@ -997,7 +1014,7 @@ __global__ __launch_bounds__(64) void k_list_dt(int nb, const double* __restrict
 // deviation from drifting with u_c allowed over the step (-1 marks a wall,
 // which does not move).  Skipped when Δt_ad is unknown.
 #ifndef SPHX_LIST_SKIN_FACTOR
-#define SPHX_LIST_SKIN_FACTOR 1.5
+#define SPHX_LIST_SKIN_FACTOR 2.0
 #endif
 #ifndef SPHX_LIST_SKIN_FLOOR
 #define SPHX_LIST_SKIN_FLOOR 0.05
@@ -1247,7 +1264,23 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
   nb.rl = (T)rl;
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
-  if (c->use_nbr) {
+  if (c->use_nbr && split_correction<DIM>()) {
+    // the list, then the moment over it (its own lane count, the passes');
+    // under profiling the section's events bracket both kernels
+    hipEvent_t pa = c->prof.ext_a, pb = c->prof.ext_b;
+    c->prof.ext_a = c->prof.ext_b = nullptr;
+    if (pa) (void)hipEventRecord(pa, c->stream);
+    SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true, false>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PairCtx<T> pl = pc;
+    pl.nbr = c->F.nbr;
+    pl.ncnt = c->F.ncnt;
+    pl.stale = nullptr;
+    const int Lm = team_lanes(c);
+    SPHX_TEAM_SWITCH(Lm, launch_pass(c, &k_correction<T, DIM, TL, false, true>, nblk(n * TL), (int)n, pl, C, a, nb, ns));
+    if (pb) (void)hipEventRecord(pb, c->stream);
+  } else if (c->use_nbr) {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
   } else {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, false>, nblk(n * TL), (int)n, pc, C, a, nb, ns));

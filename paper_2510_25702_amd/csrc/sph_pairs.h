@@ -685,7 +685,7 @@ constexpr int list_stage() {
 // the accepted candidates in candidate order with a wavefront ballot, so the
 // list order does not depend on L.  fn(j, r, r2, V_j) is called for the
 // pairs within 2h, in for_neighbors' order.
-template <typename T, int DIM, int L, typename Fn>
+template <typename T, int DIM, int L, int QD = pair_queue<T, DIM>(), typename Fn>
 __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane, const T xi[3],
                                            const NbrOut<T>& o, Fn&& fn) {
   const int wl = (int)(threadIdx.x & (kWave - 1));
@@ -708,7 +708,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
     du_wall = pair_dist(DIM == 3 ? (uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) + uc_i[2] * uc_i[2]
                                  : uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) * dt_l;
   }
-  constexpr int Q = pair_queue<T, DIM>();
+  constexpr int Q = QD;
   int qn = 0;   // this lane's queued pairs
   // the queued pairs' terms, in the order the lane found them (wavefront-
   // uniform call: every lane with a queued pair takes part)
