@@ -1194,12 +1194,15 @@ inline int nblk(int64_t n) { return (int)((n + 255) / 256) + (n == 0); }
 // passes and takes twice the lanes (two at most sizes: 160 against 242 us at
 // 640k particles, 590 against 731 us at 2.56M).  In 3D (3.75M particles) the
 // passes take 2 lanes (pressure 2.7 against 3.3 ms with one) and the
-// correction 4 (6.9 against 7.6 ms with two).
+// correction 4 (6.9 against 7.6 ms with two).  With the relative-motion
+// list radius (~100 entries) FP64 3D passes take four lanes at every size
+// (the mixer: 26.5 against 29.3 ms per step with two), FP32 keeps two (15.1
+// against 15.7 with four, 19.3 with one).
 inline int team_lanes(const sph_ctx* c) {
   if (c->team_override > 0) return c->team_override;
   const int64_t n = c->n_total;
-  if (c->P.dim == 3)   // ~170 list entries per particle: more lanes at every size
-    return n <= 1000000 ? 4 : 2;
+  if (c->P.dim == 3)   // ~100-170 list entries per particle: more lanes at every size
+    return (n <= 1000000 || c->P.precision == SPH_FP64) ? 4 : 2;
   if (n <= 100000) return 4;
   if (n <= 450000) return 2;
   return 1;
