@@ -57,24 +57,32 @@ struct CorrArgs {
   T* B[6];
   uint32_t* flags;
   int mirror;
+  const V4<T>* arec[2];   // the cell build's advection records (the list moment)
 };
 
 // The 3D correction runs as two kernels: the stencil scan writes the list
 // only (MOMENT false), then the kernel without BUILD takes the moment and B
 // over the list it wrote (~100 entries instead of ~1000 candidates whose
 // terms a wavefront evaluated on nearly every batch).  2D scans ~100
-// candidates against ~25 entries and keeps one kernel.
+// candidates against ~25 entries and keeps one kernel.  The moment walk
+// (REC) reads the list the way the other list passes do: deep batches of
+// the advection records written by the cell build (position first, V only
+// for the candidates within 2h), the next batch's entries loading under the
+// current records.
 template <int DIM>
 constexpr bool split_correction() {
   return DIM == 3;
 }
 
-template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true>
+template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true, bool REC = false>
 __device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
                                                const Consts<T>& C, const CorrArgs<T>& a,
                                                const NbrOut<T>& nb) {
   if (i >= n) return 0;
   int m_pairs = 0;
+  constexpr int NR = 2;
+  ListHead<rec_unroll<T, DIM, L, NR>()> head{};
+  if constexpr (REC) head = list_head<T, DIM, L, NR>(pc, i, lane);
   const uint32_t ti = pc.tag[i];
   if (BUILD) build_begin<T, DIM>(pc, i, lane, nb);
   if (BUILD && !MOMENT) {
@@ -113,8 +121,18 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
     acc(r, r2, vj);
     ++m_pairs;
   };
-  if (BUILD) scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair_v);
-  else for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
+  if (BUILD) {
+    scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair_v);
+  } else if (REC) {
+    // V_j from the record, its sign (a wall) dropped
+    for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, head,
+                                     [&](int, const T r[3], T r2, const auto& q) {
+                                       acc(r, r2, fabs(q[1].c));
+                                       ++m_pairs;
+                                     });
+  } else {
+    for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
+  }
   if (a.mirror) {
     const double xi0 = a.x[0][i], xi1 = a.x[1][i], xi2 = a.x[2][i];
     const double twoh = 2.0 * C.h;
@@ -175,7 +193,7 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   return m_pairs;
 }
 
-template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true>
+template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true, bool REC = false>
 __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
                                                     NbrOut<T> nb, const int32_t* __restrict__ ns) {
   if (ns) {   // sizes on the device: the build of this state was prelaunched
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts
   constexpr int PQ = (BUILD && MOMENT) ? pair_queue<T, DIM>() : 0;
   __shared__ V4<T> pqueue[PQ > 0 ? PQ * 256 : 1];
   nb.queue = PQ > 0 ? pqueue + (threadIdx.x / kWave) * (PQ * kWave) : nullptr;
-  const int m = correction_body<T, DIM, L, BUILD, MOMENT>(g / L, g % L, n, pc, C, a, nb);
+  const int m = correction_body<T, DIM, L, BUILD, MOMENT, REC>(g / L, g % L, n, pc, C, a, nb);
   count_pairs(pc.pairs, m);
 }
 
@@ -1246,6 +1264,7 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
   for (int k = 0; k < 6; ++k) a.B[k] = tp<T>(c->F.B[k]);
   a.flags = c->S.flags;
   a.mirror = c->P.obc_mode >= 3 ? 1 : 0;
+  a.arec[0] = a.arec[1] = nullptr;
   NbrOut<T> nb;
   nb.nbr = c->F.nbr;
   nb.ncnt = c->F.ncnt;
@@ -1280,8 +1299,10 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
     pl.nbr = c->F.nbr;
     pl.ncnt = c->F.ncnt;
     pl.stale = nullptr;
+    CorrArgs<T> am = a;
+    for (int k = 0; k < 2; ++k) am.arec[k] = tp<V4<T>>(c->F.arec[k]);
     const int Lm = team_lanes(c);
-    SPHX_TEAM_SWITCH(Lm, launch_pass(c, &k_correction<T, DIM, TL, false, true>, nblk(n * TL), (int)n, pl, C, a, nb, ns));
+    SPHX_TEAM_SWITCH(Lm, launch_pass(c, &k_correction<T, DIM, TL, false, true, true>, nblk(n * TL), (int)n, pl, C, am, nb, ns));
     if (pb) (void)hipEventRecord(pb, c->stream);
   } else if (c->use_nbr) {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
