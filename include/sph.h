@@ -258,10 +258,10 @@ sph_status sph_set_clock(sph_ctx* ctx, int64_t step, double t);
 sph_status sph_get_clock(const sph_ctx* ctx, int64_t* step, double* t, uint64_t* next_pid);
 
 /* Cell-linked-list build (Sec. 2.4.3: rebuilt after deletion every advection
- * step): stable counting sort of all particles by cell id (particles of one
- * cell keep their relative order in the current arrays), dropping particles
- * tagged SPH_DEAD, and permutation of every field into cell order.
- * Asynchronous. */
+ * step): counting sort of all particles by cell id and, inside a cell, by
+ * quarter of the cell along x (particles of one quarter keep their relative
+ * order in the current arrays), dropping particles tagged SPH_DEAD, and
+ * permutation of every field into that order.  Asynchronous. */
 sph_status sph_build_cells(sph_ctx* ctx);
 
 /* Correction matrix B_i, Eq. (equ-B-matrix), with the mirror boundary

@@ -222,8 +222,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t* __restrict
 }
 
 // K3a: scatter to cell-sorted positions (arbitrary order inside a cell).
+// The entry is the source index with the particle's x quarter of its cell
+// above it (bits 28-29; indices are below 2^26), so that entries order as
+// the placement ranks them.
+constexpr int kQuarterShift = 28;
 __global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t* __restrict__ slot,
                           const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm,
+                          const double* __restrict__ x0, GridDev g,
                           const int32_t* __restrict__ ns) {
   if (ns) {
     if (ns[2]) return;
@@ -233,7 +238,8 @@ __global__ void k_scatter(int n, const int32_t* __restrict__ key, const int32_t*
   if (i >= n) return;
   int k = key[i];
   if (k < 0) return;
-  perm[cell_start[k] + slot[i]] = i;
+  const int q = x_quarter(x0[i] - cell_centre(g.lo[0], k % g.n[0], g.cs), g.cs);
+  perm[cell_start[k] + slot[i]] = i | (q << kQuarterShift);
 }
 
 // K3c: gather every field into cell order; cell-relative positions in T.
@@ -264,13 +270,16 @@ struct GatherArgs {
   uint32_t* flags;
   const int32_t* ns;   // sizes on the device (prelaunched build), or NULL
   V4<T>* arec[3];      // advection records (written)
+  int32_t* cell_q;     // starts of the x quarters 1-3 of each cell (written)
 };
 
 // K3b: place every particle at its cell-ordered slot and copy its fields
-// there.  Inside a cell the order is ascending source index (the previous,
-// deterministic layout; new particles last): the rank of particle s is the
-// number of particles of its cell with a smaller source index, counted over
-// the cell's (arbitrarily ordered) scatter slots.
+// there.  Inside a cell the order is by quarter of the cell along x, then
+// ascending source index (the previous, deterministic layout; new particles
+// last): the rank of particle s is the number of particles of its cell in a
+// lower quarter or in its quarter with a smaller source index, counted over
+// the cell's (arbitrarily ordered) scatter slots.  The particle of rank 0
+// also writes where the cell's quarters 1-3 start.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T, DIM> a) {
   if (a.ns) {
@@ -303,11 +312,21 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
   const int c = a.key[s];
   if (c < 0) return;
   const int b = a.cell_start[c], e = a.cell_start[c + 1];
-  int rank = 0;
-  for (int q = b; q < e; ++q) rank += a.perm[q] < s ? 1 : 0;
+  int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
+  const int me = s | (x_quarter(xv[0] - cell_centre(a.g.lo[0], cc[0], a.g.cs), a.g.cs)
+                      << kQuarterShift);
+  int rank = 0, n1 = 0, n2 = 0, n3 = 0;   // n_k: members in quarters below k
+  for (int q = b; q < e; ++q) {
+    const int pq = a.perm[q];
+    n1 += pq < (1 << kQuarterShift) ? 1 : 0;
+    n2 += pq < (2 << kQuarterShift) ? 1 : 0;
+    n3 += pq < (3 << kQuarterShift) ? 1 : 0;
+    rank += pq < me ? 1 : 0;
+  }
+  if (rank == 0)
+    *reinterpret_cast<int4*>(a.cell_q + 4 * (int64_t)c) = int4{b + n1, b + n2, b + n3, e};
   const int d = b + rank;
   if (d >= n_out) return;
-  int cc[3] = {c % a.g.n[0], (c / a.g.n[0]) % a.g.n[1], c / (a.g.n[0] * a.g.n[1])};
   T xr[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -366,8 +385,8 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32
     k_scan_apply<<<nb, kScanThreads, 0, st>>>(S.count, nc, S.block_sums, S.cell_start, 1, ns);
   }
   if (n_in > 0)
-    k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>((int)n_in, S.key, S.slot,
-                                                          S.cell_start, S.perm, ns);
+    k_scatter<<<(int)((n_in + 255) / 256), 256, 0, st>>>(
+        (int)n_in, S.key, S.slot, S.cell_start, S.perm, F.x[0].live(), g, ns);
   GatherArgs<T, DIM> a;
   a.perm = S.perm;
   a.key = S.key;
@@ -404,6 +423,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32
   a.flags = S.flags;
   a.ns = ns;
   for (int k = 0; k < 3; ++k) a.arec[k] = static_cast<V4<T>*>(F.arec[k]);
+  a.cell_q = S.cell_q;
   k_place<T, DIM><<<(int)((n_in + 255) / 256) + (n_in == 0), 256, 0, st>>>((int)n_in, (int)n_out, a);
   for (int k = 0; k < 3; ++k) {
     F.x[k].flip();

@@ -1284,6 +1284,9 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
   for (int k = 0; k < 3; ++k) nb.cell_u[k] = tp<T>(c->F.cell_u[k]);
   nb.two_h = (T)(2.0 * c->P.h);
   nb.rl = (T)rl;
+  nb.cell_q = c->S.cell_q;
+  nb.q_rl = (T)(rl * (1.0 + 1e-5));
+  nb.q_w = (T)(4.0 / c->P.cell_size);
   const int64_t n = ns ? n_grid : c->n_total;
   const int L = corr_lanes(c, c->n_total);
   if (c->use_nbr && split_correction<DIM>()) {

@@ -159,7 +159,7 @@ struct Plan {
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
       off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate,
-      off_shift[3], off_cellu[3], off_lskin, off_lrad;
+      off_shift[3], off_cellu[3], off_lskin, off_lrad, off_cellq;
   int n_cand;
 };
 
@@ -205,6 +205,7 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_lrad = L.take(32);
   pl->off_count = L.take((size_t)g.ncell * 4);
   pl->off_cstart = L.take(((size_t)g.ncell + 1) * 4);
+  pl->off_cellq = L.take((size_t)g.ncell * 16);
   pl->off_bsums = L.take(4096 * 4);
   std::vector<int32_t> cand = candidate_cells(P, g, B, nbuf);
   pl->n_cand = (int)cand.size();
@@ -555,6 +556,7 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   S.dec = (uint32_t*)(w + pl.off_dec);
   S.count = (int32_t*)(w + pl.off_count);
   S.cell_start = (int32_t*)(w + pl.off_cstart);
+  S.cell_q = (int32_t*)(w + pl.off_cellq);
   S.block_sums = (int32_t*)(w + pl.off_bsums);
   S.cand_cells = (int32_t*)(w + pl.off_cand);
   S.n_cand_cells = pl.n_cand;

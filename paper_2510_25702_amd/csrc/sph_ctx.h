@@ -64,6 +64,7 @@ struct Scratch {
   int32_t* perm;           // [cap] sorted position -> source index
   int32_t* count;          // [ncell] particles per cell
   int32_t* cell_start;     // [ncell + 1]
+  int32_t* cell_q;         // [4 ncell] starts of the x quarters 1-3 of each cell
   int32_t* block_sums;     // scan partials
   uint32_t* dec;           // [cap] buffer decisions
   int32_t* cand_cells;     // candidate cells of the buffer update

@@ -141,6 +141,15 @@ __host__ __device__ inline double cell_centre(double lo, int c, double cs) {
   return lo + ((double)c + 0.5) * cs;
 }
 
+// Quarter of its cell along x of a cell-relative position (0..3, from the
+// low face): the cell build orders each cell by it, so that a stencil scan
+// can leave out the quarters of the neighbouring cells that lie beyond its
+// radius.
+__device__ __forceinline__ int x_quarter(double rel, double cs) {
+  const int q = (int)floor((rel + 0.5 * cs) * (4.0 / cs));
+  return q < 0 ? 0 : (q > 3 ? 3 : q);
+}
+
 // ---------------------------------------------------------------------------
 // SplitMix64 (Steele, Lea & Flood 2014) and the counter-based uniform number
 // u = 2 (z >> 11) 2^-53 - 1, z = mix(mix(mix(seed) ^ pid) ^ (step << 2 | c)).

@@ -633,6 +633,10 @@ struct NbrOut {
   const T* lskin;
   const T* cell_u[3];
   T two_h, rl;
+  // starts of the x quarters 1-3 of every cell (NULL: whole rows), q_rl a
+  // little above rl, q_w = 4 / cell size
+  const int32_t* cell_q;
+  T q_rl, q_w;
 };
 
 // Pairs within 2h found by the 3D FP32 list build wait in a per-lane queue
@@ -678,6 +682,17 @@ constexpr int list_stage() {
   return (SPHX_LIST_STAGE && DIM == 2 && L >= 4) ? kNbrMax2 : 0;
 }
 
+// Candidates per lane and batch of the stencil scan: the position-only
+// loop's, or SPHX_SCAN_UNROLL3 for the 3D scan that writes the list alone
+// (the mixer: 3 and 4 level with 2).
+#ifndef SPHX_SCAN_UNROLL3
+#define SPHX_SCAN_UNROLL3 2
+#endif
+template <int DIM, int QD>
+constexpr int scan_unroll() {
+  return (DIM == 3 && QD == 0) ? SPHX_SCAN_UNROLL3 : kUnroll;
+}
+
 // Cell-stencil scan of particle i that also writes its neighbour list: every
 // j != i with |r_ij|^2 < rl2 (rl = cell size, a little above to cover
 // rounding), in stencil order.  A team of L lanes scans a row together (lane
@@ -708,7 +723,23 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
     du_wall = pair_dist(DIM == 3 ? (uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) + uc_i[2] * uc_i[2]
                                  : uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) * dt_l;
   }
+  // The cell build orders every cell by quarter along x: the members of the
+  // row's cell at +1 in quarters k_hi and above, and of the cell at -1 in
+  // quarters below k_lo, lie farther than q_rl along x (quarter k of the
+  // cell at +1 starts cs / 2 + k cs / 4 above i's cell centre), so each row
+  // is one shorter contiguous range: 2.25 cells instead of 3
+  int k_lo = 0, k_hi = 4;
+  if (o.cell_q) {
+    const T a_hi = (o.q_rl + xi[0] - T(0.5) * pc.csz) * o.q_w;
+    const T a_lo = (xi[0] + T(1.5) * pc.csz - o.q_rl) * o.q_w;
+    k_hi = (int)ceil(a_hi);
+    k_lo = (int)floor(a_lo);
+    k_hi = k_hi < 0 ? 0 : (k_hi > 4 ? 4 : k_hi);
+    k_lo = k_lo < 0 ? 0 : (k_lo > 4 ? 4 : k_lo);
+  }
+  const int ql_k = k_lo > 0 ? k_lo - 1 : 0, qh_k = k_hi > 0 ? k_hi - 1 : 0;
   constexpr int Q = QD;
+  constexpr int SU = scan_unroll<DIM, QD>();
   int qn = 0;   // this lane's queued pairs
   // the queued pairs' terms, in the order the lane found them (wavefront-
   // uniform call: every lane with a queued pair takes part)
@@ -727,17 +758,31 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   for (int dz = -zr; dz <= zr; ++dz) {
     // the cell ranges of the plane's three rows, loaded together (the list
     // stores of a row would otherwise keep the next row's loads behind it)
-    int rows[3][4];
+    int rows[3][4], rq[3][2];
 #pragma unroll
     for (int r3 = 0; r3 < 3; ++r3) {
       const int base = ((cz + dz) * pc.ny + (cy + r3 - 1)) * pc.nx + cx;
 #pragma unroll
       for (int k = 0; k < 4; ++k) rows[r3][k] = pc.cs[base - 1 + k];
+      rq[r3][0] = rq[r3][1] = 0;
+      if (o.cell_q) {
+        rq[r3][0] = o.cell_q[4 * (int64_t)(base - 1) + ql_k];
+        rq[r3][1] = o.cell_q[4 * (int64_t)(base + 1) + qh_k];
+      }
     }
 #pragma unroll
     for (int r3 = 0; r3 < 3; ++r3) {
       const int dy = r3 - 1;
       const int j0 = rows[r3][0], j1 = rows[r3][1], j2 = rows[r3][2], j3 = rows[r3][3];
+      // the row's range within reach (an empty cell's quarter starts are not
+      // written: clamped to the cell)
+      int lo = j0, hi = j3;
+      if (o.cell_q) {
+        const int ql = rq[r3][0] < j0 ? j0 : (rq[r3][0] > j1 ? j1 : rq[r3][0]);
+        const int qh = rq[r3][1] < j2 ? j2 : (rq[r3][1] > j3 ? j3 : rq[r3][1]);
+        lo = k_lo == 0 ? j0 : ql;
+        hi = k_hi == 0 ? j2 : qh;
+      }
       const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
       // |u_c(i) - u_c| Δt_ad for the row's three cells
       T du[3] = {T(0), T(0), T(0)};
@@ -753,13 +798,13 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
         }
       }
       // the same trip count for every lane of the team
-      for (int jb = j0; jb < j3; jb += kUnroll * L) {
-        T q0[kUnroll], q1[kUnroll], q2[kUnroll], qv[kUnroll], qs[kUnroll];
+      for (int jb = lo; jb < hi; jb += SU * L) {
+        T q0[SU], q1[SU], q2[SU], qv[SU], qs[SU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < SU; ++u) {
           const int j = jb + u * L + lane;
           // (an index below 2^26: 32-bit offsets from the arrays' bases)
-          const uint32_t js = (uint32_t)(j < j3 ? j : jb) & kNbrIdxMask;
+          const uint32_t js = (uint32_t)(j < hi ? j : jb) & kNbrIdxMask;
           q0[u] = pc.xr[0][js];
           q1[u] = pc.xr[1][js];
           q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
@@ -767,7 +812,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           qs[u] = tight ? o.lskin[js] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < SU; ++u) {
           const int j = jb + u * L + lane;
           const int dx = j < j1 ? -1 : (j < j2 ? 0 : 1);
           const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
@@ -776,7 +821,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           r[1] = (xi[1] - q1[u]) + oy;
           r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
           const T r2 = dist2<T, DIM>(r);
-          const bool in = j < j3 && j != i;
+          const bool in = j < hi && j != i;
           T rad2 = o.rl2;
           if (tight) {
             // a wall (s_j < 0) does not move; a little above for rounding
@@ -796,7 +841,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           }
           if (acc && cnt + off < o.K) {
             const uint32_t ent = nbr_pack(j, dx, dy, dz);
-            if (cnt + off < o.kstage) o.stage[cnt + off] = ent;
+            if (list_stage<DIM, L>() > 0 && cnt + off < o.kstage) o.stage[cnt + off] = ent;
             else o.nbr[nbr_index<DIM>(cnt + off, i, o.stride)] = ent;
           }
           cnt += tot;
