@@ -271,6 +271,7 @@ struct GatherArgs {
   const int32_t* ns;   // sizes on the device (prelaunched build), or NULL
   V4<T>* arec[3];      // advection records (written)
   int32_t* cell_q;     // starts of the x quarters 1-3 of each cell (written)
+  float* xr32[3];      // FP32 copies of the cell-relative positions (or NULL)
 };
 
 // K3b: place every particle at its cell-ordered slot and copy its fields
@@ -334,6 +335,7 @@ __global__ __launch_bounds__(256) void k_place(int n_in, int n_out, GatherArgs<T
     double org = (k < DIM) ? cell_centre(a.g.lo[k], cc[k], a.g.cs) : 0.0;
     xr[k] = (T)(xv[k] - org);
     a.xro[k][d] = xr[k];
+    if (a.xr32[0]) a.xr32[k][d] = (float)(xv[k] - org);
     a.vo[k][d] = vr[k];
   }
   a.rhoo[d] = r;
@@ -424,6 +426,7 @@ hipError_t build_cells_impl(sph_ctx* c, int64_t n_in, int64_t n_out, const int32
   a.ns = ns;
   for (int k = 0; k < 3; ++k) a.arec[k] = static_cast<V4<T>*>(F.arec[k]);
   a.cell_q = S.cell_q;
+  for (int k = 0; k < 3; ++k) a.xr32[k] = F.xr32[k];
   k_place<T, DIM><<<(int)((n_in + 255) / 256) + (n_in == 0), 256, 0, st>>>((int)n_in, (int)n_out, a);
   for (int k = 0; k < 3; ++k) {
     F.x[k].flip();

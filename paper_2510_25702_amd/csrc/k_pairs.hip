@@ -88,7 +88,7 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   if (BUILD && !MOMENT) {
     if (is_real(ti)) {
       const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
-      scan_build<T, DIM, L, 0>(pc, i, lane, xi, nb, [](int, const T*, T, T) {});
+      scan_build<T, DIM, L, 0, true>(pc, i, lane, xi, nb, [](int, const T*, T, T) {});
     }
     return m_pairs;
   }
@@ -193,8 +193,21 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
   return m_pairs;
 }
 
+// Wavefronts per SIMD that the FP32 3D list-only scan is compiled for (1:
+// the compiler's choice, 67 registers and seven wavefronts).  8 fits 64
+// registers with 12 bytes of scratch per lane: the mixer's correction 4315
+// -> 4240 us, left out to keep every kernel free of scratch memory.
+#ifndef SPHX_SCAN_WAVES
+#define SPHX_SCAN_WAVES 1
+#endif
+template <typename T, int DIM, int L, bool BUILD>
+constexpr int scan_waves() {
+  return (BUILD && DIM == 3 && sizeof(T) == 4) ? SPHX_SCAN_WAVES : 1;
+}
+
 template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true, bool REC = false>
-__global__ __launch_bounds__(256) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    (!MOMENT) ? scan_waves<T, DIM, L, BUILD>() : 1))) void k_correction(int n, PairCtx<T> pc, Consts<T> C, CorrArgs<T> a,
                                                     NbrOut<T> nb, const int32_t* __restrict__ ns) {
   if (ns) {   // sizes on the device: the build of this state was prelaunched
     if (ns[2]) return;
@@ -507,7 +520,7 @@ struct PressArgs {
   // (check |x - x_build - u_c t| <= s_i and t <= Δt_ad = lrad[0]), else the
   // cell-size radius (check |x - x_build| <= the skin)
   const double* lrad;
-  const T* lskin;
+  const float* lskin;
   const T* cell_u[3];
   double t_el;              // time since the build at the end of this sub-step
   const uint32_t* pid;
@@ -1046,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_cell_skin(int ncell, const int32_t* __r
                                                    const uint32_t* __restrict__ tag,
                                                    const double* __restrict__ lrad, double h,
                                                    const int32_t* __restrict__ ns, T* u0, T* u1,
-                                                   T* u2, T* skin) {
+                                                   T* u2, float* skin) {
   if (ns && ns[2]) return;
   const double dt = lrad[0];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1073,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_cell_skin(int ncell, const int32_t* __r
       const double d2 = DIM == 3 ? (double)v2[j] - (double)u[2] : 0.0;
       sj = kListSkinFactor * sqrt(d0 * d0 + d1 * d1 + d2 * d2) * dt + kListSkinFloor * h;
     }
-    skin[j] = (T)sj;
+    skin[j] = (float)sj;
   }
 }
 
@@ -1253,7 +1266,7 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
     k_cell_skin<T, DIM><<<(nc + 255) / 256, 256, 0, c->stream>>>(
         nc, c->S.cell_start, tp<T>(c->F.v[0].live()), tp<T>(c->F.v[1].live()),
         tp<T>(c->F.v[2].live()), c->F.tag.live(), c->S.lrad, c->P.h, ns, tp<T>(c->F.cell_u[0]),
-        tp<T>(c->F.cell_u[1]), tp<T>(c->F.cell_u[2]), tp<T>(c->F.lskin));
+        tp<T>(c->F.cell_u[1]), tp<T>(c->F.cell_u[2]), c->F.lskin);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1280,7 +1293,8 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
   nb.queue = nullptr;
   nb.tight = tight ? 1 : 0;
   nb.lrad = c->S.lrad;
-  nb.lskin = tp<T>(c->F.lskin);
+  nb.lskin = c->F.lskin;
+  for (int k = 0; k < 3; ++k) nb.xs[k] = c->F.xr32[k];
   for (int k = 0; k < 3; ++k) nb.cell_u[k] = tp<T>(c->F.cell_u[k]);
   nb.two_h = (T)(2.0 * c->P.h);
   nb.rl = (T)rl;
@@ -1402,7 +1416,7 @@ hipError_t pressure_impl(sph_ctx* c, double dt, bool rates_only, const sph_rates
   a.bidx = c->S.bidx;
   a.flags = c->S.flags;
   a.lrad = c->S.lrad;
-  a.lskin = tp<T>(F.lskin);
+  a.lskin = F.lskin;
   for (int k = 0; k < 3; ++k) a.cell_u[k] = tp<T>(F.cell_u[k]);
   a.t_el = (double)(c->substep + 1) * dt;
   a.dt = dt;

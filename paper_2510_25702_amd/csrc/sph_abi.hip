@@ -159,7 +159,7 @@ struct Plan {
       off_key, off_slot, off_perm, off_dec, off_count, off_cstart, off_bsums, off_cand,
       off_injk, off_inji, off_counters, off_flags, off_red, off_pairs, off_npid, off_bufs,
       off_bidx, off_nbr, off_ncnt, off_xrb[3], off_stale, off_prec[3], off_drec[2], off_arec[3], off_nstate,
-      off_shift[3], off_cellu[3], off_lskin, off_lrad, off_cellq;
+      off_shift[3], off_cellu[3], off_lskin, off_lrad, off_cellq, off_xr32[3];
   int n_cand;
 };
 
@@ -201,7 +201,9 @@ void make_plan(const sph_params* P, const sph_buffer_desc* B, int nbuf, Plan* pl
   pl->off_perm = L.take(C * 4);
   pl->off_dec = L.take(C * 4);
   for (int k = 0; k < 3; ++k) pl->off_cellu[k] = L.take((size_t)g.ncell * sT);
-  pl->off_lskin = L.take(C * sT);
+  pl->off_lskin = L.take(C * 4);
+  const bool x32 = P->precision == SPH_FP64 && P->dim == 3;   // the 3D FP64 list scan's
+  for (int k = 0; k < 3; ++k) pl->off_xr32[k] = L.take(x32 ? C * 4 : 0);
   pl->off_lrad = L.take(32);
   pl->off_count = L.take((size_t)g.ncell * 4);
   pl->off_cstart = L.take(((size_t)g.ncell + 1) * 4);
@@ -545,7 +547,10 @@ sph_status sph_create(const sph_params* params, const sph_buffer_desc* bufs, int
   for (int k = 0; k < 3; ++k) F.arec[k] = w + pl.off_arec[k];
   for (int k = 0; k < 3; ++k) F.shift[k] = params->tvf_alpha != 0.0 ? w + pl.off_shift[k] : nullptr;
   for (int k = 0; k < 3; ++k) F.cell_u[k] = w + pl.off_cellu[k];
-  F.lskin = w + pl.off_lskin;
+  F.lskin = (float*)(w + pl.off_lskin);
+  for (int k = 0; k < 3; ++k)
+    F.xr32[k] = (c->P.precision == SPH_FP64 && c->P.dim == 3) ? (float*)(w + pl.off_xr32[k])
+                                                                : nullptr;
   F.nbr_k = params->dim == 2 ? kNbrMax2 : kNbrMax3;
   if (const char* nl = std::getenv("SPHX_NBR_LIST")) c->use_nbr = std::atoi(nl) != 0;
   if (const char* tl = std::getenv("SPHX_LIST_TIGHT")) c->tight_list = std::atoi(tl) != 0;

@@ -55,7 +55,8 @@ struct Fields {
   // velocity of each cell's moving particles and each particle's allowed
   // deviation from drifting with it over the step
   void* cell_u[3];         // [ncell] (pair precision)
-  void* lskin;             // [cap] (pair precision)
+  float* lskin;            // [cap]
+  float* xr32[3];          // [cap] FP32 copies of xr for the FP64 list scan (FP64 only)
 };
 
 struct Scratch {

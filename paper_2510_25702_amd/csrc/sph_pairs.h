@@ -6,6 +6,8 @@
 // inverse of the correction moment.
 #pragma once
 
+#include <type_traits>
+
 #include "sph_ctx.h"
 
 namespace sphx {
@@ -630,8 +632,10 @@ struct NbrOut {
   // for a wall), at most the cell size rl; otherwise when |r_ij| < rl
   int tight;
   double* lrad;
-  const T* lskin;
+  const float* lskin;
   const T* cell_u[3];
+  // FP32 copies of the cell-relative positions (FP64 contexts; else NULL)
+  const float* xs[3];
   T two_h, rl;
   // starts of the x quarters 1-3 of every cell (NULL: whole rows), q_rl a
   // little above rl, q_w = 4 / cell size
@@ -700,9 +704,29 @@ constexpr int scan_unroll() {
 // the accepted candidates in candidate order with a wavefront ballot, so the
 // list order does not depend on L.  fn(j, r, r2, V_j) is called for the
 // pairs within 2h, in for_neighbors' order.
-template <typename T, int DIM, int L, int QD = pair_queue<T, DIM>(), typename Fn>
+template <typename T, int DIM, int L, int QD = pair_queue<T, DIM>(), bool LO = false,
+          typename Fn>
 __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane, const T xi[3],
                                            const NbrOut<T>& o, Fn&& fn) {
+  // The FP64 scan that writes the list alone (LO) tests in FP32, on the
+  // cell build's FP32 copies of the cell-relative positions: the list needs
+  // every pair within its radius, and the radius's margin (2e-5 relative,
+  // 2e-6 at the cell-size cap) is far above FP32's rounding of r.  Only the
+  // passes' own FP64 test decides a pair.
+  constexpr bool kS32 = LO && sizeof(T) == 8;
+  using S = typename std::conditional<kS32, float, T>::type;
+  const S* px[3];
+  S xs[3];
+  if constexpr (kS32) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) px[k] = o.xs[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) px[k] = pc.xr[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xs[k] = (kS32 && k < DIM) ? px[k][i] : (S)xi[k];
+  const S csz = (S)pc.csz, rl = (S)o.rl, rl2 = (S)o.rl2;
   const int wl = (int)(threadIdx.x & (kWave - 1));
   const int team0 = wl - lane;   // first lane of the team in the wavefront
   const uint64_t tmask = (L >= kWave ? ~0ull : ((1ull << L) - 1ull)) << team0;
@@ -714,12 +738,12 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   constexpr int zr = DIM == 3 ? 1 : 0;
   // relative-motion radius (NbrOut): the parts of i's bound, a wall's term
   const bool tight = o.tight && o.lrad[0] > 0.0;
-  T rad_i = o.rl, du_wall = T(0), uc_i[3] = {T(0), T(0), T(0)}, dt_l = T(0);
+  S rad_i = rl, du_wall = S(0), uc_i[3] = {S(0), S(0), S(0)}, dt_l = S(0);
   if (tight) {
-    dt_l = (T)o.lrad[0];
-    rad_i = o.two_h + o.lskin[i];
+    dt_l = (S)o.lrad[0];
+    rad_i = (S)o.two_h + (S)o.lskin[i];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) uc_i[k] = o.cell_u[k][c];
+    for (int k = 0; k < DIM; ++k) uc_i[k] = (S)o.cell_u[k][c];
     du_wall = pair_dist(DIM == 3 ? (uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) + uc_i[2] * uc_i[2]
                                  : uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) * dt_l;
   }
@@ -730,8 +754,8 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   // is one shorter contiguous range: 2.25 cells instead of 3
   int k_lo = 0, k_hi = 4;
   if (o.cell_q) {
-    const T a_hi = (o.q_rl + xi[0] - T(0.5) * pc.csz) * o.q_w;
-    const T a_lo = (xi[0] + T(1.5) * pc.csz - o.q_rl) * o.q_w;
+    const S a_hi = ((S)o.q_rl + xs[0] - S(0.5) * csz) * (S)o.q_w;
+    const S a_lo = (xs[0] + S(1.5) * csz - (S)o.q_rl) * (S)o.q_w;
     k_hi = (int)ceil(a_hi);
     k_lo = (int)floor(a_lo);
     k_hi = k_hi < 0 ? 0 : (k_hi > 4 ? 4 : k_hi);
@@ -783,52 +807,54 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
         lo = k_lo == 0 ? j0 : ql;
         hi = k_hi == 0 ? j2 : qh;
       }
-      const T oy = -T(dy) * pc.csz, oz = -T(dz) * pc.csz;
+      const S oy = -S(dy) * csz, oz = -S(dz) * csz;
       // |u_c(i) - u_c| Δt_ad for the row's three cells
-      T du[3] = {T(0), T(0), T(0)};
+      S du[3] = {S(0), S(0), S(0)};
       if (tight) {
         const int cb = ((cz + dz) * pc.ny + (cy + dy)) * pc.nx + cx - 1;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          T d[3] = {T(0), T(0), T(0)};
+          S d[3] = {S(0), S(0), S(0)};
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) d[k] = uc_i[k] - o.cell_u[k][cb + q];
+          for (int k = 0; k < DIM; ++k) d[k] = uc_i[k] - (S)o.cell_u[k][cb + q];
           du[q] = pair_dist(DIM == 3 ? (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
                                      : d[0] * d[0] + d[1] * d[1]) * dt_l;
         }
       }
       // the same trip count for every lane of the team
       for (int jb = lo; jb < hi; jb += SU * L) {
-        T q0[SU], q1[SU], q2[SU], qv[SU], qs[SU];
+        S q0[SU], q1[SU], q2[SU], qs[SU];
+        T qv[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
           const int j = jb + u * L + lane;
           // (an index below 2^26: 32-bit offsets from the arrays' bases)
           const uint32_t js = (uint32_t)(j < hi ? j : jb) & kNbrIdxMask;
-          q0[u] = pc.xr[0][js];
-          q1[u] = pc.xr[1][js];
-          q2[u] = DIM == 3 ? pc.xr[2][js] : T(0);
-          qv[u] = pc.vol[js];   // with the positions: one round trip per batch
-          qs[u] = tight ? o.lskin[js] : T(0);
+          q0[u] = px[0][js];
+          q1[u] = px[1][js];
+          q2[u] = DIM == 3 ? px[2][js] : S(0);
+          // with the positions: one round trip per batch
+          qv[u] = LO ? T(0) : pc.vol[js];
+          qs[u] = tight ? (S)o.lskin[js] : S(0);
         }
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
           const int j = jb + u * L + lane;
           const int dx = j < j1 ? -1 : (j < j2 ? 0 : 1);
-          const T ox = j < j1 ? pc.csz : (j < j2 ? T(0) : -pc.csz);
-          T r[3];
-          r[0] = (xi[0] - q0[u]) + ox;
-          r[1] = (xi[1] - q1[u]) + oy;
-          r[2] = DIM == 3 ? (xi[2] - q2[u]) + oz : T(0);
-          const T r2 = dist2<T, DIM>(r);
+          const S ox = j < j1 ? csz : (j < j2 ? S(0) : -csz);
+          S r[3];
+          r[0] = (xs[0] - q0[u]) + ox;
+          r[1] = (xs[1] - q1[u]) + oy;
+          r[2] = DIM == 3 ? (xs[2] - q2[u]) + oz : S(0);
+          const S r2 = dist2<S, DIM>(r);
           const bool in = j < hi && j != i;
-          T rad2 = o.rl2;
+          S rad2 = rl2;
           if (tight) {
             // a wall (s_j < 0) does not move; a little above for rounding
-            const T dux = dx < 0 ? du[0] : (dx == 0 ? du[1] : du[2]);
-            const T rad = rad_i + (qs[u] < T(0) ? du_wall : qs[u] + dux);
-            const T rc = rad * T(1.00002);
-            rad2 = rc < o.rl ? rc * rc : o.rl2;
+            const S dux = dx < 0 ? du[0] : (dx == 0 ? du[1] : du[2]);
+            const S rad = rad_i + (qs[u] < S(0) ? du_wall : qs[u] + dux);
+            const S rc = rad * S(1.00002);
+            rad2 = rc < rl ? rc * rc : rl2;
           }
           const bool acc = in && r2 < rad2;
           int off = 0, tot = acc ? 1 : 0;
@@ -845,7 +871,9 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
             else o.nbr[nbr_index<DIM>(cnt + off, i, o.stride)] = ent;
           }
           cnt += tot;
-          if constexpr (Q > 0) {
+          if constexpr (LO) {
+            // the list alone
+          } else if constexpr (Q > 0) {
             if (in && r2 < pc.rc2) {
               o.queue[qn * kWave + wl] = V4<T>{r[0], r[1], r[2], qv[u]};
               ++qn;
@@ -858,7 +886,7 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
       }
     }
   }
-  if constexpr (Q > 0) flush();
+  if constexpr (Q > 0 && !LO) flush();
   // more candidates than the list holds (a particle in a cluster denser
   // than the lattice): the passes scan the stencil for this particle
   if (lane == 0) o.ncnt[i] = cnt <= o.K ? cnt : kNbrNoList;
