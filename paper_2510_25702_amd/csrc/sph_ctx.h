@@ -128,7 +128,7 @@ struct sph_ctx {
   int team_override = 0;        // lanes per particle of the neighbour passes (0: auto)
   int corr_override = 0;        // lanes per particle of the correction pass (0: auto)
   bool use_nbr = true;          // neighbour passes read the per-step list
-  bool tight_list = true;       // sph_advance's builds take the relative-motion radius
+  int tight_list = -1;          // relative-motion list radius: 1 on, 0 off, -1 by size
   bool last_outgrown = false;   // the last updated step's list was outgrown
   bool nbr_valid = false;       // the list matches the current cell build
   int substep = 0;              // acoustic sub-step being launched
