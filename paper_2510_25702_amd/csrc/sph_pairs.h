@@ -296,6 +296,12 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
 #ifndef SPHX_LAZY_MIN_NR64
 #define SPHX_LAZY_MIN_NR64 2
 #endif
+#ifndef SPHX_LAZY_MAX_NR
+#define SPHX_LAZY_MAX_NR 2
+#endif
+#ifndef SPHX_LAZY_MAX_NR64
+#define SPHX_LAZY_MAX_NR64 1
+#endif
 // Every vector of a batch's records is needed by then: left alone, the
 // compiler sinks the parts a candidate's distance test does not read into
 // the test's branch, where they cost a second memory round trip.  An empty
@@ -304,9 +310,12 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
 // pressure -4 to -6 % from 160k to 2.56M particles.  In 3D and with FP64
 // records the registers it holds cost more than the round trip (3D
 // continuity +24 % on the mixer, the FP64 U-channel step +4 %): left out.
+#ifndef SPHX_PIN_3D
+#define SPHX_PIN_3D 0
+#endif
 template <typename T, int DIM, int U, int NR>
 __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
-  if (!SPHX_PIN_RECORDS || DIM == 3 || sizeof(T) != 4) return;
+  if (!SPHX_PIN_RECORDS || (DIM == 3 && !SPHX_PIN_3D) || sizeof(T) != 4) return;
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -445,10 +454,16 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
   // (continuity, laminar advection) lost with one-entry list rows and the
   // divided stencil code (continuity 1640 -> 1753 us) but gain with the
   // chunked list, its bit-field offsets and the batches of eight (advection
-  // 1597 -> 1447 us, continuity 1551 -> 1419 us): every 3D record is
-  // gathered in two rounds.
+  // 1597 -> 1447 us, continuity 1551 -> 1419 us).  With the relative-
+  // motion radius about 70 % of the ~100 entries lie within 2h, and the
+  // FP32 three-vector pressure records load whole again (each candidate's
+  // other vectors issued after its own test; pressure 1382 -> 1195 us),
+  // while the FP32 two-vector passes keep the two rounds (continuity 768
+  // against 785 us); FP64 records all load whole (the FP64 mixer step
+  // 21.02 -> 20.44 ms).
   constexpr bool kLazy =
-      DIM == 3 && NR >= (sizeof(T) == 8 ? SPHX_LAZY_MIN_NR64 : SPHX_LAZY_MIN_NR);
+      DIM == 3 && NR >= (sizeof(T) == 8 ? SPHX_LAZY_MIN_NR64 : SPHX_LAZY_MIN_NR) &&
+      NR <= (sizeof(T) == 8 ? SPHX_LAZY_MAX_NR64 : SPHX_LAZY_MAX_NR);
   auto load_batch = [&](V4<T> (&q)[kUnroll][NR], const int (&jv)[kUnroll]) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
