@@ -317,7 +317,11 @@ sph_status sph_buffer_update_ex(sph_ctx* ctx, const uint32_t* forced_by_pid,
  * correction of the updated state are enqueued before the update's one
  * read-back (their sizes taken on the device), so on success the state is
  * the updated one already built and corrected: particles tagged SPH_DEAD
- * are dropped and the next sph_advance (or sph_step) starts from it.  The
+ * are dropped and the next sph_advance (or sph_step) starts from it.  (In
+ * 3D laminar contexts with the neighbour list, that correction writes the
+ * list only and the next step's advection pass forms B from the same walk
+ * of the list, bit for bit the B sph_correction forms; sph_eval_rates forms
+ * it first when asked for a state left so.)  The
  * first failure returns its status.  On SPH_E_CAPACITY the state is the
  * one a failed sph_buffer_update leaves; on a flag error raised by the step
  * (SPH_E_NUMERIC) it is the updated state and a cell build is required.

@@ -74,65 +74,31 @@ constexpr bool split_correction() {
   return DIM == 3;
 }
 
-template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true, bool REC = false>
-__device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
-                                               const Consts<T>& C, const CorrArgs<T>& a,
-                                               const NbrOut<T>& nb) {
-  if (i >= n) return 0;
-  int m_pairs = 0;
-  constexpr int NR = 2;
-  ListHead<rec_unroll<T, DIM, L, NR>()> head{};
-  if constexpr (REC) head = list_head<T, DIM, L, NR>(pc, i, lane);
-  const uint32_t ti = pc.tag[i];
-  if (BUILD) build_begin<T, DIM>(pc, i, lane, nb);
-  if (BUILD && !MOMENT) {
-    if (is_real(ti)) {
-      const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
-      scan_build<T, DIM, L, 0, true>(pc, i, lane, xi, nb, [](int, const T*, T, T) {});
-    }
-    return m_pairs;
+// One pair's term of the moment A_i = -sum_j V_j f_ij r_ij (x) r_ij
+// (symmetric, packed xx xy xz yy yz zz), Eq. (equ-B-matrix).
+template <typename T, int DIM>
+__device__ __forceinline__ void moment_pair(T (&A)[6], const T r[3], T r2, T Vj,
+                                            const Consts<T>& C) {
+  const T f = dw_over_r<T>(pair_dist(r2), C.inv_h_t, C.kf_t);
+  const T Vf = Vj * f;
+  A[0] -= Vf * r[0] * r[0];
+  A[1] -= Vf * r[0] * r[1];
+  A[3] -= Vf * r[1] * r[1];
+  if (DIM == 3) {
+    A[2] -= Vf * r[0] * r[2];
+    A[4] -= Vf * r[1] * r[2];
+    A[5] -= Vf * r[2] * r[2];
   }
-  if (!is_real(ti)) {
-    if (lane == 0) {
-      a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
-      if (DIM == 3) { a.B[2][i] = T(0); a.B[4][i] = T(0); a.B[5][i] = T(1); }
-    }
-    return m_pairs;
-  }
-  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
-  T A[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  auto acc = [&](const T r[3], T r2, T Vj) {
-    const T f = dw_over_r<T>(pair_dist(r2), C.inv_h_t, C.kf_t);
-    const T Vf = Vj * f;
-    A[0] -= Vf * r[0] * r[0];
-    A[1] -= Vf * r[0] * r[1];
-    A[3] -= Vf * r[1] * r[1];
-    if (DIM == 3) {
-      A[2] -= Vf * r[0] * r[2];
-      A[4] -= Vf * r[1] * r[2];
-      A[5] -= Vf * r[2] * r[2];
-    }
-  };
-  auto pair = [&](int j, const T r[3], T r2) {
-    acc(r, r2, pc.vol[j]);
-    ++m_pairs;
-  };
-  auto pair_v = [&](int, const T r[3], T r2, T vj) {   // V_j loaded with the positions
-    acc(r, r2, vj);
-    ++m_pairs;
-  };
-  if (BUILD) {
-    scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair_v);
-  } else if (REC) {
-    // V_j from the record, its sign (a wall) dropped
-    for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, head,
-                                     [&](int, const T r[3], T r2, const auto& q) {
-                                       acc(r, r2, fabs(q[1].c));
-                                       ++m_pairs;
-                                     });
-  } else {
-    for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
-  }
+}
+
+// The end of particle i's moment after its pair walk (every lane of the
+// team): the terms of the mirror images at the open faces (obc_mode >= 3,
+// Sec. 3.3), the team sum, B_i = A_i^-1 in FP64 with the singularity guard.
+// Lane 0 writes B_i and returns it in Bt.
+template <typename T, int DIM, int L>
+__device__ __forceinline__ void moment_finish(int i, int lane, const PairCtx<T>& pc,
+                                              const Consts<T>& C, const CorrArgs<T>& a,
+                                              T (&A)[6], T (&Bt)[6]) {
   if (a.mirror) {
     const double xi0 = a.x[0][i], xi1 = a.x[1][i], xi2 = a.x[2][i];
     const double twoh = 2.0 * C.h;
@@ -170,26 +136,79 @@ __device__ __forceinline__ int correction_body(int i, int lane, int n, const Pai
                             (T)(DIM == 3 ? xi2 - (xj2 - tj * b.frame[2]) : 0.0)};
             const T r2 = DIM == 3 ? (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]
                                   : r[0] * r[0] + r[1] * r[1];
-            if (r2 < pc.rc2) acc(r, r2, pc.vol[j]);
+            if (r2 < pc.rc2) moment_pair<T, DIM>(A, r, r2, pc.vol[j], C);
           }
         }
     }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) A[k] = team_sum<L>(A[k]);
-  if (lane != 0) return m_pairs;
+  if (lane != 0) return;
   double Ad[6] = {(double)A[0], (double)A[1], (double)A[2],
                   (double)A[3], (double)A[4], (double)A[5]};
   double Bd[6];
   invert_sym<DIM>(Ad, Bd);
-  a.B[0][i] = (T)Bd[0];
-  a.B[1][i] = (T)Bd[1];
-  a.B[3][i] = (T)Bd[3];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Bt[k] = (DIM == 2 && (k == 2 || k == 4 || k == 5)) ? T(0) : (T)Bd[k];
+  a.B[0][i] = Bt[0];
+  a.B[1][i] = Bt[1];
+  a.B[3][i] = Bt[3];
   if (DIM == 3) {
-    a.B[2][i] = (T)Bd[2];
-    a.B[4][i] = (T)Bd[4];
-    a.B[5][i] = (T)Bd[5];
+    a.B[2][i] = Bt[2];
+    a.B[4][i] = Bt[4];
+    a.B[5][i] = Bt[5];
   }
+}
+
+template <typename T, int DIM, int L, bool BUILD, bool MOMENT = true, bool REC = false>
+__device__ __forceinline__ int correction_body(int i, int lane, int n, const PairCtx<T>& pc,
+                                               const Consts<T>& C, const CorrArgs<T>& a,
+                                               const NbrOut<T>& nb) {
+  if (i >= n) return 0;
+  int m_pairs = 0;
+  constexpr int NR = 2;
+  ListHead<rec_unroll<T, DIM, L, NR>()> head{};
+  if constexpr (REC) head = list_head<T, DIM, L, NR>(pc, i, lane);
+  const uint32_t ti = pc.tag[i];
+  if (BUILD) build_begin<T, DIM>(pc, i, lane, nb);
+  if (BUILD && !MOMENT) {
+    if (is_real(ti)) {
+      const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+      scan_build<T, DIM, L, 0, true>(pc, i, lane, xi, nb, [](int, const T*, T, T) {});
+    }
+    return m_pairs;
+  }
+  if (!is_real(ti)) {
+    if (lane == 0) {
+      a.B[0][i] = T(1); a.B[1][i] = T(0); a.B[3][i] = T(1);
+      if (DIM == 3) { a.B[2][i] = T(0); a.B[4][i] = T(0); a.B[5][i] = T(1); }
+    }
+    return m_pairs;
+  }
+  const T xi[3] = {pc.xr[0][i], pc.xr[1][i], DIM == 3 ? pc.xr[2][i] : T(0)};
+  T A[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  auto pair = [&](int j, const T r[3], T r2) {
+    moment_pair<T, DIM>(A, r, r2, pc.vol[j], C);
+    ++m_pairs;
+  };
+  auto pair_v = [&](int, const T r[3], T r2, T vj) {   // V_j loaded with the positions
+    moment_pair<T, DIM>(A, r, r2, vj, C);
+    ++m_pairs;
+  };
+  if (BUILD) {
+    scan_build<T, DIM, L>(pc, i, lane, xi, nb, pair_v);
+  } else if (REC) {
+    // V_j from the record, its sign (a wall) dropped
+    for_neighbors_rec<T, DIM, L, NR>(pc, i, lane, xi, a.arec, head,
+                                     [&](int, const T r[3], T r2, const auto& q) {
+                                       moment_pair<T, DIM>(A, r, r2, fabs(q[1].c), C);
+                                       ++m_pairs;
+                                     });
+  } else {
+    for_neighbors<T, DIM, L>(pc, i, lane, xi, pair);
+  }
+  T Bt[6];
+  moment_finish<T, DIM, L>(i, lane, pc, C, a, A, Bt);
   return m_pairs;
 }
 
@@ -263,9 +282,16 @@ struct AdvArgs {
   const double* x[3];     // FP64 positions (buffer particles' local frame)
   T* shift[3];            // the shift of fluid particles (written)
   double* o_shift;        // rates output [3][n_out]
+  CorrArgs<T> cor;        // the correction's operands (MOM: B formed in this pass)
 };
 
-template <typename T, int DIM, int TURB, int L>
+// MOM (3D laminar list passes): the pass also forms the correction matrix
+// B_i over the same walk of the list -- the moment terms of each pair, then
+// the mirror images, the team sum and the guarded FP64 inverse, the
+// correction kernel's own code in its order, so B is the same bit for bit
+// -- instead of a separate walk of the list by the correction; B is first
+// needed by this pass's pressure record.
+template <typename T, int DIM, int TURB, int L, bool MOM = false>
 __device__ __forceinline__ int advection_body(int i, int lane, int n, const PairCtx<T>& pc,
                                               const Consts<T>& C, const AdvArgs<T>& a) {
   if (i >= n) return 0;
@@ -289,6 +315,10 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
       }
     }
     if (!a.rates_only && lane == 0) {
+      if (MOM) {   // as the correction: the identity for walls and dead slots
+        a.cor.B[0][i] = T(1); a.cor.B[1][i] = T(0); a.cor.B[3][i] = T(1);
+        a.cor.B[2][i] = T(0); a.cor.B[4][i] = T(0); a.cor.B[5][i] = T(1);
+      }
       for (int k = 0; k < 3; ++k) a.anu[k][i] = T(0);
       a.p_out[i] = T(0);
       a.vol_out[i] = (T)C.Vw;
@@ -307,6 +337,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   T Bi[6];
   T ki = T(0), ei = T(0), Dk_i = T(0), De_i = T(0), dfk = T(0), dfe = T(0);
   T sh[3] = {T(0), T(0), T(0)};   // sum_j V_j grad_i W_ij (transport velocity)
+  T Am[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // the moment (MOM)
   if (TURB) {
     load_B<T, DIM>(a.B, i, Bi);   // the velocity gradient's correction
     ki = a.k[i];
@@ -320,7 +351,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   T drho_i = T(0);
   int qb = -1;
   auto load_update = [&]() {
-    if (!TURB && !a.rates_only) load_B<T, DIM>(a.B, i, Bi);
+    if (!TURB && !a.rates_only && !MOM) load_B<T, DIM>(a.B, i, Bi);
     if (!a.rates_only) drho_i = a.drho[i];
     if (TURB && tag_kind(ti) == kBuffer) qb = a.bidx[tag_bid(ti)];
   };
@@ -343,6 +374,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
     }
     const bool wall = volw < T(0);
     const T Vj = wall ? -volw : volw;
+    if constexpr (MOM) moment_pair<T, DIM>(Am, r, r2, Vj, C);
     // no-slip dummy wall: antisymmetric velocity, same viscosity as i
     T vij[3];
     if (wall) {
@@ -393,6 +425,7 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
       }
     }
   });
+  if constexpr (MOM) moment_finish<T, DIM, L>(i, lane, pc, C, a.cor, Am, Bi);
 #pragma unroll
   for (int k = 0; k < 3; ++k) av[k] = team_sum<L>(av[k]);
   if (a.tvf) {
@@ -488,10 +521,10 @@ __device__ __forceinline__ int advection_body(int i, int lane, int n, const Pair
   return m_pairs;
 }
 
-template <typename T, int DIM, int TURB, int L>
+template <typename T, int DIM, int TURB, int L, bool MOM = false>
 __global__ __launch_bounds__(256) void k_advection(int n, PairCtx<T> pc, Consts<T> C, AdvArgs<T> a) {
   const int g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int m = advection_body<T, DIM, TURB, L>(g / L, g % L, n, pc, C, a);
+  const int m = advection_body<T, DIM, TURB, L, MOM>(g / L, g % L, n, pc, C, a);
   count_pairs(pc.pairs, m);
 }
 
@@ -1291,8 +1324,34 @@ inline int corr_lanes(const sph_ctx* c, int64_t n) {
     default: { constexpr int TL = 8; __VA_ARGS__; } break;         \
   }
 
+// The 3D moment over the list just written: B of every particle (the
+// correction's second kernel).  ns / n: the sizes as for the list.
 template <typename T, int DIM>
-hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight) {
+hipError_t moment_impl(sph_ctx* c, const int32_t* ns, int64_t n) {
+  if constexpr (DIM == 3) {
+    Consts<T> C = make_consts<T>(c);
+    PairCtx<T> pl = make_pc<T>(c, c->F.xr, c->F.x[0].cur);
+    pl.nbr = c->F.nbr;
+    pl.ncnt = c->F.ncnt;
+    pl.stale = nullptr;
+    CorrArgs<T> am;
+    for (int k = 0; k < 3; ++k) am.x[k] = c->F.x[k].live();
+    am.bufs = c->S.bufs;
+    for (int k = 0; k < 6; ++k) am.B[k] = tp<T>(c->F.B[k]);
+    am.flags = c->S.flags;
+    am.mirror = c->P.obc_mode >= 3 ? 1 : 0;
+    for (int k = 0; k < 2; ++k) am.arec[k] = tp<V4<T>>(c->F.arec[k]);
+    NbrOut<T> nb{};
+    const int Lm = team_lanes(c);
+    SPHX_TEAM_SWITCH(Lm, launch_pass(c, &k_correction<T, DIM, TL, false, true, true>, nblk(n * TL), (int)n, pl, C, am, nb, ns));
+    c->B_pending = false;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight,
+                           bool moment) {
   Consts<T> C = make_consts<T>(c);
   c->nbr_valid = false;
   tight = tight && c->use_nbr;
@@ -1347,14 +1406,14 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true, false>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    PairCtx<T> pl = pc;
-    pl.nbr = c->F.nbr;
-    pl.ncnt = c->F.ncnt;
-    pl.stale = nullptr;
-    CorrArgs<T> am = a;
-    for (int k = 0; k < 2; ++k) am.arec[k] = tp<V4<T>>(c->F.arec[k]);
-    const int Lm = team_lanes(c);
-    SPHX_TEAM_SWITCH(Lm, launch_pass(c, &k_correction<T, DIM, TL, false, true, true>, nblk(n * TL), (int)n, pl, C, am, nb, ns));
+    // B now, or in the step's advection pass (laminar: it walks the same
+    // list); until then B of this state is pending
+    if (moment || c->P.turbulence) {
+      e = moment_impl<T, DIM>(c, ns, n);
+      if (e != hipSuccess) return e;
+    } else {
+      c->B_pending = true;
+    }
     if (pb) (void)hipEventRecord(pb, c->stream);
   } else if (c->use_nbr) {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_correction<T, DIM, TL, true>, nblk(n * TL), (int)n, pc, C, a, nb, ns));
@@ -1364,6 +1423,13 @@ hipError_t correction_impl(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool t
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && c->use_nbr) c->nbr_valid = true;
   return e;
+}
+
+// The 3D laminar list passes form B in the advection pass (advection_body,
+// MOM), from the same list walk; the correction then only writes the list
+// when the step follows at once (sph_advance).
+bool advection_forms_B(const sph_ctx* c, bool rates_only) {
+  return c->P.dim == 3 && !c->P.turbulence && !rates_only && c->use_nbr && c->nbr_valid;
 }
 
 template <typename T, int DIM>
@@ -1407,13 +1473,23 @@ hipError_t advection_impl(sph_ctx* c, double dt_adv, double dt_sub, bool rates_o
   for (int k = 0; k < 3; ++k) a.x[k] = F.x[k].live();
   for (int k = 0; k < 3; ++k) a.shift[k] = tp<T>(F.shift[k]);
   a.o_shift = out ? out->shift : nullptr;
+  for (int k = 0; k < 3; ++k) a.cor.x[k] = F.x[k].live();
+  a.cor.bufs = c->S.bufs;
+  for (int k = 0; k < 6; ++k) a.cor.B[k] = tp<T>(F.B[k]);
+  a.cor.flags = c->S.flags;
+  a.cor.mirror = c->P.obc_mode >= 3 ? 1 : 0;
+  a.cor.arec[0] = a.cor.arec[1] = nullptr;
   const int64_t n = c->n_total;
   const int L = team_lanes(c);
   if (c->P.turbulence) {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_advection<T, DIM, 1, TL>, nblk(n * TL), (int)n, pc, C, a));
+  } else if (advection_forms_B(c, rates_only)) {
+    if constexpr (DIM == 3)
+      SPHX_TEAM_SWITCH(L, launch_pass(c, &k_advection<T, DIM, 0, TL, true>, nblk(n * TL), (int)n, pc, C, a));
   } else {
     SPHX_TEAM_SWITCH(L, launch_pass(c, &k_advection<T, DIM, 0, TL>, nblk(n * TL), (int)n, pc, C, a));
   }
+  if (advection_forms_B(c, rates_only)) c->B_pending = false;
   return hipGetLastError();
 }
 
@@ -1626,9 +1702,13 @@ hipError_t export_B_impl(sph_ctx* c, double* B) {
        ? (c->P.dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)) \
        : (c->P.dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)))
 
-hipError_t launch_correction(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight) {
-  return SPHX_DISPATCH(correction_impl, c, ns, n_grid, tight);
+hipError_t launch_correction(sph_ctx* c, const int32_t* ns, int64_t n_grid, bool tight,
+                             bool moment) {
+  c->B_pending = false;
+  return SPHX_DISPATCH(correction_impl, c, ns, n_grid, tight, moment);
 }
+
+hipError_t launch_moment(sph_ctx* c) { return SPHX_DISPATCH(moment_impl, c, nullptr, c->n_total); }
 
 hipError_t launch_advection(sph_ctx* c, double dt_adv, double dt_sub, bool rates_only,
                             const sph_rates* out) {

@@ -403,7 +403,8 @@ sph_status buffer_update(sph_ctx* c, const uint32_t* forced_by_pid, uint32_t* lo
     prof_end(c);
     if (e == hipSuccess) {
       profile_launch(c, SPH_K_CORRECTION);
-      e = launch_correction(c, c->S.nstate, n_max, tight);
+      // the list only: the step that follows forms B in its advection pass
+      e = launch_correction(c, c->S.nstate, n_max, tight, false);
       prof_end(c);
     }
     if (e != hipSuccess) {
@@ -963,6 +964,7 @@ sph_status sph_eval_rates(sph_ctx* c, const sph_rates* out) {
   if (!out) return fail(c, SPH_E_ARG, "out is NULL");
   if (!c->cells_valid || c->moved || !c->B_valid)
     return fail(c, SPH_E_STATE, "sph_eval_rates needs sph_build_cells and sph_correction");
+  if (c->B_pending) HIPCHK(c, launch_moment(c), "moment");   // a state left by sph_advance
   HIPCHK(c, launch_prepare_pv(c, out), "prepare_pv");
   if (out->anu || out->gradv || out->dk || out->deps || out->shift)
     HIPCHK(c, launch_advection(c, 0.0, 0.0, true, out), "advection rates");

@@ -129,6 +129,7 @@ struct sph_ctx {
   int corr_override = 0;        // lanes per particle of the correction pass (0: auto)
   bool use_nbr = true;          // neighbour passes read the per-step list
   int tight_list = -1;          // relative-motion list radius: 1 on, 0 off, -1 by size
+  bool B_pending = false;       // B of the current state is formed by the next advection pass
   bool last_outgrown = false;   // the last updated step's list was outgrown
   bool nbr_valid = false;       // the list matches the current cell build
   int substep = 0;              // acoustic sub-step being launched
@@ -158,8 +159,11 @@ hipError_t launch_build_cells(sph_ctx* c, int64_t n_in, int64_t n_out,
                               const int32_t* ns = nullptr, bool keys_done = false);
 // tight: the list takes the relative-motion radius (the coming step's Δt_ad
 // on the device, from launch_list_dt); otherwise the cell size
+// moment false (3D laminar list passes): only the list; the step's advection
+// pass forms B (B_pending until then, launch_moment forms it on demand)
 hipError_t launch_correction(sph_ctx* c, const int32_t* ns = nullptr, int64_t n_grid = 0,
-                             bool tight = false);
+                             bool tight = false, bool moment = true);
+hipError_t launch_moment(sph_ctx* c);
 // the coming step's Δt_ad, as the host forms it, into S.lrad[0]: from the
 // post-update reduction's maxima (a build launched before the host has
 // them), or with fresh a reduction of the current state first
