@@ -647,6 +647,27 @@ def test_advance_equals_the_separate_calls(sph, ora, name):
         assert events > 0
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rates_after_advance_form_the_pending_correction(sph, ora, prec):
+    # a 3D laminar sph_advance leaves its next state with the list only (the
+    # next advection pass forms B); sph_eval_rates forms B first, and it
+    # equals, bit for bit, the B of sph_correction on the same state
+    c = relabelled(ora, cases.make_mixer(dp=0.04))
+    a, b = gpu_sim(sph, c, prec), gpu_sim(sph, c, prec)
+    for _ in range(3):
+        a.advance()
+        b.build_cells()
+        b.correction()
+        b.step()
+        b.buffer_update()
+    b.build_cells()
+    b.correction()
+    ra, rb = a.rates(), b.rates()
+    for f in ("B", "ap", "drho", "anu"):
+        assert np.array_equal(ra[f], rb[f]), f
+    assert np.isfinite(ra["B"]).all()
+
+
 @pytest.mark.parametrize("name", ["uchannel", "jet_full"])
 @pytest.mark.parametrize("pname,prec,tol", [("fp64", 0, 1e-10), ("fp32", 1, 2e-5)])
 def test_full_size_advance_matches_oracle(sph, ora, name, pname, prec, tol):
