@@ -1112,6 +1112,11 @@ __global__ __launch_bounds__(256) void k_adj_moment(AdjDev A, CorrAdjArgs c) {
       double yi[3];
       to_local(b, xi[0], xi[1], xi[2], yi);
       if (!(yi[0] >= 0.0 && yi[0] < c.twoh)) continue;
+      // no image within 2h beyond the buffer's transverse half-widths + 2h
+      // (its particles keep their transverse coordinates in the mirror)
+      const double reach = c.twoh * (1.0 + 1e-5);
+      if (!(fabs(yi[1]) < b.hw[0] + reach) || (DIM == 3 && !(fabs(yi[2]) < b.hw[1] + reach)))
+        continue;
       mirror_partners<DIM, L>(A, c, b, xi, lane, true, [&](int j) {
         double yj[3];
         const double xj0 = c.x[0][j], xj1 = c.x[1][j], xj2 = c.x[2][j];

@@ -107,6 +107,15 @@ __device__ __forceinline__ void moment_finish(int i, int lane, const PairCtx<T>&
       double yi[3];
       to_local(b, xi0, xi1, xi2, yi);
       if (!(yi[0] >= 0.0 && yi[0] < twoh)) continue;
+      // the buffer's particles lie within its transverse half-widths, and
+      // the mirror keeps their transverse coordinates: beyond hw + 2h (a
+      // little more, for the pair test's rounding) no image is within 2h.
+      // The face plane is unbounded, so without this test every particle
+      // within 2h of it searched the stencil around its image (on the 3D
+      // mixer, with its four tangential inlets: 0.71 of 1.59 ms of the pass)
+      const double reach = twoh * (1.0 + 1e-5);
+      if (!(fabs(yi[1]) < b.hw[0] + reach) || (DIM == 3 && !(fabs(yi[2]) < b.hw[1] + reach)))
+        continue;
       const double tt = 2.0 * yi[0];
       const double m[3] = {xi0 - tt * b.frame[0], xi1 - tt * b.frame[1], xi2 - tt * b.frame[2]};
       int cm[3] = {0, 0, 0};
