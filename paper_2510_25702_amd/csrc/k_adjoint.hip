@@ -1220,8 +1220,11 @@ __global__ __launch_bounds__(256) void k_adj_correction(AdjDev A, CorrAdjArgs c)
       const BufDev& b = c.bufs[q];
       double yk[3];
       to_local(b, xk[0], xk[1], xk[2], yk);
-      // i-side: images of partners j in A_i
-      if (yk[0] >= 0.0 && yk[0] < c.twoh) {
+      // i-side: images of partners j in A_i (none beyond the buffer's
+      // transverse half-widths + 2h)
+      const double reach = c.twoh * (1.0 + 1e-5);
+      if (yk[0] >= 0.0 && yk[0] < c.twoh && fabs(yk[1]) < b.hw[0] + reach &&
+          (DIM == 2 || fabs(yk[2]) < b.hw[1] + reach)) {
         mirror_partners<DIM, L>(A, c, b, xk, lane, true, [&](int j) {
           double yj[3];
           const double xj0 = c.x[0][j], xj1 = c.x[1][j], xj2 = c.x[2][j];
