@@ -297,7 +297,7 @@ __device__ __forceinline__ void write_drec(V4<T>* const* dr, int i, const T x[3]
 #define SPHX_LAZY_MIN_NR64 2
 #endif
 #ifndef SPHX_LAZY_MAX_NR
-#define SPHX_LAZY_MAX_NR 2
+#define SPHX_LAZY_MAX_NR 1
 #endif
 #ifndef SPHX_LAZY_MAX_NR64
 #define SPHX_LAZY_MAX_NR64 1
@@ -336,8 +336,11 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 // pressure 2357 -> 2339), and 12 over two-vector records (continuity 1423
 // -> 1342 us at three wavefronts per SIMD against four; 16: 1588 us at
 // two); fewer candidates per batch for more resident wavefronts lost (6 / 4:
-// pressure 2321 / 2386 against 2179 us).  FP64 3D ones keep 6 (pressure
-// 3942 against 5374 us at 8).
+// pressure 2321 / 2386 against 2179 us).  With the relative-motion radius
+// and whole records: pressure 8 (6: 1310, 10: 1383 against 1194 us), the
+// two-vector records 10 (8: continuity 730, advection 905 us; 10: 708, 968;
+// 12: 761, 1081).  FP64 3D ones keep 6 (pressure 3942 against 5374 us at
+// 8).
 #ifndef SPHX_REC_UNROLL_WIDE
 #define SPHX_REC_UNROLL_WIDE 2
 #endif
@@ -348,7 +351,7 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 #define SPHX_REC_UNROLL_NARROW3 8
 #endif
 #ifndef SPHX_REC_UNROLL_NARROW3_NR2
-#define SPHX_REC_UNROLL_NARROW3_NR2 12
+#define SPHX_REC_UNROLL_NARROW3_NR2 10
 #endif
 #ifndef SPHX_REC_UNROLL_ONE
 #define SPHX_REC_UNROLL_ONE 6
@@ -456,11 +459,11 @@ __device__ __forceinline__ void for_neighbors_rec(const PairCtx<T>& pc, int i, i
   // chunked list, its bit-field offsets and the batches of eight (advection
   // 1597 -> 1447 us, continuity 1551 -> 1419 us).  With the relative-
   // motion radius about 70 % of the ~100 entries lie within 2h, and the
-  // FP32 three-vector pressure records load whole again (each candidate's
-  // other vectors issued after its own test; pressure 1382 -> 1195 us),
-  // while the FP32 two-vector passes keep the two rounds (continuity 768
-  // against 785 us); FP64 records all load whole (the FP64 mixer step
-  // 21.02 -> 20.44 ms).
+  // records load whole again (each candidate's other vectors issued after
+  // its own test): FP32 pressure 1382 -> 1195 us, FP64 mixer step 21.02 ->
+  // 20.44 ms, and, once the advection pass also formed B, the FP32
+  // two-vector passes in batches of 10 (continuity 761 -> 708 us, advection
+  // 1081 -> 968 us).  The two rounds remain as an option (SPHX_LAZY_*).
   constexpr bool kLazy =
       DIM == 3 && NR >= (sizeof(T) == 8 ? SPHX_LAZY_MIN_NR64 : SPHX_LAZY_MIN_NR) &&
       NR <= (sizeof(T) == 8 ? SPHX_LAZY_MAX_NR64 : SPHX_LAZY_MAX_NR);
