@@ -356,8 +356,21 @@ __device__ __forceinline__ void pin_records(V4<T> (&q)[U][NR]) {
 #ifndef SPHX_REC_UNROLL_ONE
 #define SPHX_REC_UNROLL_ONE 6
 #endif
+// Four-lane FP64 3D teams take deeper batches: 3 for the three-vector
+// pressure records, 4 for two-vector ones (the FP64 mixer: pressure 2244 ->
+// 2136 us at 3, 2489 at 4; continuity 1445 -> 1356 / 1331 us; advection with
+// B 1667 -> 1618 / 1571 us; the 2D four-lane passes keep 2: the U-channel
+// step 0.279 against 0.288 ms at 3).
+#ifndef SPHX_REC_UNROLL_WIDE3_64
+#define SPHX_REC_UNROLL_WIDE3_64 3
+#endif
+#ifndef SPHX_REC_UNROLL_WIDE3_64_NR2
+#define SPHX_REC_UNROLL_WIDE3_64_NR2 4
+#endif
 template <typename T, int DIM, int L, int NR>
 constexpr int rec_unroll() {
+  if (L >= 4 && DIM == 3 && sizeof(T) == 8)
+    return NR <= 2 ? SPHX_REC_UNROLL_WIDE3_64_NR2 : SPHX_REC_UNROLL_WIDE3_64;
   if (L >= 4) return SPHX_REC_UNROLL_WIDE;
   if (L == 1) return SPHX_REC_UNROLL_ONE;
   if (DIM == 3 && sizeof(T) == 4)
