@@ -268,7 +268,7 @@ sph_status sph_build_cells(sph_ctx* ctx);
  * treatment of Sec. 3.3 at every buffer's open face when obc_mode >= 3
  * (pair sums in the configured precision, inversion in FP64).  Also builds
  * the step's neighbour list, which the later passes of the step read: every
- * pair within the cell size or, from 100k particles, within a radius that
+ * pair within the cell size or, from 10k particles, within a radius that
  * bounds the pair's relative motion over the coming step (the same list
  * sph_advance builds for the state).  Requires sph_build_cells since the last
  * position change (SPH_E_STATE).  Asynchronous. */

@@ -331,11 +331,12 @@ void prof_end(sph_ctx* c) {
 namespace {
 
 // Below this many particles the relative-motion radius's two extra launches
-// per step cost more than its shorter list saves: measured per step (FP32-
-// mixed) with and without it, the 5.2k-particle channel 0.155 against 0.148
-// ms, the 57.6k U-channel 0.245 against 0.243, the 138k adjoint channel
-// 0.278 against 0.293, the 160k jet 0.339 against 0.359.
-constexpr int64_t kTightMinN = 100000;
+// per step cost about what its shorter list saves: measured per step (FP32-
+// mixed / FP64) with and without it, the 5.2k-particle channel 0.147 / 0.145
+// against 0.148 / 0.143 ms, the 57.6k U-channel 0.230 / 0.281 against 0.240
+// / 0.293, the 138k adjoint channel 0.278 against 0.293, the 160k jet 0.339
+// against 0.359.
+constexpr int64_t kTightMinN = 10000;
 
 // Whether the list built for the current state takes the relative-motion
 // radius (sph_advance and sph_correction decide alike).
