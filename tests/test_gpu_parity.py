@@ -647,6 +647,32 @@ def test_advance_equals_the_separate_calls(sph, ora, name):
         assert events > 0
 
 
+@pytest.mark.parametrize("name", ["mixer3d", "uchannel"])
+def test_cells_are_ordered_by_x_quarter(sph, ora, name):
+    # the cell build orders the particles by cell id, x fastest, and inside
+    # a cell by quarter of the cell along x (the list scan's row trim relies
+    # on each quarter being one contiguous range)
+    make = {"mixer3d": lambda: cases.make_mixer(dp=0.04),
+            "uchannel": lambda: cases.make_uchannel(dp=0.05, Lleg=3.0)}[name]
+    c = relabelled(ora, make())
+    g = gpu_sim(sph, c, 1)
+    g.advance()
+    g.build_cells()
+    x = g.state()["x"]
+    P = c.params
+    lo, hi, cs = np.array(P["lo"], float), np.array(P["hi"], float), float(P["cell_size"])
+    dim = int(P["dim"])
+    n = [int(np.ceil((hi[k] - lo[k]) / cs)) if k < dim else 1 for k in range(3)]
+    cc = [np.floor((x[:, k] - lo[k]) / cs).astype(np.int64) if k < dim
+          else np.zeros(len(x), np.int64) for k in range(3)]
+    cell = cc[0] + n[0] * (cc[1] + n[1] * cc[2])
+    rel = x[:, 0] - (lo[0] + (cc[0] + 0.5) * cs)
+    q = np.clip(np.floor((rel + 0.5 * cs) * (4.0 / cs)).astype(np.int64), 0, 3)
+    key = cell * 4 + q
+    assert np.all(np.diff(key) >= 0)
+    assert len(np.unique(cell)) > 10 and len(np.unique(q)) == 4
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rates_after_advance_form_the_pending_correction(sph, ora, prec):
     # a 3D laminar sph_advance leaves its next state with the list only (the
