@@ -478,7 +478,7 @@ sph_status sph_adjoint_step(sph_ctx* ctx, const sph_particles* pre, int64_t n_pr
  * step's cell build, list, correction matrices and update data, so that the
  * reverse does not read the context's state.  *n_step receives the step's
  * particle slots.  Leaves the context at the state after the update.
- * Asynchronous.
+ * Synchronises once (the replayed update's read-back of its counts).
  *
  * sph_adjoint_reverse: the reverse sweep of sph_adjoint_step from a
  * workspace filled by sph_adjoint_forward (and n_step from that call); lam
