@@ -335,9 +335,11 @@ sph_status sph_advance(sph_ctx* ctx, const sph_step_ctrl* ctrl, sph_step_info* i
 sph_status sph_buffer_decisions(sph_ctx* ctx, uint32_t* dec);
 
 /* Pair operators at the current state (p and V from rho, B from the last
- * sph_correction) into the FP64 device arrays of `out` (NULL members are
- * skipped; gradv/dk/deps only with turbulence).  Requires sph_correction
- * since the last position change.  Asynchronous. */
+ * sph_correction, or formed first for a state left by sph_advance whose B
+ * the next step would form) into the FP64 device arrays of `out` (NULL
+ * members are skipped; gradv/dk/deps only with turbulence).  Requires
+ * sph_correction (or sph_advance) since the last position change.
+ * Asynchronous. */
 sph_status sph_eval_rates(sph_ctx* ctx, const sph_rates* out);
 
 /* Neighbour lists with the FP64 predicate |x_i - x_j|^2 < (2h)^2, j != i,
