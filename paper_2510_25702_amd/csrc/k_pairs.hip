@@ -66,9 +66,9 @@ struct CorrArgs {
 // terms a wavefront evaluated on nearly every batch).  2D scans ~100
 // candidates against ~25 entries and keeps one kernel.  The moment walk
 // (REC) reads the list the way the other list passes do: deep batches of
-// the advection records written by the cell build (position first, V only
-// for the candidates within 2h), the next batch's entries loading under the
-// current records.
+// the advection records written by the cell build, the next batch's entries
+// loading under the current records.  In sph_advance's 3D laminar steps the
+// advection pass forms B in its own walk instead (advection_body, MOM).
 template <int DIM>
 constexpr bool split_correction() {
   return DIM == 3;
