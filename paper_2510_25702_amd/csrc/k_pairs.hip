@@ -1098,8 +1098,8 @@ __global__ __launch_bounds__(kListDtThreads) void k_list_dt(int nb, const double
 // Per cell of a fresh build, for the relative-motion list radius: u_c, the
 // mean velocity of the cell's moving (real) particles, and for each of its
 // particles s_i = kListSkinFactor |v_i - u_c| Δt_ad + kListSkinFloor h, the
-// deviation from drifting with u_c allowed over the step (-1 marks a wall,
-// which does not move).  Skipped when Δt_ad is unknown.
+// deviation from drifting with u_c allowed over the step (a wall, which
+// does not move, deviates by |u_c| Δt_ad).  Skipped when Δt_ad is unknown.
 #ifndef SPHX_LIST_SKIN_FACTOR
 #define SPHX_LIST_SKIN_FACTOR 2.0
 #endif
@@ -1156,8 +1156,11 @@ __global__ __launch_bounds__(256) void k_cell_skin(int ncell, const int32_t* __r
     u1[c] = u[1];
     if (DIM == 3) u2[c] = u[2];
   }
+  // a wall does not move: from drifting with u_c it deviates by |u_c| t, and
+  // s_wall + |u_c(i) - u_c| dt_ad >= |u_c(i)| dt_ad bounds its pairs
+  const double s_wall = sqrt(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]) * inv * dt;
   for (int j = j0 + lane; j < j1; j += CL) {
-    double sj = -1.0;   // a wall: reference velocity 0, no deviation
+    double sj = s_wall;
     if (is_real(tag[j])) {
       const double d0 = (double)v0[j] - (double)u[0], d1 = (double)v1[j] - (double)u[1];
       const double d2 = DIM == 3 ? (double)v2[j] - (double)u[2] : 0.0;

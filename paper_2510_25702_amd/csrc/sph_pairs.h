@@ -659,8 +659,8 @@ struct NbrOut {
   int kstage;
   V4<T>* queue;      // LDS pair queue of this wavefront (pair_queue entries per lane)
   // relative-motion radius (tight, with lrad[0] = the step's Δt_ad > 0): j is
-  // listed when |r_ij| < 2h + s_i + s_j + |u_c(i) - u_c(j)| Δt_ad (u_c(j) = 0
-  // for a wall), at most the cell size rl; otherwise when |r_ij| < rl
+  // listed when |r_ij| < 2h + s_i + s_j + |u_c(i) - u_c(j)| Δt_ad (a wall's
+  // s_j = |u_c(j)| Δt_ad), at most the cell size rl; otherwise when |r_ij| < rl
   int tight;
   double* lrad;
   const float* lskin;
@@ -767,16 +767,14 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
   const int cy = cyz % pc.ny;
   const int cz = cyz / pc.ny;
   constexpr int zr = DIM == 3 ? 1 : 0;
-  // relative-motion radius (NbrOut): the parts of i's bound, a wall's term
+  // relative-motion radius (NbrOut): i's part of the bound
   const bool tight = o.tight && o.lrad[0] > 0.0;
-  S rad_i = rl, du_wall = S(0), uc_i[3] = {S(0), S(0), S(0)}, dt_l = S(0);
+  S rad_i = rl, uc_i[3] = {S(0), S(0), S(0)}, dt_l = S(0);
   if (tight) {
     dt_l = (S)o.lrad[0];
     rad_i = (S)o.two_h + (S)o.lskin[i];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) uc_i[k] = (S)o.cell_u[k][c];
-    du_wall = pair_dist(DIM == 3 ? (uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) + uc_i[2] * uc_i[2]
-                                 : uc_i[0] * uc_i[0] + uc_i[1] * uc_i[1]) * dt_l;
   }
   // The cell build orders every cell by quarter along x: the members of the
   // row's cell at +1 in quarters k_hi and above, and of the cell at -1 in
@@ -881,11 +879,10 @@ __device__ __forceinline__ void scan_build(const PairCtx<T>& pc, int i, int lane
           const bool in = j < hi && j != i;
           S rad2 = rl2;
           if (tight) {
-            // a wall (s_j < 0) does not move; a little above for rounding
+            // a little above for rounding, at most the cell size
             const S dux = dx < 0 ? du[0] : (dx == 0 ? du[1] : du[2]);
-            const S rad = rad_i + (qs[u] < S(0) ? du_wall : qs[u] + dux);
-            const S rc = rad * S(1.00002);
-            rad2 = rc < rl ? rc * rc : rl2;
+            const S rc = fmin((rad_i + qs[u] + dux) * S(1.00002), rl);
+            rad2 = rc * rc;
           }
           const bool acc = in && r2 < rad2;
           int off = 0, tot = acc ? 1 : 0;
