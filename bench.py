@@ -221,8 +221,8 @@ def summarize_traffic(args, cf, cw, bf, bw):
                  f"{copy_bytes // 1024} KiB (scale {fs:.4f}), WRITE_SIZE reads {write_copy:.0f} KiB "
                  f"(scale {ws:.4f}).  Mean per launch over the second half of each kernel's "
                  "launches.\n\nCommands (repository root, one MI355X), then "
-                 "`python bench.py --workload " + args.workload + " --summarize-traffic "
-                 f"{cf} {cw} {bf} {bw}`:\n\n```\n" + "\n".join(cmds) + "\n```\n\n"
+                 "`python bench.py --workload " + args.workload + f" --steps {args.steps} --warmup "
+                 f"{args.warmup} --summarize-traffic {cf} {cw} {bf} {bw}`:\n\n```\n" + "\n".join(cmds) + "\n```\n\n"
                  "| kernel | FETCH KiB | WRITE KiB | HBM bytes per launch (scaled) |\n"
                  "|---|---:|---:|---:|\n" + "\n".join(rows) + "\n\n"
                  f"Digest of the neighbour-pass sources (`kernel_source_hash`: "
@@ -849,7 +849,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              f"decomposition is a design note, not part of this build.", file=sys.stderr)
+              f"decomposition is described, not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   if (BUILD && g == 0) {
     nb.stale[0] = 0;
     nb.stale[1] = 0;
-    // the list radius this build takes, for the passes' check of it
+    // whether this pass lists by the relative-motion radius, for the passes' check of it
     nb.lrad[1] = (nb.tight && nb.lrad[0] > 0.0) ? 1.0 : 0.0;
   }
   constexpr int KS = BUILD ? list_stage<DIM, L>() : 0;
@@ -558,7 +558,7 @@ struct PressArgs {
   V4<T>* drec[2];           // continuity records of the new state (written)
   const T* xrb[3];          // positions at the neighbour-list build (NULL: no list)
   uint32_t* stale_w;        // outgrown-list word of the next positions
-  // the build's list radius: lrad[1] = 1 for the relative-motion radius
+  // the radius the list was built with: lrad[1] = 1 for the relative-motion radius
   // (check |x - x_build - u_c t| <= s_i and t <= Δt_ad = lrad[0]), else the
   // cell-size radius (check |x - x_build| <= the skin)
   const double* lrad;
